@@ -1,0 +1,196 @@
+/*
+ * pins.h -- C ABI of the MI355X (gfx950) PINS solver library, libpins.so.
+ *
+ * PINS (Wu, Liang, Yang, arXiv 2502.03749) solves the Kantorovich problem of
+ * eq. (ot):   min <C, X>  s.t.  X e_n = a,  X^T e_m = b,  X >= 0,
+ * with a in R^m_{++}, b in R^n_{++}, e^T a = e^T b = 1, by the two-loop method
+ * of Alg. 2: an entropic proximal-point (EPPA) outer loop, eq. (x_inner), whose
+ * k-th subproblem is entropic OT on the shifted cost C^k = C - eta log X^k,
+ * eq. (eppa-sub); each subproblem is solved by a log-domain Sinkhorn warm-up
+ * (Alg. 1 sweeps) and sparse-Newton refinement on the dual, eqs.
+ * (eppa-sub-dual) and (eppa-hess): Sparsify, truncated preconditioned CG and
+ * Armijo backtracking.
+ *
+ * All arithmetic that decides the result runs in hand-written HIP kernels on
+ * the GPU; the host side only validates, allocates and sequences launches.
+ *
+ * Conventions
+ *  - Every array is row-major, double precision, unless stated otherwise.
+ *  - The library never frees memory it did not allocate.  Inputs stay owned
+ *    by the caller; outputs are written into caller-owned arrays.
+ *  - No exception crosses this boundary; every call returns a pins_status.
+ *  - One pins_ctx per host thread.  A ctx owns its device workspace and
+ *    reuses it across calls; calls on one ctx must not overlap.
+ *  - Errors leave a message retrievable with pins_last_error().
+ */
+#ifndef PINS_H
+#define PINS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PINS_ABI_VERSION 1
+
+typedef struct pins_ctx pins_ctx;
+
+typedef enum {
+    PINS_OK = 0,
+    PINS_NOT_CONVERGED = 1, /* outputs valid; the last subproblem hit the Newton cap T2 */
+    PINS_EINVAL = -1,       /* invalid argument; nothing written */
+    PINS_ENOMEM = -2,       /* device allocation failed / workspace limit exceeded */
+    PINS_EDEVICE = -3,      /* HIP runtime error */
+    PINS_ENUMERIC = -4,     /* non-finite value met (NaN/Inf in C or in an iterate) */
+    PINS_EUNSUPPORTED = -5  /* combination of options not implemented */
+} pins_status;
+
+/* How the cost C of eq. (ot) is given. */
+typedef enum {
+    PINS_COST_DENSE = 0,  /* C: m*n array */
+    PINS_COST_POINTS = 1, /* C_ij = ||x_i - y_j||^2 * scale; x: m*d, y: n*d */
+    PINS_COST_GRID = 2    /* s x s pixel grid, m = n = s*s, pixel p = row*s + col,
+                             C_pq = ((row_p-row_q)^2 + (col_p-col_q)^2) * scale;
+                             computed on the fly, never materialised */
+} pins_cost_kind;
+
+typedef enum {
+    PINS_FP64 = 0, /* every step in double precision */
+    PINS_MIXED = 1 /* Sinkhorn warm-up sweeps evaluate exp and accumulate the
+                      log-sum-exp in float (exponent formed in double);
+                      Newton, CG, line search, potentials and outputs stay double */
+} pins_precision;
+
+typedef enum {
+    PINS_SHIFT_IMPLICIT = 0,    /* C^k kept as (k+1) C minus a row and a column vector
+                                   (exact algebraic form of C - eta log X^k); O(m+n) per shift */
+    PINS_SHIFT_MATERIALIZED = 1 /* C^k stored as an m*n array and updated elementwise,
+                                   C^{k+1} = C^k + C - f (+) g + eta */
+} pins_shift_mode;
+
+/* Solver parameters.  pins_params_default() fills the paper's defaults
+ * (numerical appendix, "Implementation Details"): K = 250, T1 = 100,
+ * T2 = 50, Armijo beta = 0.5, c1 = 1e-4, CG relative residual 1e-6,
+ * marginal tolerance 1e-9. */
+typedef struct {
+    double eta;           /* proximal/entropic parameter, > 0 */
+    int32_t max_outer;    /* K, number of EPPA outer iterations (fixed; >= 1) */
+    int32_t max_sinkhorn; /* T1, warm-up cap per subproblem */
+    int32_t max_newton;   /* T2, Newton cap per subproblem */
+    int32_t cg_max_iter;  /* CG iteration cap */
+    double warm_tol;      /* warm-up ends when the row-marginal L1 error <= warm_tol */
+    double inner_tol;     /* Newton ends at ||Xe-a||_1 + ||X^Te-b||_1 <= inner_tol (subproblems < K-1) */
+    double final_tol;     /* same for the last subproblem */
+    double cg_rtol;       /* CG stops at ||res||_2 <= cg_rtol ||rhs||_2 */
+    double ls_beta;       /* Armijo backtracking factor */
+    double ls_c1;         /* Armijo constant */
+    int32_t ls_max;       /* number of trial steps 1, beta, ..., beta^(ls_max-1) */
+    int32_t rho_levels;   /* Sparsify levels tried: thresholds rho * 10^l, l < rho_levels */
+    double rho;           /* Sparsify keeps Xt_ij >= rho*10^l*min(a_i,b_j) for the smallest */
+    double budget;        /* level l whose count is <= budget*(m+n-1) */
+    int32_t precision;    /* pins_precision */
+    int32_t shift_mode;   /* pins_shift_mode */
+    int32_t profile;      /* nonzero: time every kernel launch with HIP events (pins_result.kern_*) */
+    int32_t reserved;
+} pins_params;
+
+/* One problem instance.  For pins_solve the pointers are host pointers, for
+ * the *_device entry points they are device pointers. */
+typedef struct {
+    int32_t kind;      /* pins_cost_kind */
+    int32_t m, n;      /* sizes; GRID: m = n = grid_s^2 */
+    int32_t d;         /* POINTS: dimension */
+    int32_t grid_s;    /* GRID: side */
+    int32_t reserved;
+    const double* C;   /* DENSE: m*n */
+    const double* x;   /* POINTS: m*d */
+    const double* y;   /* POINTS: n*d */
+    double cost_scale; /* multiplies C; <= 0 means 1/max C (GRID: 1/(2(s-1)^2)) */
+    const double* a;   /* m, positive, sums to 1 (|sum-1| <= 1e-10) */
+    const double* b;   /* n, positive, sums to 1 */
+} pins_problem;
+
+#define PINS_NKERN 16
+
+/* Results.  alpha/beta/X point to caller-owned arrays (host for pins_solve,
+ * device for the *_device entry points); X may be NULL (not written).
+ * Outputs are the standard-form potentials at eps = eta/K:
+ *   X_ij = exp((alpha_i + beta_j - C_ij)/eps),  gauge <a,alpha> = <b,beta>,
+ * which is the plan X^K of Alg. 2 after K outer iterations. */
+typedef struct {
+    double* alpha;        /* m */
+    double* beta;         /* n */
+    double* X;            /* m*n or NULL */
+    double cost;          /* <C, X^K> (C as scaled) */
+    double eps;           /* eta / K */
+    double resid;         /* ||X^K e - a||_1 + ||X^K^T e - b||_1 */
+    double dual;          /* <a,alpha> + <b,beta>, an LP dual value when the marginals hold */
+    double gap;           /* cost - dual */
+    double entropy;       /* -sum X log X */
+    double cost_scale;    /* scale actually applied to C */
+    double time_ms;       /* wall time of the call */
+    int32_t status;       /* pins_status of this instance */
+    int32_t flags;        /* bit0: last subproblem hit T2; bit1: an earlier one did; bit2: non-finite */
+    int32_t outer_iters, sinkhorn_iters, newton_iters, cg_iters, fallbacks, nnz_last;
+    double kern_ms[PINS_NKERN];   /* summed kernel time per kernel class (profile != 0) */
+    int32_t kern_calls[PINS_NKERN];
+} pins_result;
+
+/* Kernel classes reported in kern_ms / kern_calls. */
+#define PINS_K_ROW_LSE 0   /* Sinkhorn f-update (row log-sum-exp sweep) */
+#define PINS_K_COL_LSE 1   /* Sinkhorn g-update, column partials */
+#define PINS_K_COL_MERGE 2 /* Sinkhorn g-update, merge + warm-up control */
+#define PINS_K_GRAD 3      /* Newton pass: Xt row/col sums, Sparsify histogram */
+#define PINS_K_GRAD_MERGE 4 /* gradient merge, convergence, Sparsify level, CSR row pointers */
+#define PINS_K_FILL 5      /* CSR fill */
+#define PINS_K_CSC 6       /* CSC transpose */
+#define PINS_K_PCG 7       /* preconditioned CG */
+#define PINS_K_LS 8        /* Armijo trial pass */
+#define PINS_K_UPDATE 9    /* dual update */
+#define PINS_K_SHIFT 10    /* outer shift */
+#define PINS_K_FINAL 11    /* potentials and outputs */
+#define PINS_K_SETUP 12    /* cost preparation, initialisation */
+
+int pins_abi_version(void);
+
+/* Fill *p with the defaults above (eta = 1e-2). */
+void pins_params_default(pins_params* p);
+
+/* Create a context on HIP device `device`.  *out receives the handle.
+ * Returns PINS_EDEVICE if the device cannot be used. */
+int pins_create(int device, pins_ctx** out);
+void pins_destroy(pins_ctx* ctx);
+
+/* Message of the last failing call on ctx (never NULL). */
+const char* pins_last_error(const pins_ctx* ctx);
+
+/* Device bytes a solve of `count` problems needs (workspace; inputs and
+ * outputs excluded).  Used for admission by HBM footprint. */
+int pins_workspace_bytes(const pins_problem* probs, int count, const pins_params* p, size_t* bytes);
+
+/* Solve one problem given by HOST pointers; synchronous.  Copies the inputs
+ * to the device, runs Alg. 2, writes alpha, beta (and X if non-NULL) to host
+ * arrays and fills the scalars of *res. */
+int pins_solve(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res);
+
+/* Solve one problem given by DEVICE pointers on HIP stream `stream` (NULL =
+ * the null stream).  Outputs res->alpha/beta/X are device pointers.  The
+ * call returns when the solve has finished (the host sequences the
+ * data-dependent loops). */
+int pins_solve_device(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res,
+                      void* stream);
+
+/* Solve `count` independent problems in one batch (DEVICE pointers): every
+ * kernel launch covers all instances still active, each instance keeps its
+ * own iteration control, and each result equals the one its problem gets
+ * alone.  All problems must share the cost kind (dense/points or grid).
+ * Returns the worst status; res[i].status holds each instance's. */
+int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
+                            pins_result* res, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

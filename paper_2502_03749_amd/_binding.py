@@ -1,0 +1,246 @@
+"""ctypes binding of libpins.so (include/pins.h) -- argument marshalling only.
+
+Every step of the solve runs in the HIP library; nothing here computes any
+part of the method.  If the library is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpins.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pins.h")
+
+PINS_OK = 0
+PINS_NOT_CONVERGED = 1
+PINS_EINVAL = -1
+PINS_ENOMEM = -2
+PINS_EDEVICE = -3
+PINS_ENUMERIC = -4
+PINS_EUNSUPPORTED = -5
+
+COST_DENSE, COST_POINTS, COST_GRID = 0, 1, 2
+FP64, MIXED = 0, 1
+SHIFT_IMPLICIT, SHIFT_MATERIALIZED = 0, 1
+NKERN = 16
+KERNEL_NAMES = ["row_lse", "col_lse", "col_merge", "grad", "grad_merge", "fill", "csc", "pcg", "ls", "update",
+                "shift", "final", "setup"]
+
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("max_outer", ctypes.c_int32), ("max_sinkhorn", ctypes.c_int32),
+                ("max_newton", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32), ("warm_tol", ctypes.c_double),
+                ("inner_tol", ctypes.c_double), ("final_tol", ctypes.c_double), ("cg_rtol", ctypes.c_double),
+                ("ls_beta", ctypes.c_double), ("ls_c1", ctypes.c_double), ("ls_max", ctypes.c_int32),
+                ("rho_levels", ctypes.c_int32), ("rho", ctypes.c_double), ("budget", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("shift_mode", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("grid_s", ctypes.c_int32), ("reserved", ctypes.c_int32), ("C", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("cost_scale", ctypes.c_double),
+                ("a", ctypes.c_void_p), ("b", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("X", ctypes.c_void_p),
+                ("cost", ctypes.c_double), ("eps", ctypes.c_double), ("resid", ctypes.c_double),
+                ("dual", ctypes.c_double), ("gap", ctypes.c_double), ("entropy", ctypes.c_double),
+                ("cost_scale", ctypes.c_double), ("time_ms", ctypes.c_double), ("status", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("sinkhorn_iters", ctypes.c_int32),
+                ("newton_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("nnz_last", ctypes.c_int32), ("kern_ms", ctypes.c_double * NKERN),
+                ("kern_calls", ctypes.c_int32 * NKERN)]
+
+    def scalars(self) -> dict:
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("alpha", "beta", "X", "kern_ms",
+                                                                            "kern_calls")}
+        out["kern_ms"] = {KERNEL_NAMES[i]: self.kern_ms[i] for i in range(len(KERNEL_NAMES))}
+        out["kern_calls"] = {KERNEL_NAMES[i]: self.kern_calls[i] for i in range(len(KERNEL_NAMES))}
+        return out
+
+
+class PinsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("pins error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libpins.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpins.so is not built (run __graft_entry__.build() or "
+                              "python paper_2502_03749_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.pins_abi_version.restype = ctypes.c_int
+        L.pins_params_default.argtypes = [ctypes.POINTER(Params)]
+        L.pins_params_default.restype = None
+        L.pins_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        L.pins_destroy.argtypes = [vp]
+        L.pins_destroy.restype = None
+        L.pins_last_error.argtypes = [vp]
+        L.pins_last_error.restype = ctypes.c_char_p
+        L.pins_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.pins_solve.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(Result)]
+        L.pins_solve_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(Result),
+                                        vp]
+        L.pins_solve_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
+                                              ctypes.POINTER(Result), vp]
+        _lib = L
+    return _lib
+
+
+def declared_functions() -> list:
+    """Names of the functions include/pins.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pins_[a-z_]+)\s*\(", txt)))
+
+
+def params(**kw) -> Params:
+    p = Params()
+    lib().pins_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Context:
+    """A library context on one HIP device (owns the device workspace)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = lib().pins_create(device, ctypes.byref(h))
+        if rc != PINS_OK:
+            raise PinsError(rc, "pins_create(%d) failed" % device)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pins_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().pins_last_error(self.h).decode()
+
+    def _check(self, rc):
+        if rc < 0:
+            raise PinsError(rc, self.last_error())
+        return rc
+
+    # -------------------------------------------------------------- host API
+    def solve(self, kind, a, b, prm: Params, C=None, x=None, y=None, grid_s=0, cost_scale=0.0, want_plan=False):
+        """pins_solve with numpy host arrays.  Returns dict(alpha, beta, X, **scalars)."""
+        a = np.ascontiguousarray(a, np.float64)
+        b = np.ascontiguousarray(b, np.float64)
+        keep = [a, b]
+        P = Problem(kind=kind, m=a.size, n=b.size, d=0, grid_s=grid_s, cost_scale=cost_scale,
+                    a=a.ctypes.data, b=b.ctypes.data)
+        if C is not None:
+            C = np.ascontiguousarray(C, np.float64)
+            keep.append(C)
+            P.C = C.ctypes.data
+        if x is not None:
+            x = np.ascontiguousarray(x, np.float64)
+            y = np.ascontiguousarray(y, np.float64)
+            keep += [x, y]
+            P.x, P.y, P.d = x.ctypes.data, y.ctypes.data, x.shape[1]
+        alpha = np.empty(a.size)
+        beta = np.empty(b.size)
+        X = np.empty((a.size, b.size)) if want_plan else None
+        R = Result(alpha=alpha.ctypes.data, beta=beta.ctypes.data, X=X.ctypes.data if X is not None else None)
+        rc = self._check(lib().pins_solve(self.h, ctypes.byref(P), ctypes.byref(prm), ctypes.byref(R)))
+        out = R.scalars()
+        out.update(alpha=alpha, beta=beta, X=X, rc=rc)
+        return out
+
+    # ------------------------------------------------------------ device API
+    def solve_batch_device(self, problems, prm: Params, outs, stream=None):
+        """pins_solve_batch_device.
+
+        problems: list of dicts with kind, a, b and C | (x, y) | grid_s (torch CUDA float64 tensors or
+        raw device pointers as ints); outs: list of dicts with alpha, beta and optional X (device).
+        Returns (rc, [scalars per instance]).
+        """
+        cnt = len(problems)
+        P = (Problem * cnt)()
+        R = (Result * cnt)()
+        for q, pr in enumerate(problems):
+            P[q].kind = pr["kind"]
+            P[q].m = pr["m"]
+            P[q].n = pr["n"]
+            P[q].d = pr.get("d", 0)
+            P[q].grid_s = pr.get("grid_s", 0)
+            P[q].cost_scale = pr.get("cost_scale", 0.0)
+            for f in ("C", "x", "y", "a", "b"):
+                if pr.get(f) is not None:
+                    setattr(P[q], f, _ptr(pr[f]))
+            R[q].alpha = _ptr(outs[q]["alpha"])
+            R[q].beta = _ptr(outs[q]["beta"])
+            if outs[q].get("X") is not None:
+                R[q].X = _ptr(outs[q]["X"])
+        rc = self._check(lib().pins_solve_batch_device(self.h, P, cnt, ctypes.byref(prm), R,
+                                                       ctypes.c_void_p(stream or 0)))
+        return rc, [R[q].scalars() for q in range(cnt)]
+
+    def solve_device(self, problem, prm: Params, out, stream=None):
+        cnt_rc, res = self.solve_batch_device([problem], prm, [out], stream)
+        return cnt_rc, res[0]
+
+
+def _ptr(t):
+    if isinstance(t, int):
+        return t
+    if hasattr(t, "data_ptr"):
+        if not t.is_contiguous():
+            raise ValueError("device arrays must be contiguous")
+        import torch
+
+        if t.dtype != torch.float64:
+            raise TypeError("device arrays must be float64")
+        return t.data_ptr()
+    raise TypeError("unsupported array type %r" % type(t))
+
+
+def workspace_bytes(problems, prm: Params) -> int:
+    cnt = len(problems)
+    P = (Problem * cnt)()
+    for q, pr in enumerate(problems):
+        P[q].kind = pr["kind"]
+        P[q].m = pr["m"]
+        P[q].n = pr["n"]
+        P[q].d = pr.get("d", 0)
+        P[q].grid_s = pr.get("grid_s", 0)
+        P[q].a = 1
+        P[q].b = 1
+        P[q].C = 1
+        P[q].x = 1
+        P[q].y = 1
+    out = ctypes.c_size_t(0)
+    rc = lib().pins_workspace_bytes(P, cnt, ctypes.byref(prm), ctypes.byref(out))
+    if rc != PINS_OK:
+        raise PinsError(rc, "pins_workspace_bytes failed")
+    return out.value

@@ -1,0 +1,670 @@
+// pins_host.cpp -- C ABI of libpins.so: validation, device workspace, and the
+// host sequencing of Alg. 2 (EPPA outer loop; Sinkhorn warm-up; sparse Newton
+// with Sparsify, CG, Armijo line search).  Every arithmetic step of the
+// method runs in the HIP kernels of pins_kernels.hip; the host only decides,
+// from small control blocks read back from the device, when a batch has left
+// a loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pins.h"
+#include "pins_internal.h"
+#include "pins_launch.h"
+
+using namespace pins;
+
+struct pins_ctx {
+    int device = 0;
+    std::string err;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    std::vector<hipEvent_t> events;  // profiling pool, used in pairs
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+    bool profile = false;
+};
+
+namespace {
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(x)                                     \
+    do {                                              \
+        hipError_t e_ = (x);                          \
+        if (e_ != hipSuccess) throw HipError{e_, #x}; \
+    } while (0)
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Fail{code, msg}; }
+
+constexpr size_t NONE = (size_t)-1;
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += al256(bytes);
+        return o;
+    }
+};
+
+// Offsets of one instance's device arrays inside the workspace.
+struct InstPlan {
+    int m, n, d, R, nrb, ncb, cap;
+    size_t loga, logb, F, G, Ah, Bh, rc, dir, cgw, part, part2, blk, blk2, hist, rowptr, col, val, colptr, rowT,
+        valT, cfill, Ck, Cpts;
+    size_t C, x, y, a, b, alpha, beta, X;  // host-API staging
+};
+
+long nnz_capacity(int m, int n, double budget) {
+    const double lim = std::ceil(budget * (double)(m + n - 1));
+    const double mn = (double)m * (double)n;
+    return std::max(1L, (long)std::min(lim, mn));
+}
+
+InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, bool host_api, bool want_x) {
+    InstPlan q;
+    const int m = P.m, n = P.n, N = m + n;
+    const size_t D = sizeof(double), I4 = sizeof(int);
+    q.m = m;
+    q.n = n;
+    q.d = P.d;
+    q.R = std::min(TILE_RMAX, m);
+    q.nrb = (m + q.R - 1) / q.R;
+    q.ncb = (n + TILE_C - 1) / TILE_C;
+    q.cap = (int)nnz_capacity(m, n, p.budget);
+    const long tiles = (long)q.nrb * q.ncb;
+    const long nblk = std::max({tiles, (long)(m + 3) / 4, (long)(N + 255) / 256});
+    q.loga = cv.take(m * D);
+    q.logb = cv.take(n * D);
+    q.F = cv.take(m * D);
+    q.G = cv.take(n * D);
+    q.Ah = cv.take(m * D);
+    q.Bh = cv.take(n * D);
+    q.rc = cv.take(N * D);
+    q.dir = cv.take(N * D);
+    q.cgw = cv.take(4 * (size_t)N * D);
+    q.part = cv.take((size_t)q.nrb * n * 2 * D);
+    q.part2 = cv.take((size_t)q.ncb * m * D);
+    q.blk = cv.take((size_t)nblk * LS_T * D);
+    q.blk2 = cv.take((size_t)nblk * D);
+    q.hist = cv.take((size_t)m * NLEV * I4);
+    q.rowptr = cv.take((m + 1) * I4);
+    q.col = cv.take((size_t)q.cap * I4);
+    q.val = cv.take((size_t)q.cap * D);
+    q.colptr = cv.take((n + 1) * I4);
+    q.rowT = cv.take((size_t)q.cap * I4);
+    q.valT = cv.take((size_t)q.cap * D);
+    q.cfill = cv.take(n * I4);
+    q.Ck = (p.shift_mode == PINS_SHIFT_MATERIALIZED) ? cv.take((size_t)m * n * D) : NONE;
+    q.Cpts = (P.kind == PINS_COST_POINTS) ? cv.take((size_t)m * n * D) : NONE;
+    q.C = q.x = q.y = q.a = q.b = q.alpha = q.beta = q.X = NONE;
+    if (host_api) {
+        if (P.kind == PINS_COST_DENSE) q.C = cv.take((size_t)m * n * D);
+        if (P.kind == PINS_COST_POINTS) {
+            q.x = cv.take((size_t)m * P.d * D);
+            q.y = cv.take((size_t)n * P.d * D);
+        }
+        q.a = cv.take(m * D);
+        q.b = cv.take(n * D);
+        q.alpha = cv.take(m * D);
+        q.beta = cv.take(n * D);
+        if (want_x) q.X = cv.take((size_t)m * n * D);
+    }
+    return q;
+}
+
+struct Batch {
+    std::vector<InstPlan> plans;
+    size_t insts = 0, ctrl = 0, scratch = 0, total = 0;
+    int max_m = 0, max_n = 0, max_mn = 0, max_tiles = 0;
+};
+
+constexpr int SCRATCH_BLK = 512;
+
+Batch plan_batch(const pins_problem* probs, int count, const pins_params& p, bool host_api, const pins_result* res) {
+    Batch B;
+    Carver cv;
+    B.insts = cv.take(sizeof(DevInst) * count);
+    B.ctrl = cv.take(sizeof(Ctrl) * count);
+    B.scratch = cv.take(sizeof(double) * (size_t)SCRATCH_BLK * count);
+    for (int q = 0; q < count; ++q) {
+        const bool want_x = host_api && res && res[q].X;
+        B.plans.push_back(plan_instance(cv, probs[q], p, host_api, want_x));
+        const InstPlan& P = B.plans.back();
+        B.max_m = std::max(B.max_m, P.m);
+        B.max_n = std::max(B.max_n, P.n);
+        B.max_mn = std::max(B.max_mn, P.m + P.n);
+        B.max_tiles = std::max(B.max_tiles, P.nrb * P.ncb);
+    }
+    B.total = cv.off;
+    return B;
+}
+
+void check_params(const pins_params& p) {
+    if (!(p.eta > 0.0) || !std::isfinite(p.eta)) fail(PINS_EINVAL, "eta must be positive and finite");
+    if (p.max_outer < 1) fail(PINS_EINVAL, "max_outer (K) must be >= 1");
+    if (p.max_sinkhorn < 0 || p.max_newton < 0 || p.cg_max_iter < 0 || p.ls_max < 1)
+        fail(PINS_EINVAL, "iteration caps must be non-negative and ls_max >= 1");
+    if (!(p.warm_tol >= 0.0) || !(p.inner_tol >= 0.0) || !(p.final_tol >= 0.0) || !(p.cg_rtol >= 0.0))
+        fail(PINS_EINVAL, "tolerances must be non-negative");
+    if (!(p.ls_beta > 0.0 && p.ls_beta < 1.0) || !(p.ls_c1 > 0.0 && p.ls_c1 < 1.0))
+        fail(PINS_EINVAL, "Armijo constants must lie in (0, 1)");
+    if (p.rho_levels < 1 || p.rho_levels > NLEV) fail(PINS_EINVAL, "rho_levels must be in [1, 16]");
+    if (!(p.rho > 0.0) || !std::isfinite(p.rho) || !(p.budget > 0.0) || !std::isfinite(p.budget))
+        fail(PINS_EINVAL, "rho and budget must be positive and finite");
+    if (p.precision != PINS_FP64 && p.precision != PINS_MIXED) fail(PINS_EINVAL, "unknown precision");
+    if (p.shift_mode != PINS_SHIFT_IMPLICIT && p.shift_mode != PINS_SHIFT_MATERIALIZED)
+        fail(PINS_EINVAL, "unknown shift_mode");
+}
+
+void check_problem_shape(const pins_problem& P) {
+    if (P.kind != PINS_COST_DENSE && P.kind != PINS_COST_POINTS && P.kind != PINS_COST_GRID)
+        fail(PINS_EINVAL, "unknown cost kind");
+    if (P.m < 1 || P.n < 1) fail(PINS_EINVAL, "m and n must be >= 1");
+    if (P.kind == PINS_COST_GRID && (P.grid_s < 1 || P.grid_s > 46340 || P.m != P.grid_s * P.grid_s || P.n != P.m))
+        fail(PINS_EINVAL, "GRID needs m = n = grid_s^2");
+    if ((double)P.m * (double)P.n > 2147483647.0) fail(PINS_EUNSUPPORTED, "m*n must be below 2^31");
+    if (P.kind == PINS_COST_DENSE && !P.C) fail(PINS_EINVAL, "DENSE needs C");
+    if (P.kind == PINS_COST_POINTS && (!P.x || !P.y || P.d < 1)) fail(PINS_EINVAL, "POINTS needs x, y and d >= 1");
+    if (!P.a || !P.b) fail(PINS_EINVAL, "a and b are required");
+    if (!std::isfinite(P.cost_scale)) fail(PINS_EINVAL, "cost_scale must be finite");
+}
+
+void check_marginal(const double* v, int len, const char* name) {
+    double s = 0.0;
+    for (int i = 0; i < len; ++i) {
+        if (!(v[i] > 0.0) || !std::isfinite(v[i])) fail(PINS_EINVAL, std::string(name) + " must be positive and finite");
+        s += v[i];
+    }
+    if (std::fabs(s - 1.0) > 1e-10) fail(PINS_EINVAL, std::string(name) + " must sum to 1 (|sum-1| <= 1e-10)");
+}
+
+// One event pair per launch when profiling; summed per kernel class at the end.
+struct Prof {
+    pins_ctx* c;
+    hipStream_t st;
+    int kind = -1;
+    Prof(pins_ctx* c_, hipStream_t s, int k) : c(c_), st(s) {
+        if (!c->profile) return;
+        kind = k;
+        if (c->ev_used + 2 > c->events.size()) {
+            for (int q = 0; q < 512; ++q) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                c->events.push_back(e);
+            }
+            c->ev_kind.resize(c->events.size() / 2);
+        }
+        HIPCHK(hipEventRecord(c->events[c->ev_used], st));
+    }
+    void end() {
+        if (kind < 0) return;
+        HIPCHK(hipEventRecord(c->events[c->ev_used + 1], st));
+        c->ev_kind[c->ev_used / 2] = kind;
+        c->ev_used += 2;
+        kind = -1;
+    }
+};
+
+template <class Fn>
+void run(pins_ctx* c, hipStream_t st, int kind, Fn&& fn) {
+    Prof pr(c, st, kind);
+    fn();
+    HIPCHK(hipGetLastError());
+    pr.end();
+}
+
+void* pinned(pins_ctx* c, size_t bytes) {
+    if (bytes > c->pinned_bytes) {
+        if (c->pinned) HIPCHK(hipHostFree(c->pinned));
+        c->pinned = nullptr;
+        c->pinned_bytes = 0;
+        HIPCHK(hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault));
+        c->pinned_bytes = bytes;
+    }
+    return c->pinned;
+}
+
+char* workspace(pins_ctx* c, size_t bytes) {
+    if (bytes > c->ws_bytes) {
+        if (c->ws) HIPCHK(hipFree(c->ws));
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+        if (hipMalloc(&c->ws, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            c->ws = nullptr;
+            fail(PINS_ENOMEM, "device workspace allocation failed (" + std::to_string(bytes) + " bytes)");
+        }
+        c->ws_bytes = bytes;
+    }
+    return (char*)c->ws;
+}
+
+// Read the control blocks back (synchronises the stream).
+const Ctrl* readback(pins_ctx* c, hipStream_t st, const Ctrl* d_ctrl, int count) {
+    Ctrl* h = (Ctrl*)pinned(c, sizeof(Ctrl) * count + sizeof(DevInst) * count);
+    HIPCHK(hipMemcpyAsync(h, d_ctrl, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return h;
+}
+
+int solve_impl(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params& p, pins_result* res,
+               hipStream_t st, bool host_api) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    if (count < 1) fail(PINS_EINVAL, "count must be >= 1");
+    if (!probs || !res) fail(PINS_EINVAL, "problems and results are required");
+    check_params(p);
+    const bool grid0 = probs[0].kind == PINS_COST_GRID;
+    for (int q = 0; q < count; ++q) {
+        check_problem_shape(probs[q]);
+        if ((probs[q].kind == PINS_COST_GRID) != grid0)
+            fail(PINS_EUNSUPPORTED, "a batch must not mix GRID with DENSE/POINTS costs");
+        if (!host_api && (!res[q].alpha || !res[q].beta)) fail(PINS_EINVAL, "res.alpha and res.beta are required");
+        if (host_api && (!res[q].alpha || !res[q].beta)) fail(PINS_EINVAL, "res.alpha and res.beta are required");
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    ctx->profile = p.profile != 0;
+    ctx->ev_used = 0;
+
+    // marginals are validated on the host (device arrays are copied back first)
+    {
+        std::vector<double> hb;
+        for (int q = 0; q < count; ++q) {
+            const pins_problem& P = probs[q];
+            if (host_api) {
+                check_marginal(P.a, P.m, "a");
+                check_marginal(P.b, P.n, "b");
+            } else {
+                hb.resize(std::max(P.m, P.n));
+                HIPCHK(hipMemcpy(hb.data(), P.a, sizeof(double) * P.m, hipMemcpyDeviceToHost));
+                check_marginal(hb.data(), P.m, "a");
+                HIPCHK(hipMemcpy(hb.data(), P.b, sizeof(double) * P.n, hipMemcpyDeviceToHost));
+                check_marginal(hb.data(), P.n, "b");
+            }
+        }
+    }
+
+    const Batch B = plan_batch(probs, count, p, host_api, res);
+    char* ws = workspace(ctx, B.total);
+    DevInst* d_insts = (DevInst*)(ws + B.insts);
+    Ctrl* d_ctrl = (Ctrl*)(ws + B.ctrl);
+    double* d_scratch = (double*)(ws + B.scratch);
+    auto Dp = [&](size_t off) { return off == NONE ? (double*)nullptr : (double*)(ws + off); };
+    auto Ip = [&](size_t off) { return (int*)(ws + off); };
+
+    const bool mat = p.shift_mode == PINS_SHIFT_MATERIALIZED;
+    const int src = (grid0 && !mat) ? SRC_GRID : SRC_DENSE;  // exponent source
+    const int base_src = grid0 ? SRC_GRID : SRC_DENSE;       // unshifted cost
+
+    Prof setup(ctx, st, PINS_K_SETUP);
+    std::vector<DevInst> hI(count);
+    bool need_max = false;
+    for (int q = 0; q < count; ++q) {
+        const pins_problem& P = probs[q];
+        const InstPlan& L = B.plans[q];
+        DevInst& I = hI[q];
+        std::memset(&I, 0, sizeof(I));
+        const double *dC = P.C, *dx = P.x, *dy = P.y, *da = P.a, *db = P.b;
+        if (host_api) {
+            const size_t D = sizeof(double);
+            if (P.kind == PINS_COST_DENSE) {
+                HIPCHK(hipMemcpyAsync(Dp(L.C), P.C, D * L.m * L.n, hipMemcpyHostToDevice, st));
+                dC = Dp(L.C);
+            }
+            if (P.kind == PINS_COST_POINTS) {
+                HIPCHK(hipMemcpyAsync(Dp(L.x), P.x, D * L.m * P.d, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(Dp(L.y), P.y, D * L.n * P.d, hipMemcpyHostToDevice, st));
+                dx = Dp(L.x);
+                dy = Dp(L.y);
+            }
+            HIPCHK(hipMemcpyAsync(Dp(L.a), P.a, D * L.m, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(Dp(L.b), P.b, D * L.n, hipMemcpyHostToDevice, st));
+            da = Dp(L.a);
+            db = Dp(L.b);
+        }
+        I.m = L.m;
+        I.n = L.n;
+        I.grid_s = P.grid_s;
+        I.R = L.R;
+        I.nrb = L.nrb;
+        I.ncb = L.ncb;
+        I.nnz_cap = L.cap;
+        I.ldc = L.n;
+        I.a = da;
+        I.b = db;
+        if (P.kind == PINS_COST_DENSE) {
+            I.cbase = dC;
+        } else if (P.kind == PINS_COST_POINTS) {
+            I.cbase = Dp(L.Cpts);
+            launch_points_cost(st, dx, dy, L.m, L.n, P.d, Dp(L.Cpts));
+            HIPCHK(hipGetLastError());
+        }
+        if (P.cost_scale > 0.0) {
+            I.bscale = P.cost_scale;
+        } else if (P.kind == PINS_COST_GRID) {
+            I.bscale = P.grid_s > 1 ? 1.0 / (2.0 * (double)(P.grid_s - 1) * (double)(P.grid_s - 1)) : 1.0;
+        } else {
+            I.bscale = -1.0;  // replaced by 1/max C on the device
+        }
+        if (P.kind != PINS_COST_GRID) need_max = true;
+        I.Ck = Dp(L.Ck);
+        I.csrc = mat ? I.Ck : I.cbase;
+        I.cscale = mat ? 1.0 : I.bscale;
+        I.loga = Dp(L.loga);
+        I.logb = Dp(L.logb);
+        I.F = Dp(L.F);
+        I.G = Dp(L.G);
+        I.Ah = Dp(L.Ah);
+        I.Bh = Dp(L.Bh);
+        I.rc = Dp(L.rc);
+        I.d = Dp(L.dir);
+        I.cgw = Dp(L.cgw);
+        I.part = Dp(L.part);
+        I.part2 = Dp(L.part2);
+        I.blk = Dp(L.blk);
+        I.blk2 = Dp(L.blk2);
+        I.hist = Ip(L.hist);
+        I.rowptr = Ip(L.rowptr);
+        I.col = Ip(L.col);
+        I.val = Dp(L.val);
+        I.colptr = Ip(L.colptr);
+        I.rowT = Ip(L.rowT);
+        I.valT = Dp(L.valT);
+        I.cfill = Ip(L.cfill);
+        if (host_api) {
+            I.alpha = Dp(L.alpha);
+            I.beta = Dp(L.beta);
+            I.X = Dp(L.X);
+        } else {
+            I.alpha = res[q].alpha;
+            I.beta = res[q].beta;
+            I.X = res[q].X;
+        }
+    }
+    {
+        DevInst* h = (DevInst*)((char*)pinned(ctx, sizeof(Ctrl) * count + sizeof(DevInst) * count) +
+                                sizeof(Ctrl) * count);
+        std::memcpy(h, hI.data(), sizeof(DevInst) * count);
+        HIPCHK(hipMemcpyAsync(d_insts, h, sizeof(DevInst) * count, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(d_ctrl, 0, sizeof(Ctrl) * count, st));
+        HIPCHK(hipStreamSynchronize(st));  // the pinned staging area is reused by readback()
+    }
+
+    LaunchCtx L;
+    L.stream = st;
+    L.insts = d_insts;
+    L.insts_mut = d_insts;
+    L.ctrl = d_ctrl;
+    L.count = count;
+    L.max_m = B.max_m;
+    L.max_n = B.max_n;
+    L.max_mn = B.max_mn;
+    L.max_tiles = B.max_tiles;
+    KP& kp = L.kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.eta = p.eta;
+    kp.inv_eta = 1.0 / p.eta;
+    kp.warm_tol = p.warm_tol;
+    kp.tol = p.inner_tol;
+    kp.cg_rtol = p.cg_rtol;
+    kp.ls_beta = p.ls_beta;
+    kp.ls_c1 = p.ls_c1;
+    kp.log_rho = std::log(p.rho);
+    kp.budget = p.budget;
+    kp.T1 = p.max_sinkhorn;
+    kp.T2 = p.max_newton;
+    kp.cg_max = p.cg_max_iter;
+    kp.ls_max = p.ls_max;
+    kp.nlev = p.rho_levels;
+    kp.shift_mode = p.shift_mode;
+    kp.last = 0;
+
+    // a0: cost scale (1/max over the dense cost unless given) and finiteness
+    if (need_max) {
+        launch_cost_max(L, d_scratch, SCRATCH_BLK, mat ? 0 : 1);
+        HIPCHK(hipGetLastError());
+    }
+    launch_init(L, base_src);
+    HIPCHK(hipGetLastError());
+    setup.end();
+    {
+        const Ctrl* h = readback(ctx, st, d_ctrl, count);
+        for (int q = 0; q < count; ++q)
+            if (h[q].nonfinite) fail(PINS_EINVAL, "C has non-finite entries (instance " + std::to_string(q) + ")");
+    }
+
+    const bool f32 = p.precision == PINS_MIXED;
+    const int K = p.max_outer;
+    const int M_WARM = 1 << PH_WARM, M_FB = 1 << PH_FALLBACK;
+    for (int k = 0; k < K; ++k) {
+        kp.tol = (k == K - 1) ? p.final_tol : p.inner_tol;
+        kp.last = (k == K - 1) ? 1 : 0;
+        if (k > 0) run(ctx, st, PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
+        // warm-up: chunks of W Sinkhorn iterations, then a readback
+        if (p.max_sinkhorn > 0) {
+            int W = 1;
+            for (;;) {
+                for (int w = 0; w < W; ++w) {
+                    run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
+                    run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
+                    run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
+                }
+                const Ctrl* h = readback(ctx, st, d_ctrl, count);
+                bool any = false;
+                for (int q = 0; q < count; ++q) any |= h[q].phase == PH_WARM;
+                if (!any) break;
+                W = std::min(2 * W, 8);
+            }
+        }
+        // Newton steps; a readback after each
+        for (;;) {
+            run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
+            run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L); });
+            run(ctx, st, PINS_K_FILL, [&] { launch_fill(L, src); });
+            run(ctx, st, PINS_K_CSC, [&] { launch_csc(L); });
+            run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
+            run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
+            for (int h = 1; h < p.ls_max; h += LS_T) run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, false); });
+            run(ctx, st, PINS_K_UPDATE, [&] { launch_update(L); });
+            run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, false, M_FB); });
+            run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, false, M_FB); });
+            run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_FB); });
+            const Ctrl* h = readback(ctx, st, d_ctrl, count);
+            bool any = false;
+            for (int q = 0; q < count; ++q) any |= (h[q].phase == PH_NEWTON || h[q].phase == PH_FALLBACK);
+            if (!any) break;
+        }
+    }
+    bool want_x = false;
+    for (int q = 0; q < count; ++q) want_x |= hI[q].X != nullptr;
+    run(ctx, st, PINS_K_FINAL, [&] { launch_final(L, base_src, (double)K, want_x); });
+    const Ctrl* h = readback(ctx, st, d_ctrl, count);
+
+    // outputs
+    if (host_api) {
+        for (int q = 0; q < count; ++q) {
+            const InstPlan& Lp = B.plans[q];
+            HIPCHK(hipMemcpyAsync(res[q].alpha, Dp(Lp.alpha), sizeof(double) * Lp.m, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(res[q].beta, Dp(Lp.beta), sizeof(double) * Lp.n, hipMemcpyDeviceToHost, st));
+            if (res[q].X)
+                HIPCHK(hipMemcpyAsync(res[q].X, Dp(Lp.X), sizeof(double) * Lp.m * Lp.n, hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    double kms[PINS_NKERN] = {0};
+    int kcalls[PINS_NKERN] = {0};
+    if (ctx->profile) {
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t e = 0; e + 1 < ctx->ev_used; e += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]));
+            const int kd = ctx->ev_kind[e / 2];
+            kms[kd] += ms;
+            kcalls[kd] += 1;
+        }
+    }
+    const double wall = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    int worst = PINS_OK;
+    for (int q = 0; q < count; ++q) {
+        pins_result& r = res[q];
+        const Ctrl& S = h[q];
+        r.cost = S.cost;
+        r.eps = p.eta / (double)K;
+        r.resid = S.resid;
+        r.dual = S.dual;
+        r.gap = S.cost - S.dual;
+        r.entropy = S.entropy;
+        r.cost_scale = need_max ? S.scale : hI[q].bscale;
+        r.time_ms = wall;
+        r.flags = S.flags | (S.nonfinite ? 4 : 0);
+        r.outer_iters = K;
+        r.sinkhorn_iters = S.sink_total;
+        r.newton_iters = S.newton_total;
+        r.cg_iters = S.cg_total;
+        r.fallbacks = S.fb_total;
+        r.nnz_last = S.nnz;
+        r.status = S.nonfinite ? PINS_ENUMERIC : ((S.flags & 1) ? PINS_NOT_CONVERGED : PINS_OK);
+        for (int kk = 0; kk < PINS_NKERN; ++kk) {
+            r.kern_ms[kk] = kms[kk];
+            r.kern_calls[kk] = kcalls[kk];
+        }
+        if (r.status < 0 && (worst >= 0 || r.status < worst)) worst = r.status;
+        if (worst >= 0 && r.status > worst) worst = r.status;
+    }
+    return worst;
+}
+
+template <class Fn>
+int guarded(pins_ctx* ctx, Fn&& fn) {
+    if (!ctx) return PINS_EINVAL;
+    try {
+        ctx->err.clear();
+        return fn();
+    } catch (const Fail& f) {
+        ctx->err = f.msg;
+        return f.code;
+    } catch (const HipError& e) {
+        ctx->err = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
+        return PINS_EDEVICE;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        return PINS_ENOMEM;
+    } catch (...) {
+        ctx->err = "unexpected internal error";
+        return PINS_EDEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pins_abi_version(void) { return PINS_ABI_VERSION; }
+
+void pins_params_default(pins_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->eta = 1e-2;
+    p->max_outer = 250;
+    p->max_sinkhorn = 100;
+    p->max_newton = 50;
+    p->cg_max_iter = 1000;
+    p->warm_tol = 1e-3;
+    p->inner_tol = 1e-9;
+    p->final_tol = 1e-12;
+    p->cg_rtol = 1e-6;
+    p->ls_beta = 0.5;
+    p->ls_c1 = 1e-4;
+    p->ls_max = 30;
+    p->rho_levels = 13;
+    p->rho = 1e-9;
+    p->budget = 64.0;
+    p->precision = PINS_FP64;
+    p->shift_mode = PINS_SHIFT_IMPLICIT;
+    p->profile = 0;
+}
+
+int pins_create(int device, pins_ctx** out) {
+    if (!out) return PINS_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return PINS_EDEVICE;
+    }
+    pins_ctx* c = new (std::nothrow) pins_ctx;
+    if (!c) return PINS_ENOMEM;
+    c->device = device;
+    *out = c;
+    return PINS_OK;
+}
+
+void pins_destroy(pins_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+}
+
+const char* pins_last_error(const pins_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int pins_workspace_bytes(const pins_problem* probs, int count, const pins_params* p, size_t* bytes) {
+    if (!probs || !p || !bytes || count < 1) return PINS_EINVAL;
+    try {
+        check_params(*p);
+        for (int q = 0; q < count; ++q) check_problem_shape(probs[q]);
+        *bytes = plan_batch(probs, count, *p, false, nullptr).total;
+        return PINS_OK;
+    } catch (const Fail& f) {
+        return f.code;
+    } catch (...) {
+        return PINS_EINVAL;
+    }
+}
+
+int pins_solve(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res) {
+    return guarded(ctx, [&] {
+        if (!prob || !p || !res) fail(PINS_EINVAL, "null argument");
+        return solve_impl(ctx, prob, 1, *p, res, nullptr, true);
+    });
+}
+
+int pins_solve_device(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res,
+                      void* stream) {
+    return guarded(ctx, [&] {
+        if (!prob || !p || !res) fail(PINS_EINVAL, "null argument");
+        return solve_impl(ctx, prob, 1, *p, res, (hipStream_t)stream, false);
+    });
+}
+
+int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
+                            pins_result* res, void* stream) {
+    return guarded(ctx, [&] {
+        if (!probs || !p || !res) fail(PINS_EINVAL, "null argument");
+        return solve_impl(ctx, probs, count, *p, res, (hipStream_t)stream, false);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// pins_internal.h -- device-side data layout shared by the HIP kernels and
+// the host orchestrator of libpins.so.  Not part of the public ABI.
+//
+// Representation of the shifted cost (Alg. 2, C^k = C - eta log X^k):
+// with X^0 = a b^T and the recovery map of eq. (eppa_x), every shifted cost is
+//     C^k = (k+1) C - Ahat (+) Bhat
+// for two vectors Ahat (m), Bhat (n).  The kernels therefore evaluate the
+// exponent of the recovery map as
+//     log Xt_ij = (F_i + G_j - kappa * Csrc_ij) / eta
+// where (implicit mode) kappa = k+1, Csrc = C, F = f + Ahat - eta, G = g + Bhat,
+// or (materialised mode) kappa = 1, Csrc = C^k stored densely, F = f - eta,
+// G = g.  (f, g) are the inner duals of Alg. 2; a Sinkhorn or Newton update of
+// (f, g) is the same update of (F, G).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pins {
+
+constexpr int NLEV = 16;     // maximum number of Sparsify levels
+constexpr int LS_T = 8;      // trial step sizes per line-search pass (after the first)
+constexpr int TILE_C = 256;  // columns per tile (one per thread)
+constexpr int TILE_RMAX = 16;  // maximum rows per tile
+
+enum Phase : int { PH_DONE = 0, PH_WARM = 1, PH_NEWTON = 2, PH_FALLBACK = 3 };
+enum LsState : int { LS_PENDING = 0, LS_ACCEPTED = 1, LS_FAILED = 2 };
+enum SrcKind : int { SRC_DENSE = 0, SRC_GRID = 1 };
+
+// Per-instance descriptor (device memory, read-only in kernels).
+struct DevInst {
+    int m, n;
+    int grid_s;   // SRC_GRID: side of the grid (m = n = s*s)
+    int R;        // rows per tile of the tile kernels (<= TILE_RMAX)
+    int nrb, ncb; // row blocks (ceil(m/R)), column blocks (ceil(n/TILE_C))
+    int nnz_cap;  // capacity of the CSR/CSC arrays
+    int pad0;
+    long ldc;                 // leading dimension of csrc / cbase
+    const double* csrc;       // exponent cost source: C (implicit) or C^k (materialised)
+    double cscale;            // scale applied to csrc entries
+    const double* cbase;      // unshifted cost for the outputs (dense kinds)
+    double bscale;            // its scale
+    const double* a;
+    const double* b;
+    double* loga;
+    double* logb;
+    double* F;
+    double* G;
+    double* Ah;  // Ahat
+    double* Bh;  // Bhat
+    double* rc;  // r = Xt e (m) followed by c = Xt^T e (n)
+    double* d;   // Newton direction (m+n)
+    double* cgw; // CG work: res, z, p, Ap (4*(m+n))
+    double* part;   // column partials of tile kernels: nrb * n * 2
+    double* part2;  // row partials of tile kernels: ncb * m * LS_T
+    double* blk;    // per-block scalars: >= max blocks * LS_T
+    double* blk2;   // second per-block scalar area (merge kernels)
+    int* hist;      // m * NLEV Sparsify histogram
+    int* rowptr;    // m+1
+    int* col;       // nnz_cap
+    double* val;    // nnz_cap
+    int* colptr;    // n+1
+    int* rowT;      // nnz_cap
+    double* valT;   // nnz_cap
+    int* cfill;     // n
+    double* Ck;     // materialised shifted cost (m*n) or nullptr
+    double* alpha;  // outputs
+    double* beta;
+    double* X;      // optional dense plan
+};
+
+// Per-instance control block (device memory; the host reads it back).
+struct Ctrl {
+    int phase, t, ticket, ls_state;
+    int level, nnz, ls_h, flags;
+    int sink_total, newton_total, cg_total, fb_total;
+    int last_cg, ticket2, nonfinite, pad;
+    double kappa, err, resid, alpha;
+    double gd, dab, fa, cost;
+    double entropy, dual, scale, pad2;
+};
+
+// Kernel-wide parameters (passed by value).
+struct KP {
+    double eta, inv_eta;
+    double warm_tol, tol;   // tol: marginal tolerance of the current subproblem
+    double cg_rtol, ls_beta, ls_c1, log_rho;
+    double budget;
+    int T1, T2, cg_max, ls_max;
+    int nlev, shift_mode, last, pad;
+};
+
+}  // namespace pins

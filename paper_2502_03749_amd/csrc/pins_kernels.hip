@@ -1,0 +1,1213 @@
+// pins_kernels.hip -- HIP kernels of the PINS hot path for MI355X (gfx950).
+//
+// Every kernel covers a batch of independent instances: blockIdx.y is the
+// instance, and each instance's control block (Ctrl::phase) decides whether
+// the instance takes part in a launch.  An instance's arithmetic never
+// depends on which other instances are in the batch, so a batched result is
+// bitwise the result of the same problem solved alone.
+//
+// Wave64 throughout.  Reductions are fixed-order trees (wave butterflies,
+// then LDS in wave order, then per-block partials summed in block order), so
+// every run is bitwise reproducible.  No value atomics: atomics only count
+// integers (Sparsify histogram, CSC counts) or hand out tickets.
+//
+// Paper references: Alg. 1 / Alg. 2 (log-domain Sinkhorn, PINS), eq. (eppa_x)
+// recovery map, eq. (eppa-sub-dual) dual objective, eq. (eppa-hess) Hessian.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "pins_internal.h"
+#include "pins_launch.h"
+
+namespace pins {
+
+static constexpr double INV_LN10 = 0.43429448190325182765;
+
+// ---------------------------------------------------------------------------
+// cost sources
+// ---------------------------------------------------------------------------
+
+// Dense row-major cost.  `base` selects the unshifted cost (outputs, shift)
+// instead of the exponent source (which is C^k in materialised mode).
+struct DenseSrc {
+    const double* __restrict__ C;
+    long ld;
+    double s;
+    __device__ __forceinline__ DenseSrc(const DevInst& I, bool base = false)
+        : C(base ? I.cbase : I.csrc), ld(I.ldc), s(base ? I.bscale : I.cscale) {}
+    __device__ __forceinline__ double at(int i, int j) const { return C[(long)i * ld + j] * s; }
+};
+
+// Squared distance between pixels p = row*s + col of an s x s grid, times the
+// scale; exact integers before scaling, never stored.
+struct GridSrc {
+    int s;
+    double sc;
+    __device__ __forceinline__ GridSrc(const DevInst& I, bool base = false) : s(I.grid_s), sc(base ? I.bscale : I.cscale) {}
+    __device__ __forceinline__ double at(int i, int j) const {
+        const int ri = i / s, ci = i - ri * s, rj = j / s, cj = j - rj * s;
+        const int dr = ri - rj, dc = ci - cj;
+        return (double)(dr * dr + dc * dc) * sc;
+    }
+};
+
+// log of the recovery map, eq. (eppa_x): (F_i + G_j - kappa*C_ij)/eta
+__device__ __forceinline__ double expo(double Fi, double Gj, double kap, double c, double ie) {
+    return (Fi + Gj - kap * c) * ie;
+}
+
+// Sparsify level coordinate: Xt_ij >= rho*10^l*min(a_i,b_j)  <=>  q >= l
+__device__ __forceinline__ double lev_q(double x, double log_rho, double la, double lb) {
+    return (x - log_rho - fmin(la, lb)) * INV_LN10;
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// (max, sum) pairs of log-sum-exp; an empty pair is (-inf, 0).
+template <class T>
+__device__ __forceinline__ T ex(double y);
+template <>
+__device__ __forceinline__ double ex<double>(double y) { return exp(y); }
+template <>
+__device__ __forceinline__ float ex<float>(double y) { return __expf((float)y); }
+
+template <class T>
+__device__ __forceinline__ void lse_combine(double& mx, T& sm, double m2, T s2) {
+    const double M = fmax(mx, m2);
+    const T u = (mx == -INFINITY) ? T(0) : sm * ex<T>(mx - M);
+    const T v = (m2 == -INFINITY) ? T(0) : s2 * ex<T>(m2 - M);
+    mx = M;
+    sm = u + v;
+}
+
+template <class T>
+__device__ __forceinline__ void wave_lse(double& mx, T& sm) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double m2 = __shfl_xor(mx, o);
+        const T s2 = __shfl_xor(sm, o);
+        lse_combine(mx, sm, m2, s2);
+    }
+}
+
+// Sum over a block of NT threads, result broadcast to all; fixed order.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    constexpr int NW = NT / 64;
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t += sh[k];
+    return t;
+}
+
+// Sum of p[0..len) by a block of NT threads in a fixed order.
+template <int NT>
+__device__ __forceinline__ double block_sum_array(const double* p, int len, double* sh) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < len; k += NT) v += p[k];
+    return block_sum<NT>(v, sh);
+}
+
+// Exclusive scan of cnt(k), k < len, by a block of NT threads; writes out[k]
+// (clamped to cap) and out[len]; returns the unclamped total.
+template <int NT, class CountF>
+__device__ __forceinline__ long block_scan_excl(CountF cnt, int len, int* out, int cap, int* sh) {
+    constexpr int NW = NT / 64;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    long carry = 0;
+    for (int base = 0; base < len; base += NT) {
+        const int k = base + threadIdx.x;
+        const int c = (k < len) ? cnt(k) : 0;
+        int inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o);
+            if (l >= o) inc += t;
+        }
+        __syncthreads();
+        if (l == 63) sh[w] = inc;
+        __syncthreads();
+        int woff = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int s = sh[q];
+            if (q < w) woff += s;
+            tot += s;
+        }
+        if (k < len) {
+            const long e = carry + woff + inc - c;
+            out[k] = (int)(e < cap ? e : cap);
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[len] = (int)(carry < cap ? carry : cap);
+    __syncthreads();
+    return carry;
+}
+
+// Last-block detection: every participating block calls this once; it
+// returns true in exactly one block, after all others have released their
+// writes.  The ticket is reset for the next launch.
+__device__ __forceinline__ bool last_block(int* ticket, int nblocks) {
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = atomicAdd(ticket, 1);
+        s_last = (t == nblocks - 1);
+        if (s_last) atomicExch(ticket, 0);
+    }
+    __syncthreads();
+    if (s_last) __threadfence();
+    return s_last != 0;
+}
+
+__device__ __forceinline__ bool phase_in(const Ctrl* ctrl, int b, int mask) {
+    return (mask >> ctrl[b].phase) & 1;
+}
+
+// ---------------------------------------------------------------------------
+// a2: Sinkhorn f-update (row log-sum-exp sweep), one wave per row.
+//   F_i <- eta*log a_i - eta*LSE_j((G_j - kappa*C_ij)/eta)
+// Also the row-marginal error of the state before the update:
+//   r_i = a_i*exp((F_old - F_new)/eta),   blk[block] = sum |r_i - a_i|.
+// T = float: exp and the sum in single precision (mixed path); the exponent
+// and the running maximum stay double.
+// ---------------------------------------------------------------------------
+template <class Src, class T>
+__global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                 int mask) {
+    const int b = blockIdx.y;
+    if (!phase_in(ctrl, b, mask)) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n;
+    if ((int)blockIdx.x * 4 >= m) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + w;
+    __shared__ double serr[4];
+    double err = 0.0;
+    if (i < m) {
+        const double kap = ctrl[b].kappa, ie = kp.inv_eta;
+        const Src src(I);
+        const double* __restrict__ G = I.G;
+        double mx = -INFINITY;
+        T sm = T(0);
+        constexpr int U = 4;
+        for (int j0 = 0; j0 < n; j0 += 64 * U) {
+            double z[U];
+            double cm = -INFINITY;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * 64 + lane;
+                z[u] = (j < n) ? (G[j] - kap * src.at(i, j)) * ie : -INFINITY;
+                cm = fmax(cm, z[u]);
+            }
+            if (cm > mx) {
+                sm *= ex<T>(mx - cm);
+                mx = cm;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * 64 + lane;
+                if (j < n) sm += ex<T>(z[u] - mx);
+            }
+        }
+        wave_lse(mx, sm);
+        if (lane == 0) {
+            const double lse = mx + log((double)sm);
+            const double Fo = I.F[i];
+            const double Fn = kp.eta * (I.loga[i] - lse);
+            const double ai = I.a[i];
+            err = fabs(ai * exp((Fo - Fn) * ie) - ai);
+            I.F[i] = Fn;
+        }
+    }
+    if (lane == 0) serr[w] = err;
+    __syncthreads();
+    if (threadIdx.x == 0) I.blk[blockIdx.x] = ((serr[0] + serr[1]) + serr[2]) + serr[3];
+}
+
+// ---------------------------------------------------------------------------
+// a3: Sinkhorn g-update, column partials.  Tile = R rows x 256 columns, one
+// column per thread: part[rb][j] = (max, sum) of (F_i - kappa*C_ij)/eta over
+// the tile's rows (with the new F: Gauss-Seidel).
+// ---------------------------------------------------------------------------
+template <class Src, class T>
+__global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                 int mask) {
+    const int b = blockIdx.y;
+    if (!phase_in(ctrl, b, mask)) return;
+    const DevInst& I = insts[b];
+    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
+    if (rb >= I.nrb) return;
+    const int m = I.m, n = I.n;
+    const int j = cb * TILE_C + threadIdx.x;
+    if (j >= n) return;
+    const int i0 = rb * I.R, i1 = min(m, i0 + I.R);
+    const double kap = ctrl[b].kappa, ie = kp.inv_eta;
+    const Src src(I);
+    const double* __restrict__ F = I.F;
+    double mx = -INFINITY;
+    T sm = T(0);
+    constexpr int U = 4;
+    for (int i = i0; i < i1; i += U) {
+        double z[U];
+        double cm = -INFINITY;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ii = i + u;
+            z[u] = (ii < i1) ? (F[ii] - kap * src.at(ii, j)) * ie : -INFINITY;
+            cm = fmax(cm, z[u]);
+        }
+        if (cm > mx) {
+            sm *= ex<T>(mx - cm);
+            mx = cm;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u < i1) sm += ex<T>(z[u] - mx);
+    }
+    reinterpret_cast<double2*>(I.part)[(long)rb * n + j] = make_double2(mx, (double)sm);
+}
+
+// Merge of the column partials: G_j <- eta*log b_j - eta*LSE; the last block
+// runs the warm-up control (row error of the sweep, exit test).
+__global__ __launch_bounds__(256) void k_col_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                   int mask) {
+    const int b = blockIdx.y;
+    if (!phase_in(ctrl, b, mask)) return;
+    const DevInst& I = insts[b];
+    const int n = I.n, m = I.m;
+    const int nb = (n + 255) / 256;
+    if ((int)blockIdx.x >= nb) return;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n) {
+        const double2* __restrict__ P = reinterpret_cast<const double2*>(I.part);
+        double mx = -INFINITY;
+        for (int rb = 0; rb < I.nrb; ++rb) mx = fmax(mx, P[(long)rb * n + j].x);
+        double s = 0.0;
+        for (int rb = 0; rb < I.nrb; ++rb) {
+            const double2 q = P[(long)rb * n + j];
+            if (q.x != -INFINITY) s += q.y * exp(q.x - mx);
+        }
+        I.G[j] = kp.eta * (I.logb[j] - (mx + log(s)));
+    }
+    if (last_block(&ctrl[b].ticket, nb)) {
+        __shared__ double sh[4];
+        const double err = block_sum_array<256>(I.blk, (m + 3) / 4, sh);
+        if (threadIdx.x == 0) {
+            Ctrl& S = ctrl[b];
+            if (S.phase == PH_WARM) {
+                S.err = err;
+                S.t += 1;
+                S.sink_total += 1;
+                if (!isfinite(err)) {
+                    S.nonfinite = 1;
+                    S.phase = PH_DONE;
+                } else if (err <= kp.warm_tol || S.t >= kp.T1) {
+                    S.phase = PH_NEWTON;
+                    S.t = 0;
+                }
+            } else if (S.phase == PH_FALLBACK) {
+                S.phase = PH_NEWTON;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a5: Newton pass.  Tile = R rows x 256 columns.  Xt_ij of eq. (eppa_x);
+// column partials part[rb][j], row partials part2[cb][i], and the Sparsify
+// histogram hist[i][l] (count of entries whose highest kept level is l).
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
+    if (rb >= I.nrb) return;
+    const int m = I.m, n = I.n;
+    const int i0 = rb * I.R, rows = min(I.R, m - i0);
+    __shared__ int hist[TILE_RMAX * NLEV];
+    __shared__ double red[TILE_RMAX][TILE_C + 1];
+    for (int t = threadIdx.x; t < TILE_RMAX * NLEV; t += 256) hist[t] = 0;
+    __syncthreads();
+    const int j = cb * TILE_C + threadIdx.x;
+    const bool valid = j < n;
+    const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
+    const int nlev = kp.nlev;
+    const Src src(I);
+    const double Gj = valid ? I.G[j] : 0.0, lbj = valid ? I.logb[j] : 0.0;
+    double colacc = 0.0;
+    for (int r = 0; r < rows; ++r) {
+        const int i = i0 + r;
+        double e = 0.0;
+        if (valid) {
+            const double x = expo(I.F[i], Gj, kap, src.at(i, j), ie);
+            e = exp(x);
+            const double q = lev_q(x, lrho, I.loga[i], lbj);
+            if (q >= 0.0) {
+                const int l = (q >= (double)(nlev - 1)) ? nlev - 1 : (int)q;
+                atomicAdd(&hist[r * NLEV + l], 1);
+            }
+        }
+        colacc += e;
+        red[r][threadIdx.x] = e;
+    }
+    if (valid) I.part[(long)rb * n + j] = colacc;
+    __syncthreads();
+    // row sums: 16 threads per row, 16 columns each, then a 16-lane butterfly
+    {
+        const int r = threadIdx.x >> 4, s = threadIdx.x & 15;
+        double v = 0.0;
+        if (r < rows)
+            for (int k = 0; k < 16; ++k) v += red[r][s * 16 + k];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (r < rows && s == 0) I.part2[(long)cb * m + i0 + r] = v;
+    }
+    for (int t = threadIdx.x; t < rows * NLEV; t += 256) {
+        const int v = hist[t];
+        if (v) atomicAdd(&I.hist[(long)(i0 + t / NLEV) * NLEV + (t % NLEV)], v);
+    }
+}
+
+// Gradient merge: r = Xt e, c = Xt^T e into rc; the last block tests
+// convergence (||a-r||_1 + ||b-c||_1 <= tol, or the Newton cap), picks the
+// Sparsify level (densest level within the budget) and builds the CSR row
+// pointers by an exclusive scan of the per-row kept counts.
+__global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+                                                    KP kp) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n, N = m + n;
+    const int nb = (N + 255) / 256;
+    if ((int)blockIdx.x >= nb) return;
+    __shared__ double sh[4];
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    double dev = 0.0;
+    if (k < m) {
+        double s = 0.0;
+        for (int cb = 0; cb < I.ncb; ++cb) s += I.part2[(long)cb * m + k];
+        I.rc[k] = s;
+        dev = fabs(I.a[k] - s);
+    } else if (k < N) {
+        const int j = k - m;
+        double s = 0.0;
+        for (int rb = 0; rb < I.nrb; ++rb) s += I.part[(long)rb * n + j];
+        I.rc[k] = s;
+        dev = fabs(I.b[j] - s);
+    }
+    const double bs = block_sum<256>(dev, sh);
+    if (threadIdx.x == 0) I.blk2[blockIdx.x] = bs;
+    if (!last_block(&ctrl[b].ticket, nb)) return;
+
+    const double res = block_sum_array<256>(I.blk2, nb, sh);
+    Ctrl& S = ctrl[b];
+    __shared__ int s_go, s_lev;
+    __shared__ int ish[4];
+    if (threadIdx.x == 0) {
+        S.resid = res;
+        int go = 0;
+        if (!isfinite(res)) {
+            S.nonfinite = 1;
+            S.phase = PH_DONE;
+        } else if (res <= kp.tol) {
+            S.phase = PH_DONE;
+        } else if (S.t >= kp.T2) {
+            S.flags |= kp.last ? 1 : 2;
+            S.phase = PH_DONE;
+        } else {
+            go = 1;
+        }
+        s_go = go;
+    }
+    __syncthreads();
+    if (s_go) {
+        // level totals: tot[l] = number of entries whose highest kept level is l
+        __shared__ long tot[NLEV];
+        const int nlev = kp.nlev;
+        for (int l = 0; l < nlev; ++l) {
+            int c = 0;
+            for (int i = threadIdx.x; i < m; i += 256) c += I.hist[(long)i * NLEV + l];
+            c = wave_sum_i(c);
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) ish[threadIdx.x >> 6] = c;
+            __syncthreads();
+            if (threadIdx.x == 0) tot[l] = (long)ish[0] + ish[1] + ish[2] + ish[3];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double lim = kp.budget * (double)(m + n - 1);
+            int lev = nlev - 1;
+            long cum = 0;
+            // count kept at level l = sum_{l' >= l} tot[l']; smallest l within the budget
+            long kept[NLEV];
+            for (int l = nlev - 1; l >= 0; --l) {
+                cum += tot[l];
+                kept[l] = cum;
+            }
+            for (int l = 0; l < nlev; ++l)
+                if ((double)kept[l] <= lim) {
+                    lev = l;
+                    break;
+                }
+            s_lev = lev;
+            S.level = lev;
+        }
+        __syncthreads();
+        const int lev = s_lev;
+        const int* __restrict__ H = I.hist;
+        const long total = block_scan_excl<256>(
+            [&](int i) {
+                int c = 0;
+                for (int l = lev; l < nlev; ++l) c += H[(long)i * NLEV + l];
+                return c;
+            },
+            m, I.rowptr, I.nnz_cap, ish);
+        if (threadIdx.x == 0) S.nnz = (int)(total < I.nnz_cap ? total : I.nnz_cap);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * NLEV; t += 256) I.hist[t] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// a6: Sparsify fill, one wave per row: entries with level >= chosen level,
+// in increasing column order (ballot compaction).
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + w;
+    if (i >= m) return;
+    const double lev = (double)ctrl[b].level;
+    const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
+    const Src src(I);
+    int base = I.rowptr[i];
+    const int end = I.rowptr[i + 1];
+    const double Fi = I.F[i], la = I.loga[i];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int j0 = 0; j0 < n && base < end; j0 += 64) {
+        const int j = j0 + lane;
+        bool keep = false;
+        double x = 0.0;
+        if (j < n) {
+            x = expo(Fi, I.G[j], kap, src.at(i, j), ie);
+            keep = lev_q(x, lrho, la, I.logb[j]) >= lev;
+        }
+        const unsigned long long bal = __ballot(keep);
+        const int slot = base + __popcll(bal & below);
+        if (keep && slot < end) {
+            I.col[slot] = j;
+            I.val[slot] = exp(x);
+        }
+        base += __popcll(bal);
+    }
+    // slots left over (kept count below the histogram's) hold explicit zeros
+    // so that the CSR is always well formed
+    for (int s = base + lane; s < end; s += 64) {
+        I.col[s] = 0;
+        I.val[s] = 0.0;
+    }
+}
+
+// CSC copy of S (for S^T u in the Hessian product), one block per instance:
+// column counts, scan, scatter, then each column sorted by row index so the
+// order (and the products) are deterministic.
+__global__ __launch_bounds__(1024) void k_csc(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n;
+    const int nnz = ctrl[b].nnz;
+    __shared__ int ish[16];
+    for (int j = threadIdx.x; j < n; j += 1024) I.cfill[j] = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < nnz; k += 1024) atomicAdd(&I.cfill[I.col[k]], 1);
+    __syncthreads();
+    const int* cf = I.cfill;
+    block_scan_excl<1024>([&](int j) { return cf[j]; }, n, I.colptr, 0x7fffffff, ish);
+    for (int j = threadIdx.x; j < n; j += 1024) I.cfill[j] = I.colptr[j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += 1024) {
+        const int k1 = I.rowptr[i + 1];
+        for (int k = I.rowptr[i]; k < k1; ++k) {
+            const int s = atomicAdd(&I.cfill[I.col[k]], 1);
+            I.rowT[s] = i;
+            I.valT[s] = I.val[k];
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += 1024) {
+        const int k0 = I.colptr[j], k1 = I.colptr[j + 1];
+        for (int k = k0 + 1; k < k1; ++k) {
+            const int r = I.rowT[k];
+            const double v = I.valT[k];
+            int q = k - 1;
+            while (q >= k0 && I.rowT[q] > r) {
+                I.rowT[q + 1] = I.rowT[q];
+                I.valT[q + 1] = I.valT[q];
+                --q;
+            }
+            I.rowT[q + 1] = r;
+            I.valT[q + 1] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a7: truncated Jacobi-preconditioned CG on M d = eta*grad P, where
+// M = [diag(r) S; S^T diag(c)] = -eta * (sparsified Hessian of eq. (eppa-hess)),
+// x0 = 0, stop at ||res||_2 <= cg_rtol*||rhs||_2 or cg_max.  One block per
+// instance.  Then the line-search inputs <grad P, d>, <a,dF>+<b,dG>.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n, N = m + n;
+    double* __restrict__ x = I.d;
+    double* __restrict__ res = I.cgw;
+    double* __restrict__ z = I.cgw + N;
+    double* __restrict__ p = I.cgw + 2 * N;
+    double* __restrict__ Ap = I.cgw + 3 * N;
+    const double* __restrict__ dg = I.rc;
+    const int* __restrict__ rp = I.rowptr;
+    const int* __restrict__ ci = I.col;
+    const double* __restrict__ sv = I.val;
+    const int* __restrict__ cp = I.colptr;
+    const int* __restrict__ ri = I.rowT;
+    const double* __restrict__ svT = I.valT;
+    __shared__ double sh[16];
+    const double eta = kp.eta;
+    double bb = 0.0, rz = 0.0;
+    for (int k = threadIdx.x; k < N; k += 1024) {
+        const double tgt = (k < m) ? I.a[k] : I.b[k - m];
+        const double rh = eta * (tgt - dg[k]);
+        x[k] = 0.0;
+        res[k] = rh;
+        const double zz = rh / dg[k];
+        p[k] = zz;
+        bb += rh * rh;
+        rz += rh * zz;
+    }
+    bb = block_sum<1024>(bb, sh);
+    rz = block_sum<1024>(rz, sh);
+    const double bn = sqrt(bb);
+    int it = 0;
+    if (bn > 0.0) {
+        while (it < kp.cg_max) {
+            __syncthreads();
+            double pap = 0.0;
+            for (int k = threadIdx.x; k < N; k += 1024) {
+                double s = dg[k] * p[k];
+                if (k < m) {
+                    for (int q = rp[k]; q < rp[k + 1]; ++q) s += sv[q] * p[m + ci[q]];
+                } else {
+                    const int j = k - m;
+                    for (int q = cp[j]; q < cp[j + 1]; ++q) s += svT[q] * p[ri[q]];
+                }
+                Ap[k] = s;
+                pap += p[k] * s;
+            }
+            pap = block_sum<1024>(pap, sh);
+            if (!(pap > 0.0)) break;
+            const double al = rz / pap;
+            double rr = 0.0, rz2 = 0.0;
+            for (int k = threadIdx.x; k < N; k += 1024) {
+                x[k] += al * p[k];
+                const double rk = res[k] - al * Ap[k];
+                res[k] = rk;
+                const double zk = rk / dg[k];
+                z[k] = zk;
+                rr += rk * rk;
+                rz2 += rk * zk;
+            }
+            rr = block_sum<1024>(rr, sh);
+            rz2 = block_sum<1024>(rz2, sh);
+            ++it;
+            if (sqrt(rr) <= kp.cg_rtol * bn) break;
+            const double be = rz2 / rz;
+            rz = rz2;
+            for (int k = threadIdx.x; k < N; k += 1024) p[k] = z[k] + be * p[k];
+        }
+    }
+    __syncthreads();
+    // line-search inputs
+    double gd = 0.0, dab = 0.0, fa = 0.0;
+    for (int k = threadIdx.x; k < N; k += 1024) {
+        const double tgt = (k < m) ? I.a[k] : I.b[k - m];
+        gd += (tgt - dg[k]) * x[k];
+        dab += tgt * x[k];
+        fa += fabs(tgt * x[k]);
+    }
+    gd = block_sum<1024>(gd, sh);
+    dab = block_sum<1024>(dab, sh);
+    fa = block_sum<1024>(fa, sh);
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        S.last_cg = it;
+        S.cg_total += it;
+        S.gd = gd;
+        S.dab = dab;
+        S.fa = fa;
+        S.ls_h = 0;
+        if (!(gd > 0.0)) {
+            S.ls_state = LS_FAILED;
+        } else if (kp.ls_c1 * gd <= 64.0 * DBL_EPSILON * fa) {
+            S.ls_state = LS_ACCEPTED;  // increase below the evaluation's resolution: full step
+            S.alpha = 1.0;
+        } else {
+            S.ls_state = LS_PENDING;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a8: Armijo trials on P^k (eq. eppa-sub-dual), NT step sizes per pass:
+//   P(f+al df, g+al dg) - P(f,g) = al(<a,df>+<b,dg>) - eta sum_ij Xt_ij expm1(al(df_i+dg_j)/eta)
+// accept the first al = beta^h with increase >= c1*al*<grad P, d>.
+// ---------------------------------------------------------------------------
+template <class Src, int NT>
+__global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON || ctrl[b].ls_state != LS_PENDING) return;
+    const DevInst& I = insts[b];
+    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
+    if (rb >= I.nrb) return;
+    const int m = I.m, n = I.n;
+    const int h0 = ctrl[b].ls_h;
+    const int nt = min(NT, kp.ls_max - h0);
+    double al[NT];
+    {
+        double a0 = 1.0;
+        for (int h = 0; h < h0; ++h) a0 *= kp.ls_beta;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            al[t] = a0;
+            a0 *= kp.ls_beta;
+        }
+    }
+    const int i0 = rb * I.R, rows = min(I.R, m - i0);
+    const int j = cb * TILE_C + threadIdx.x;
+    const bool valid = j < n;
+    const double kap = ctrl[b].kappa, ie = kp.inv_eta;
+    const Src src(I);
+    double acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+    if (valid) {
+        const double Gj = I.G[j], dGj = I.d[m + j];
+        for (int r = 0; r < rows; ++r) {
+            const int i = i0 + r;
+            const double e = exp(expo(I.F[i], Gj, kap, src.at(i, j), ie));
+            const double del = (I.d[i] + dGj) * ie;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] += e * expm1(al[t] * del);
+        }
+    }
+    __shared__ double sh[4];
+    const int nblk = I.nrb * I.ncb;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const double s = block_sum<256>(acc[t], sh);
+        if (threadIdx.x == 0) I.blk[(long)blockIdx.x * NT + t] = s;
+    }
+    if (!last_block(&ctrl[b].ticket, nblk)) return;
+    double tot[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double v = 0.0;
+        for (int k = threadIdx.x; k < nblk; k += 256) v += I.blk[(long)k * NT + t];
+        tot[t] = block_sum<256>(v, sh);
+    }
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        int acc_t = -1;
+        for (int t = 0; t < nt; ++t) {
+            const double inc = al[t] * S.dab - kp.eta * tot[t];
+            if (inc >= kp.ls_c1 * al[t] * S.gd) {
+                acc_t = t;
+                break;
+            }
+        }
+        if (acc_t >= 0) {
+            S.alpha = al[acc_t];
+            S.ls_state = LS_ACCEPTED;
+        } else {
+            S.ls_h = h0 + nt;
+            if (S.ls_h >= kp.ls_max) S.ls_state = LS_FAILED;
+        }
+    }
+}
+
+// a9: (f, g) += alpha*(df, dg); without an accepted step the instance takes
+// one Sinkhorn iteration instead (phase FALLBACK).  One block per instance.
+__global__ __launch_bounds__(1024) void k_update(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = I.m + I.n;
+    const int st = ctrl[b].ls_state;
+    const double al = ctrl[b].alpha;
+    if (st == LS_ACCEPTED)
+        for (int k = threadIdx.x; k < N; k += 1024) {
+            if (k < m)
+                I.F[k] += al * I.d[k];
+            else
+                I.G[k - m] += al * I.d[k];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        S.t += 1;
+        S.newton_total += 1;
+        if (st != LS_ACCEPTED) {
+            S.phase = PH_FALLBACK;
+            S.fb_total += 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a1: outer shift, C^{k+1} = C^k + C - f (+) g + eta, warm start (f, g) kept.
+// Implicit: (F, Ahat) <- (2F - Ahat, F), (G, Bhat) <- (2G - Bhat, G),
+// kappa <- kappa + 1.  Materialised: C^k += C - F (+) G (elementwise kernel),
+// Ahat += F, Bhat += G.  Both re-enter the warm-up.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_shift_vec(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+                                                    int materialised, int start_phase) {
+    const int b = blockIdx.x;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = I.m + I.n;
+    for (int k = threadIdx.x; k < N; k += 1024) {
+        double* Fv = (k < m) ? I.F + k : I.G + (k - m);
+        double* Av = (k < m) ? I.Ah + k : I.Bh + (k - m);
+        const double f = *Fv, a = *Av;
+        if (materialised) {
+            *Av = a + f;
+        } else {
+            *Fv = 2.0 * f - a;
+            *Av = f;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        if (!materialised) S.kappa += 1.0;
+        S.t = 0;
+        S.phase = S.nonfinite ? PH_DONE : start_phase;
+    }
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void k_shift_dense(const DevInst* __restrict__ insts) {
+    const int b = blockIdx.y;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n;
+    const long mn = (long)m * n;
+    const Src base(I, true);
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < mn; q += (long)gridDim.x * 256) {
+        const int i = (int)(q / n), j = (int)(q - (long)i * n);
+        I.Ck[q] = I.Ck[q] + base.at(i, j) - I.F[i] - I.G[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// setup: log marginals, initial duals (f = g = 0), X^0 = a b^T.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_init(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.x;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = I.m + I.n;
+    const double eta = kp.eta;
+    const bool mat = kp.shift_mode != 0;
+    for (int k = threadIdx.x; k < N; k += 1024) {
+        if (k < m) {
+            const double la = log(I.a[k]);
+            I.loga[k] = la;
+            I.Ah[k] = eta * la;
+            I.F[k] = mat ? -eta : eta * la - eta;
+        } else {
+            const double lb = log(I.b[k - m]);
+            I.logb[k - m] = lb;
+            I.Bh[k - m] = eta * lb;
+            I.G[k - m] = mat ? 0.0 : eta * lb;
+        }
+    }
+    for (int t = threadIdx.x; t < m * NLEV; t += 1024) I.hist[t] = 0;
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        S.phase = S.nonfinite ? PH_DONE : (kp.T1 > 0 ? PH_WARM : PH_NEWTON);
+        S.kappa = 1.0;
+    }
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void k_init_ck(const DevInst* __restrict__ insts, KP kp) {
+    const int b = blockIdx.y;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n;
+    const long mn = (long)m * n;
+    const Src base(I, true);
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < mn; q += (long)gridDim.x * 256) {
+        const int i = (int)(q / n), j = (int)(q - (long)i * n);
+        I.Ck[q] = base.at(i, j) - kp.eta * (I.loga[i] + I.logb[j]);
+    }
+}
+
+// a0: dense squared-Euclidean cost of point clouds (unscaled), one thread per entry.
+__global__ __launch_bounds__(256) void k_points_cost(const double* __restrict__ x, const double* __restrict__ y,
+                                                     int m, int n, int d, double* __restrict__ C) {
+    const long mn = (long)m * n;
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < mn; q += (long)gridDim.x * 256) {
+        const int i = (int)(q / n), j = (int)(q - (long)i * n);
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double t = x[(long)i * d + k] - y[(long)j * d + k];
+            s += t * t;
+        }
+        C[q] = s;
+    }
+}
+
+// a0: max of a dense cost (for the 1/max normalisation) and a finiteness
+// check; per-block partial maxima, then the last block writes the scale.
+__global__ __launch_bounds__(256) void k_cost_max(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+                                                  double* __restrict__ scratch) {
+    const int b = blockIdx.y;
+    const DevInst& I = insts[b];
+    const long mn = (long)I.m * I.n;
+    double mx = 0.0;
+    int bad = 0;
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < mn; q += (long)gridDim.x * 256) {
+        const int i = (int)(q / I.n), j = (int)(q - (long)i * I.n);
+        const double v = I.cbase[(long)i * I.ldc + j];
+        if (!isfinite(v)) bad = 1;
+        mx = fmax(mx, v);
+    }
+    __shared__ double sm[256];
+    __shared__ int sb;
+    if (threadIdx.x == 0) sb = 0;
+    __syncthreads();
+    sm[threadIdx.x] = mx;
+    if (bad) atomicOr(&sb, 1);
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        scratch[(long)b * gridDim.x + blockIdx.x] = sm[0];
+        if (sb) atomicOr(&ctrl[b].nonfinite, 1);
+    }
+    if (!last_block(&ctrl[b].ticket, gridDim.x)) return;
+    if (threadIdx.x == 0) {
+        double M = 0.0;
+        for (int k = 0; k < (int)gridDim.x; ++k) M = fmax(M, scratch[(long)b * gridDim.x + k]);
+        ctrl[b].scale = (M > 0.0) ? 1.0 / M : 1.0;
+    }
+}
+
+// Copy the scale found by k_cost_max into the descriptors of the instances
+// whose scale was not given (bscale <= 0 marks them).
+__global__ void k_set_scale(DevInst* insts, Ctrl* ctrl, int count, int exponent_uses_base) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    if (!(insts[b].bscale > 0.0)) {
+        const double s = ctrl[b].scale;
+        insts[b].bscale = s;
+        if (exponent_uses_base) insts[b].cscale = s;
+    }
+    ctrl[b].scale = insts[b].bscale;
+}
+
+// ---------------------------------------------------------------------------
+// a10: outputs.  Standard-form potentials at eps = eta/K:
+//   alpha = (F + [Ahat])/K, beta = (G + [Bhat])/K  ([.] materialised mode),
+// gauge <a,alpha> = <b,beta>; then one pass for X^K, <C,X>, entropy and the
+// marginals.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_potentials(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                     double K) {
+    const int b = blockIdx.x;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = I.m + I.n;
+    const bool mat = kp.shift_mode != 0;
+    __shared__ double sh[16];
+    double sa = 0.0, sb = 0.0;
+    for (int k = threadIdx.x; k < N; k += 1024) {
+        if (k < m) {
+            const double v = (I.F[k] + (mat ? I.Ah[k] : 0.0)) / K;
+            I.alpha[k] = v;
+            sa += I.a[k] * v;
+        } else {
+            const double v = (I.G[k - m] + (mat ? I.Bh[k - m] : 0.0)) / K;
+            I.beta[k - m] = v;
+            sb += I.b[k - m] * v;
+        }
+    }
+    sa = block_sum<1024>(sa, sh);
+    sb = block_sum<1024>(sb, sh);
+    const double tg = 0.5 * (sb - sa);
+    double du = 0.0;
+    for (int k = threadIdx.x; k < N; k += 1024) {
+        if (k < m) {
+            const double v = I.alpha[k] + tg;
+            I.alpha[k] = v;
+            du += I.a[k] * v;
+        } else {
+            const double v = I.beta[k - m] - tg;
+            I.beta[k - m] = v;
+            du += I.b[k - m] * v;
+        }
+    }
+    du = block_sum<1024>(du, sh);
+    if (threadIdx.x == 0) ctrl[b].dual = du;
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                               double K, int write_x) {
+    const int b = blockIdx.y;
+    const DevInst& I = insts[b];
+    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
+    if (rb >= I.nrb) return;
+    const int m = I.m, n = I.n;
+    const int i0 = rb * I.R, rows = min(I.R, m - i0);
+    __shared__ double red[TILE_RMAX][TILE_C + 1];
+    __shared__ double sh[4];
+    const int j = cb * TILE_C + threadIdx.x;
+    const bool valid = j < n;
+    const double ieps = K * kp.inv_eta;
+    const Src base(I, true);
+    const double bj = valid ? I.beta[j] : 0.0;
+    double colacc = 0.0, cst = 0.0, ent = 0.0;
+    for (int r = 0; r < rows; ++r) {
+        const int i = i0 + r;
+        double xv = 0.0;
+        if (valid) {
+            const double c = base.at(i, j);
+            const double lx = (I.alpha[i] + bj - c) * ieps;
+            xv = exp(lx);
+            cst += c * xv;
+            if (xv > 0.0) ent -= xv * lx;
+            if (write_x && I.X) I.X[(long)i * n + j] = xv;
+        }
+        colacc += xv;
+        red[r][threadIdx.x] = xv;
+    }
+    if (valid) I.part[(long)rb * n + j] = colacc;
+    __syncthreads();
+    {
+        const int r = threadIdx.x >> 4, s = threadIdx.x & 15;
+        double v = 0.0;
+        if (r < rows)
+            for (int k = 0; k < 16; ++k) v += red[r][s * 16 + k];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (r < rows && s == 0) I.part2[(long)cb * m + i0 + r] = v;
+    }
+    cst = block_sum<256>(cst, sh);
+    ent = block_sum<256>(ent, sh);
+    if (threadIdx.x == 0) {
+        I.blk[(long)blockIdx.x * 2] = cst;
+        I.blk[(long)blockIdx.x * 2 + 1] = ent;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_final_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
+    const int b = blockIdx.y;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n, N = m + n;
+    const int nb = (N + 255) / 256;
+    if ((int)blockIdx.x >= nb) return;
+    __shared__ double sh[4];
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    double dev = 0.0;
+    if (k < m) {
+        double s = 0.0;
+        for (int cb = 0; cb < I.ncb; ++cb) s += I.part2[(long)cb * m + k];
+        dev = fabs(s - I.a[k]);
+    } else if (k < N) {
+        const int j = k - m;
+        double s = 0.0;
+        for (int rb = 0; rb < I.nrb; ++rb) s += I.part[(long)rb * n + j];
+        dev = fabs(s - I.b[j]);
+    }
+    const double bs = block_sum<256>(dev, sh);
+    if (threadIdx.x == 0) I.blk2[blockIdx.x] = bs;
+    if (!last_block(&ctrl[b].ticket, nb)) return;
+    const double res = block_sum_array<256>(I.blk2, nb, sh);
+    const int nblk = I.nrb * I.ncb;
+    double c = 0.0, e = 0.0;
+    for (int q = threadIdx.x; q < nblk; q += 256) {
+        c += I.blk[(long)q * 2];
+        e += I.blk[(long)q * 2 + 1];
+    }
+    c = block_sum<256>(c, sh);
+    e = block_sum<256>(e, sh);
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        S.resid = res;
+        S.cost = c;
+        S.entropy = e;
+        if (!isfinite(c) || !isfinite(res)) S.nonfinite = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline dim3 g2(int x, int y) { return dim3((unsigned)(x > 0 ? x : 1), (unsigned)y); }
+
+#define PINS_SRC_DISPATCH(src, KERNEL_TMPL, ...)             \
+    do {                                                      \
+        if ((src) == SRC_GRID)                                \
+            KERNEL_TMPL(GridSrc, ##__VA_ARGS__);              \
+        else                                                  \
+            KERNEL_TMPL(DenseSrc, ##__VA_ARGS__);             \
+    } while (0)
+
+void launch_row_lse(const LaunchCtx& L, int src, bool f32, int mask) {
+    const dim3 g = g2((L.max_m + 3) / 4, L.count);
+#define K_(S, T) hipLaunchKernelGGL((k_row_lse<S, T>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, mask)
+    if (f32) {
+        PINS_SRC_DISPATCH(src, K_, float);
+    } else {
+        PINS_SRC_DISPATCH(src, K_, double);
+    }
+#undef K_
+}
+
+void launch_col_lse(const LaunchCtx& L, int src, bool f32, int mask) {
+    const dim3 g = g2(L.max_tiles, L.count);
+#define K_(S, T) hipLaunchKernelGGL((k_col_lse<S, T>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, mask)
+    if (f32) {
+        PINS_SRC_DISPATCH(src, K_, float);
+    } else {
+        PINS_SRC_DISPATCH(src, K_, double);
+    }
+#undef K_
+}
+
+void launch_col_merge(const LaunchCtx& L, int mask) {
+    hipLaunchKernelGGL(k_col_merge, g2((L.max_n + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
+                       L.kp, mask);
+}
+
+void launch_grad(const LaunchCtx& L, int src) {
+    const dim3 g = g2(L.max_tiles, L.count);
+#define K_(S) hipLaunchKernelGGL((k_grad<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+    PINS_SRC_DISPATCH(src, K_);
+#undef K_
+}
+
+void launch_grad_merge(const LaunchCtx& L) {
+    hipLaunchKernelGGL(k_grad_merge, g2((L.max_mn + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
+                       L.kp);
+}
+
+void launch_fill(const LaunchCtx& L, int src) {
+    const dim3 g = g2((L.max_m + 3) / 4, L.count);
+#define K_(S) hipLaunchKernelGGL((k_fill<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+    PINS_SRC_DISPATCH(src, K_);
+#undef K_
+}
+
+void launch_csc(const LaunchCtx& L) {
+    hipLaunchKernelGGL(k_csc, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl);
+}
+
+void launch_pcg(const LaunchCtx& L) {
+    hipLaunchKernelGGL(k_pcg, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+}
+
+void launch_ls(const LaunchCtx& L, int src, bool first) {
+    const dim3 g = g2(L.max_tiles, L.count);
+#define K_(S, NT) hipLaunchKernelGGL((k_ls<S, NT>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+    if (first) {
+        PINS_SRC_DISPATCH(src, K_, 1);
+    } else {
+        PINS_SRC_DISPATCH(src, K_, LS_T);
+    }
+#undef K_
+}
+
+void launch_update(const LaunchCtx& L) {
+    hipLaunchKernelGGL(k_update, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl);
+}
+
+void launch_shift(const LaunchCtx& L, int base_src) {
+    const bool mat = L.kp.shift_mode != 0;
+    if (mat) {
+        const dim3 g = g2(1024, L.count);
+#define K_(S) hipLaunchKernelGGL((k_shift_dense<S>), g, dim3(256), 0, L.stream, L.insts)
+        PINS_SRC_DISPATCH(base_src, K_);
+#undef K_
+    }
+    hipLaunchKernelGGL(k_shift_vec, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, mat ? 1 : 0,
+                       L.kp.T1 > 0 ? (int)PH_WARM : (int)PH_NEWTON);
+}
+
+void launch_init(const LaunchCtx& L, int base_src) {
+    hipLaunchKernelGGL(k_init, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+    if (L.kp.shift_mode != 0) {
+        const dim3 g = g2(1024, L.count);
+#define K_(S) hipLaunchKernelGGL((k_init_ck<S>), g, dim3(256), 0, L.stream, L.insts, L.kp)
+        PINS_SRC_DISPATCH(base_src, K_);
+#undef K_
+    }
+}
+
+void launch_points_cost(hipStream_t st, const double* x, const double* y, int m, int n, int d, double* C) {
+    const long mn = (long)m * n;
+    int blocks = (int)((mn + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_points_cost, dim3(blocks), dim3(256), 0, st, x, y, m, n, d, C);
+}
+
+void launch_cost_max(const LaunchCtx& L, double* scratch, int nblk, int exponent_uses_base) {
+    hipLaunchKernelGGL(k_cost_max, dim3(nblk, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, scratch);
+    hipLaunchKernelGGL(k_set_scale, dim3((L.count + 63) / 64), dim3(64), 0, L.stream, L.insts_mut, L.ctrl, L.count,
+                       exponent_uses_base);
+}
+
+void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x) {
+    hipLaunchKernelGGL(k_potentials, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, K);
+    const dim3 g = g2(L.max_tiles, L.count);
+#define K_(S) hipLaunchKernelGGL((k_final<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, K, write_x ? 1 : 0)
+    PINS_SRC_DISPATCH(base_src, K_);
+#undef K_
+    hipLaunchKernelGGL(k_final_merge, g2((L.max_mn + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl);
+}
+
+}  // namespace pins

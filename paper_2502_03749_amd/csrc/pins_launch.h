@@ -1,0 +1,38 @@
+// pins_launch.h -- host-side launch wrappers of the HIP kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pins_internal.h"
+
+namespace pins {
+
+// Everything a launch needs to cover one batch.
+struct LaunchCtx {
+    hipStream_t stream;
+    const DevInst* insts;  // device array [count]
+    DevInst* insts_mut;    // same array, for the setup kernels that fill scales
+    Ctrl* ctrl;            // device array [count]
+    KP kp;
+    int count;
+    int max_m, max_n, max_mn;  // maxima over the batch (max_mn = max m+n)
+    int max_tiles;             // max nrb*ncb
+};
+
+void launch_row_lse(const LaunchCtx& L, int src, bool f32, int mask);
+void launch_col_lse(const LaunchCtx& L, int src, bool f32, int mask);
+void launch_col_merge(const LaunchCtx& L, int mask);
+void launch_grad(const LaunchCtx& L, int src);
+void launch_grad_merge(const LaunchCtx& L);
+void launch_fill(const LaunchCtx& L, int src);
+void launch_csc(const LaunchCtx& L);
+void launch_pcg(const LaunchCtx& L);
+void launch_ls(const LaunchCtx& L, int src, bool first);
+void launch_update(const LaunchCtx& L);
+void launch_shift(const LaunchCtx& L, int base_src);
+void launch_init(const LaunchCtx& L, int base_src);
+void launch_points_cost(hipStream_t st, const double* x, const double* y, int m, int n, int d, double* C);
+void launch_cost_max(const LaunchCtx& L, double* scratch, int nblk, int exponent_uses_base);
+void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x);
+
+}  // namespace pins

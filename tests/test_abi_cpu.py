@@ -1,0 +1,68 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+its struct layouts match the ctypes mirror, and the host-only calls behave.
+No compute call is made (there is no GPU here)."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+import paper_2502_03749_amd as P
+from paper_2502_03749_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = P.declared_functions()
+    assert "pins_solve" in names and "pins_solve_batch_device" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert L.pins_abi_version() == 1
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pins.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(pins_params), sizeof(pins_problem),'
+                   ' sizeof(pins_result), offsetof(pins_result, kern_ms), offsetof(pins_problem, a));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert got == [ctypes.sizeof(B.Params), ctypes.sizeof(B.Problem), ctypes.sizeof(B.Result),
+                   B.Result.kern_ms.offset, B.Problem.a.offset]
+
+
+def test_default_params_are_the_papers():
+    p = P.params()
+    assert (p.max_outer, p.max_sinkhorn, p.max_newton) == (250, 100, 50)
+    assert (p.ls_beta, p.ls_c1, p.cg_rtol, p.inner_tol) == (0.5, 1e-4, 1e-6, 1e-9)
+
+
+def test_workspace_bytes_scales_with_size():
+    prm = P.params()
+    small = P.workspace_bytes([dict(kind=P.COST_DENSE, m=100, n=100)], prm)
+    big = P.workspace_bytes([dict(kind=P.COST_DENSE, m=1000, n=1000)], prm)
+    assert 0 < small < big
+    two = P.workspace_bytes([dict(kind=P.COST_DENSE, m=100, n=100)] * 2, prm)
+    assert two > small
+    mat = P.workspace_bytes([dict(kind=P.COST_DENSE, m=1000, n=1000)], P.params(shift_mode=P.SHIFT_MATERIALIZED))
+    assert mat >= big + 1000 * 1000 * 8
+
+
+def test_workspace_bytes_rejects_bad_input():
+    with pytest.raises(B.PinsError):
+        P.workspace_bytes([dict(kind=P.COST_GRID, m=10, n=10, grid_s=3)], P.params())
+    with pytest.raises(B.PinsError):
+        P.workspace_bytes([dict(kind=P.COST_DENSE, m=10, n=10)], P.params(eta=-1.0))
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(B.PinsError) as e:
+        P.Context(0)
+    assert e.value.code == B.PINS_EDEVICE

@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar (FP64 path): relative cost difference <= 1e-9, GPU marginal residual
+<= 1e-10, plan L1 distance <= 1e-9, gauge-fixed potentials within 1e-8
+(costs are normalised to [0, 1]).  Mixed path: relative cost difference
+<= 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2502_03749_amd as P  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _t(v):
+    return torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=DEV)
+
+
+def gpu_solve(ctx, prob, prm, want_plan=True):
+    """Device-API solve of a host problem dict (kind, a, b, C | x,y | grid_s)."""
+    m, n = len(prob["a"]), len(prob["b"])
+    default_scale = 1.0 if prob["kind"] == P.COST_DENSE else 0.0  # dense C is used as given
+    dp = dict(kind=prob["kind"], m=m, n=n, a=_t(prob["a"]), b=_t(prob["b"]),
+              cost_scale=prob.get("cost_scale", default_scale))
+    if "C" in prob:
+        dp["C"] = _t(prob["C"])
+    if "x" in prob:
+        dp["x"], dp["y"], dp["d"] = _t(prob["x"]), _t(prob["y"]), prob["x"].shape[1]
+    if "grid_s" in prob:
+        dp["grid_s"] = prob["grid_s"]
+    out = dict(alpha=torch.empty(m, dtype=torch.float64, device=DEV),
+               beta=torch.empty(n, dtype=torch.float64, device=DEV),
+               X=torch.empty(m, n, dtype=torch.float64, device=DEV) if want_plan else None)
+    rc, r = ctx.solve_device(dp, prm, out, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    r["rc"] = rc
+    r["alpha"] = out["alpha"].cpu().numpy()
+    r["beta"] = out["beta"].cpu().numpy()
+    r["X"] = out["X"].cpu().numpy() if want_plan else None
+    return r
+
+
+def check_parity(g, o, a, b, cost_tol=1e-9, plan_tol=1e-9, resid_tol=1e-10):
+    rel = abs(g["cost"] - o["cost"]) / max(abs(o["cost"]), 1e-300)
+    assert g["rc"] == 0, g
+    assert rel <= cost_tol, (g["cost"], o["cost"], rel)
+    assert g["resid"] <= resid_tol, g["resid"]
+    if g["X"] is not None and o["X"] is not None:
+        l1 = np.abs(g["X"] - o["X"]).sum()
+        assert l1 <= plan_tol, l1
+        # the plan is the exponential of the potentials (standard form)
+        Xp = np.exp((g["alpha"][:, None] + g["beta"][None, :] - g["_C"]) / g["eps"])
+        assert np.abs(Xp - g["X"]).sum() <= 1e-10
+    # gauge <a,alpha> = <b,beta>; gauge-fixed potentials agree (costs are O(1))
+    assert abs(a @ g["alpha"] - b @ g["beta"]) <= 1e-12
+    assert np.abs(g["alpha"] - o["alpha"]).max() <= 1e-8
+    assert np.abs(g["beta"] - o["beta"]).max() <= 1e-8
+    return rel
+
+
+def _rand(m, n, seed):
+    g = np.random.default_rng(seed)
+    C = g.uniform(0, 1, (m, n))
+    a = g.uniform(0.2, 1.0, m)
+    b = g.uniform(0.2, 1.0, n)
+    return C, a / a.sum(), b / b.sum()
+
+
+@pytest.mark.parametrize("m,n,eta,K", [(1, 1, 0.1, 2), (1, 5, 0.1, 3), (6, 1, 0.1, 3), (2, 2, 0.4, 3),
+                                       (7, 5, 0.05, 6), (37, 53, 0.03, 8), (100, 100, 0.01, 10),
+                                       (300, 17, 0.02, 5), (17, 600, 0.02, 5)])
+def test_dense_parity(ctx, m, n, eta, K):
+    print("case dense m=%d n=%d eta=%g K=%d" % (m, n, eta, K), flush=True)
+    C, a, b = _rand(m, n, 1000 + m * 7 + n)
+    prm = P.params(eta=eta, max_outer=K)
+    g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), prm)
+    g["_C"] = C
+    o = oracle.pins(C, a, b, eta=eta, K=K)
+    check_parity(g, o, a, b)
+
+
+def test_points_plane_instance_reaches_lp(ctx):
+    """100x100 plane instance, K = 2000: parity with the oracle and <= 1e-8 vs the LP."""
+    from oracle import lp
+
+    inst = W.points_instance(0)
+    C = oracle.cost_points(inst["x"], inst["y"])
+    K = 2000
+    print("case points 100x100 K=%d" % K, flush=True)
+    prm = P.params(eta=1e-2, max_outer=K)
+    g = gpu_solve(ctx, dict(kind=P.COST_POINTS, x=inst["x"], y=inst["y"], a=inst["a"], b=inst["b"]), prm)
+    g["_C"] = C
+    o = oracle.pins(C, inst["a"], inst["b"], eta=1e-2, K=K)
+    check_parity(g, o, inst["a"], inst["b"])
+    ot, _ = lp.lp_highs(C, inst["a"], inst["b"])
+    assert abs(g["cost"] - ot) / ot <= 1e-8
+
+
+@pytest.mark.parametrize("s,K", [(5, 6), (12, 10)])
+def test_grid_streamed_parity(ctx, s, K):
+    print("case grid s=%d K=%d" % (s, K), flush=True)
+    pr = W.blob_pair(3, s=s)
+    C = oracle.cost_grid(s)
+    prm = P.params(eta=0.1, max_outer=K)
+    g = gpu_solve(ctx, dict(kind=P.COST_GRID, grid_s=s, a=pr["a"], b=pr["b"]), prm)
+    g["_C"] = C
+    o = oracle.pins(C, pr["a"], pr["b"], eta=0.1, K=K)
+    check_parity(g, o, pr["a"], pr["b"])
+
+
+@pytest.mark.parametrize("kind", ["dense", "grid"])
+def test_materialised_shift_parity(ctx, kind):
+    print("case materialised %s" % kind, flush=True)
+    if kind == "dense":
+        C, a, b = _rand(40, 29, 77)
+        prob = dict(kind=P.COST_DENSE, C=C, a=a, b=b)
+        eta = 0.02
+    else:
+        pr = W.blob_pair(5, s=9)
+        C, a, b = oracle.cost_grid(9), pr["a"], pr["b"]
+        prob = dict(kind=P.COST_GRID, grid_s=9, a=a, b=b)
+        eta = 0.1
+    K = 12
+    prm = P.params(eta=eta, max_outer=K, shift_mode=P.SHIFT_MATERIALIZED)
+    g = gpu_solve(ctx, prob, prm)
+    g["_C"] = C
+    o = oracle.pins(C, a, b, eta=eta, K=K)
+    check_parity(g, o, a, b)
+
+
+@pytest.mark.parametrize("kind", ["dense", "grid"])
+def test_mixed_precision_parity(ctx, kind):
+    print("case mixed %s" % kind, flush=True)
+    if kind == "dense":
+        C, a, b = _rand(64, 48, 91)
+        prob = dict(kind=P.COST_DENSE, C=C, a=a, b=b)
+        eta = 0.02
+    else:
+        pr = W.blob_pair(7, s=14)
+        C, a, b = oracle.cost_grid(14), pr["a"], pr["b"]
+        prob = dict(kind=P.COST_GRID, grid_s=14, a=a, b=b)
+        eta = 0.1
+    K = 15
+    prm = P.params(eta=eta, max_outer=K, precision=P.MIXED)
+    g = gpu_solve(ctx, prob, prm)
+    g["_C"] = C
+    o = oracle.pins(C, a, b, eta=eta, K=K)
+    rel = abs(g["cost"] - o["cost"]) / o["cost"]
+    assert g["rc"] == 0 and rel <= 1e-6 and g["resid"] <= 1e-10
+
+
+def test_batch_equals_alone(ctx):
+    """Uneven batch: every instance's result is bitwise the one it gets alone."""
+    print("case batch", flush=True)
+    shapes = [(7, 5), (64, 33), (130, 257), (1, 9), (300, 300)]
+    probs, outs, hosts = [], [], []
+    prm = P.params(eta=0.03, max_outer=6)
+    for q, (m, n) in enumerate(shapes):
+        C, a, b = _rand(m, n, 500 + q)
+        hosts.append((C, a, b))
+        probs.append(dict(kind=P.COST_DENSE, m=m, n=n, C=_t(C), a=_t(a), b=_t(b), cost_scale=1.0))
+        outs.append(dict(alpha=torch.empty(m, dtype=torch.float64, device=DEV),
+                         beta=torch.empty(n, dtype=torch.float64, device=DEV)))
+    rc, rs = ctx.solve_batch_device(probs, prm, outs, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for q, (C, a, b) in enumerate(hosts):
+        g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), prm, want_plan=False)
+        assert rs[q]["cost"] == g["cost"], q
+        assert np.array_equal(outs[q]["alpha"].cpu().numpy(), g["alpha"]), q
+        assert np.array_equal(outs[q]["beta"].cpu().numpy(), g["beta"]), q
+        assert rs[q]["newton_iters"] == g["newton_iters"] and rs[q]["cg_iters"] == g["cg_iters"]
+
+
+def test_deterministic(ctx):
+    print("case determinism", flush=True)
+    C, a, b = _rand(90, 70, 3)
+    prm = P.params(eta=0.02, max_outer=8)
+    g1 = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), prm)
+    g2 = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), prm)
+    assert g1["cost"] == g2["cost"]
+    assert np.array_equal(g1["X"], g2["X"]) and np.array_equal(g1["alpha"], g2["alpha"])
+
+
+def test_host_api_matches_device_api(ctx):
+    print("case host api", flush=True)
+    C, a, b = _rand(33, 44, 8)
+    prm = P.params(eta=0.03, max_outer=5)
+    h = ctx.solve(P.COST_DENSE, a, b, prm, C=C, want_plan=True, cost_scale=1.0)
+    g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), prm)
+    assert h["cost"] == g["cost"]
+    assert np.array_equal(h["X"], g["X"]) and np.array_equal(h["alpha"], g["alpha"])
+
+
+def test_invalid_inputs_rejected(ctx):
+    print("case invalid", flush=True)
+    C, a, b = _rand(5, 4, 1)
+    prm = P.params(eta=0.1, max_outer=2)
+    bad_a = a.copy()
+    bad_a[0] += 1e-6
+    with pytest.raises(P.PinsError) as e:
+        ctx.solve(P.COST_DENSE, bad_a, b, prm, C=C)
+    assert e.value.code == -1
+    neg = a.copy()
+    neg[1] = -neg[1]
+    with pytest.raises(P.PinsError):
+        ctx.solve(P.COST_DENSE, neg, b, prm, C=C)
+    with pytest.raises(P.PinsError):
+        ctx.solve(P.COST_DENSE, a, b, P.params(eta=0.0), C=C)
+    Cn = C.copy()
+    Cn[2, 3] = np.nan
+    with pytest.raises(P.PinsError) as e:
+        ctx.solve(P.COST_DENSE, a, b, prm, C=Cn)
+    assert e.value.code == -1
+    # the context stays usable
+    r = ctx.solve(P.COST_DENSE, a, b, prm, C=C)
+    assert r["rc"] == 0
+
+
+def test_caps_report_not_converged(ctx):
+    print("case caps", flush=True)
+    C, a, b = _rand(30, 30, 12)
+    r = ctx.solve(P.COST_DENSE, a, b, P.params(eta=0.01, max_outer=3, max_newton=0, max_sinkhorn=1), C=C)
+    assert r["rc"] == 1 and (r["flags"] & 1)
+    assert np.isfinite(r["alpha"]).all() and np.isfinite(r["cost"])
