@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the PINS hot path on one MI355X.
+
+Workload (image-histogram family): 64 independent pairs of 28x28 histograms
+(m = n = 784), each a mixture of 1-3 Gaussian blobs plus a 1e-6 floor,
+normalised; cost = squared grid distance / max (streamed from the grid, never
+stored); eta = 0.1; K = 250 EPPA outer iterations (the paper's cap), T1 = 100,
+T2 = 50, Armijo (0.5, 1e-4), CG relative residual 1e-6, marginal tolerance
+1e-9 (last subproblem 1e-12).
+
+One step = one batched call of the C ABI (pins_solve_batch_device) that
+solves all 64 pairs; value = solves per second over the timed steps.  Inputs
+are resident in HBM before the timed region starts.
+
+The JSON line also carries:
+  roofline     -- the dominant kernel class, its algorithmic work per launch
+                  over its average launch time (HIP events on the solver's
+                  stream, recorded by the library in the timed region);
+  cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same
+                  workload (rank 0, one thread);
+  accuracy     -- relative cost difference of the sampled instance against
+                  the oracle at the same K (bar: 1e-6);
+  variants     -- plain single-instance throughput and the other precision.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks and derived ALU peaks (256 CUs, 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CU * 4 SIMD * 16 lanes * 2 (FMA) * 2.4 GHz
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+# Algorithmic FP64 flops per matrix entry of each dense pass, counting an
+# exponential (or expm1) as EXP_FLOPS: range reduction (2), a degree-11
+# Horner polynomial (22), reconstruction (2); see the design notes.
+EXP_FLOPS = 26.0
+FLOPS_PER_ENTRY = {
+    # exponent (3) + exp + scale of the grid cost (1) + row/col accumulation (2) + level test (3)
+    "grad": 9.0 + EXP_FLOPS,
+    # exponent (3) + exp + expm1 for one trial + product/accumulate (3)
+    "ls": 7.0 + 2.0 * EXP_FLOPS,
+    # exponent (3) + online max/rescale/accumulate (3) + exp
+    "row_lse": 7.0 + EXP_FLOPS,
+    "col_lse": 7.0 + EXP_FLOPS,
+    # exponent (3) + level test (3); exp only on kept entries (not counted)
+    "fill": 7.0,
+    "csc": 7.0,
+    # exponent (3) + exp + cost/entropy/marginal accumulations (6)
+    "final": 10.0 + EXP_FLOPS,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--pairs", type=int, default=64)
+    ap.add_argument("--K", type=int, default=250)
+    ap.add_argument("--eta", type=float, default=0.1)
+    ap.add_argument("--side", type=int, default=28)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="do not record per-launch HIP events")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the PINS hot path runs independent instances per GPU and "
+              "this build has no multi-GPU path (see the design notes for how it would shard); "
+              "run with --gpus 1.", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_03749_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    s = args.side
+    n = s * s
+    pairs = [W.blob_pair(i, s=s) for i in range(args.pairs)]
+    t = lambda v: torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev)
+    probs = [dict(kind=P.COST_GRID, m=n, n=n, grid_s=s, a=t(p["a"]), b=t(p["b"])) for p in pairs]
+    outs = [dict(alpha=torch.empty(n, dtype=torch.float64, device=dev),
+                 beta=torch.empty(n, dtype=torch.float64, device=dev)) for _ in pairs]
+    prec = P.MIXED if args.precision == "mixed" else P.FP64
+    ctx = P.Context(0)
+    stream = torch.cuda.current_stream()
+    st = stream.cuda_stream
+
+    def step(prm, probs_=probs, outs_=outs):
+        rc, rs = ctx.solve_batch_device(probs_, prm, outs_, stream=st)
+        if rc < 0 or any(r["status"] != 0 for r in rs):
+            raise RuntimeError("solve failed: rc=%d statuses=%s" % (rc, [r["status"] for r in rs]))
+        return rs
+
+    prm = P.params(eta=args.eta, max_outer=args.K, precision=prec, profile=0 if args.no_profile else 1)
+    for _ in range(args.warmup):
+        step(prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        results.append(step(prm))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solves = args.pairs * args.steps
+    value = solves / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # roofline of the dominant kernel class over the timed region
+    kms, kwork, kcalls = {}, {}, {}
+    for rs in results:
+        r0 = rs[0]  # kernel times are per batch (identical in every result of a batch)
+        for k, v in r0["kern_ms"].items():
+            kms[k] = kms.get(k, 0.0) + v
+            kcalls[k] = kcalls.get(k, 0) + r0["kern_calls"][k]
+        for r in rs:
+            for k, v in r["kern_work"].items():
+                kwork[k] = kwork.get(k, 0.0) + v
+    roofline = None
+    if kms and sum(kms.values()) > 0:
+        dom = max(kms, key=kms.get)
+        calls = max(kcalls.get(dom, 0), 1)
+        avg_ms = kms[dom] / calls
+        fpe = FLOPS_PER_ENTRY.get(dom)
+        if fpe is not None and kwork.get(dom, 0) > 0:
+            flops_per_launch = kwork[dom] * fpe / calls
+            achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+            roofline = dict(kernel=dom, bound="alu", achieved=achieved, peak=PEAK_FP64_VECTOR_TFLOPS,
+                            unit="TFLOP/s", frac=achieved / PEAK_FP64_VECTOR_TFLOPS,
+                            traffic=_traffic(dom), avg_launch_us=1e3 * avg_ms, launches=calls,
+                            entries_per_launch=kwork[dom] / calls, flops_per_entry=fpe)
+        else:
+            roofline = dict(kernel=dom, bound="latency", achieved=None, peak=None, unit=None, frac=None,
+                            traffic=None, avg_launch_us=1e3 * avg_ms, launches=calls)
+        roofline["kernel_ms_share"] = {k: round(v / sum(kms.values()), 4) for k, v in
+                                       sorted(kms.items(), key=lambda kv: -kv[1]) if v > 0}
+
+    line = dict(metric="OT solves/sec at rel. cost error <=1e-6 (plain vs batched/served); p50/p99 latency",
+                value=value, unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32+f64" if prec == P.MIXED else "f64", data="synthetic",
+                config=dict(workload="image-histogram pairs, 28x28 grid (m=n=784), squared grid distance/max "
+                                     "streamed, eta=0.1, K=250, batched (one call per step)",
+                            pairs=args.pairs, m=n, n=n, eta=args.eta, K=args.K, precision=args.precision,
+                            mode="batched"),
+                roofline=roofline)
+
+    last = results[-1]
+    line["iterations"] = dict(sinkhorn=[r["sinkhorn_iters"] for r in last][:4],
+                              newton=[r["newton_iters"] for r in last][:4],
+                              cg=[r["cg_iters"] for r in last][:4])
+
+    if not args.no_variants:
+        variants = {}
+        other = P.FP64 if prec == P.MIXED else P.MIXED
+        prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step(prm2)
+        torch.cuda.synchronize()
+        variants["batched_" + ("fp64" if other == P.FP64 else "mixed") + "_solves_per_s"] = \
+            args.pairs / (time.perf_counter() - t1)
+        prm1 = P.params(eta=args.eta, max_outer=args.K, precision=prec)
+        nplain = min(4, args.pairs)
+        lat = []
+        for q in range(nplain):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            step(prm1, [probs[q]], [outs[q]])
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t1)
+        variants["plain_single_instance_solves_per_s"] = nplain / sum(lat)
+        variants["plain_single_instance_ms"] = [round(1e3 * v, 2) for v in lat]
+        line["variants"] = variants
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        C = oracle.cost_grid(s)
+        p0 = pairs[0]
+        t1 = time.perf_counter()
+        ref = oracle.pins(C, p0["a"], p0["b"], want_plan=False, eta=args.eta, K=args.K)
+        dt = time.perf_counter() - t1
+        line["cpu_baseline"] = dict(value=1.0 / dt, unit="solves/s", cores=1, kind="oracle",
+                                    sample="1 of the %d pairs (pair 0), full solve at the same K=%d, "
+                                           "single-threaded C oracle, %.1f s" % (args.pairs, args.K, dt))
+        g0 = last[0]
+        line["accuracy"] = dict(rel_cost_diff_vs_oracle=abs(g0["cost"] - ref["cost"]) / ref["cost"],
+                                gpu_resid=g0["resid"], oracle_resid=ref["resid"], bar=1e-6)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def _traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they match the current kernels."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2502_03749_amd", "csrc", "pins_kernels.hip"), "rb").read()
+        if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return rec.get("per_launch_bytes", {}).get(kernel)
+    except Exception:
+        return None
+
+
+if __name__ == "__main__":
+    main()

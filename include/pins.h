@@ -136,6 +136,8 @@ typedef struct {
     int32_t outer_iters, sinkhorn_iters, newton_iters, cg_iters, fallbacks, nnz_last;
     double kern_ms[PINS_NKERN];   /* summed kernel time per kernel class (profile != 0) */
     int32_t kern_calls[PINS_NKERN];
+    double kern_work[PINS_NKERN]; /* matrix entries visited per kernel class by this instance
+                                     (dense passes only; always filled) */
 } pins_result;
 
 /* Kernel classes reported in kern_ms / kern_calls. */
@@ -145,7 +147,7 @@ typedef struct {
 #define PINS_K_GRAD 3      /* Newton pass: Xt row/col sums, Sparsify histogram */
 #define PINS_K_GRAD_MERGE 4 /* gradient merge, convergence, Sparsify level, CSR row pointers */
 #define PINS_K_FILL 5      /* CSR fill */
-#define PINS_K_CSC 6       /* CSC transpose */
+#define PINS_K_CSC 6       /* CSC fill (column order) */
 #define PINS_K_PCG 7       /* preconditioned CG */
 #define PINS_K_LS 8        /* Armijo trial pass */
 #define PINS_K_UPDATE 9    /* dual update */

@@ -58,13 +58,14 @@ class Result(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("sinkhorn_iters", ctypes.c_int32),
                 ("newton_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
                 ("nnz_last", ctypes.c_int32), ("kern_ms", ctypes.c_double * NKERN),
-                ("kern_calls", ctypes.c_int32 * NKERN)]
+                ("kern_calls", ctypes.c_int32 * NKERN), ("kern_work", ctypes.c_double * NKERN)]
 
     def scalars(self) -> dict:
         out = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("alpha", "beta", "X", "kern_ms",
-                                                                            "kern_calls")}
+                                                                            "kern_calls", "kern_work")}
         out["kern_ms"] = {KERNEL_NAMES[i]: self.kern_ms[i] for i in range(len(KERNEL_NAMES))}
         out["kern_calls"] = {KERNEL_NAMES[i]: self.kern_calls[i] for i in range(len(KERNEL_NAMES))}
+        out["kern_work"] = {KERNEL_NAMES[i]: self.kern_work[i] for i in range(len(KERNEL_NAMES))}
         return out
 
 

@@ -69,8 +69,8 @@ struct Carver {
 // Offsets of one instance's device arrays inside the workspace.
 struct InstPlan {
     int m, n, d, R, nrb, ncb, cap;
-    size_t loga, logb, F, G, Ah, Bh, rc, dir, cgw, part, part2, blk, blk2, hist, rowptr, col, val, colptr, rowT,
-        valT, cfill, Ck, Cpts;
+    size_t loga, logb, F, G, Ah, Bh, rc, dir, cgw, part, part2, blk, blk2, hist, histc, rowptr, col, val, colptr,
+        rowT, valT, Ck, Cpts;
     size_t C, x, y, a, b, alpha, beta, X;  // host-API staging
 };
 
@@ -107,13 +107,13 @@ InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, 
     q.blk = cv.take((size_t)nblk * LS_T * D);
     q.blk2 = cv.take((size_t)nblk * D);
     q.hist = cv.take((size_t)m * NLEV * I4);
+    q.histc = cv.take((size_t)n * NLEV * I4);
     q.rowptr = cv.take((m + 1) * I4);
     q.col = cv.take((size_t)q.cap * I4);
     q.val = cv.take((size_t)q.cap * D);
     q.colptr = cv.take((n + 1) * I4);
     q.rowT = cv.take((size_t)q.cap * I4);
     q.valT = cv.take((size_t)q.cap * D);
-    q.cfill = cv.take(n * I4);
     q.Ck = (p.shift_mode == PINS_SHIFT_MATERIALIZED) ? cv.take((size_t)m * n * D) : NONE;
     q.Cpts = (P.kind == PINS_COST_POINTS) ? cv.take((size_t)m * n * D) : NONE;
     q.C = q.x = q.y = q.a = q.b = q.alpha = q.beta = q.X = NONE;
@@ -384,13 +384,13 @@ int solve_impl(pins_ctx* ctx, const pins_problem* probs, int count, const pins_p
         I.blk = Dp(L.blk);
         I.blk2 = Dp(L.blk2);
         I.hist = Ip(L.hist);
+        I.histc = Ip(L.histc);
         I.rowptr = Ip(L.rowptr);
         I.col = Ip(L.col);
         I.val = Dp(L.val);
         I.colptr = Ip(L.colptr);
         I.rowT = Ip(L.rowT);
         I.valT = Dp(L.valT);
-        I.cfill = Ip(L.cfill);
         if (host_api) {
             I.alpha = Dp(L.alpha);
             I.beta = Dp(L.beta);
@@ -481,18 +481,34 @@ int solve_impl(pins_ctx* ctx, const pins_problem* probs, int count, const pins_p
             run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
             run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L); });
             run(ctx, st, PINS_K_FILL, [&] { launch_fill(L, src); });
-            run(ctx, st, PINS_K_CSC, [&] { launch_csc(L); });
+            run(ctx, st, PINS_K_CSC, [&] { launch_fill_csc(L, src); });
             run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
             run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
-            for (int h = 1; h < p.ls_max; h += LS_T) run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, false); });
-            run(ctx, st, PINS_K_UPDATE, [&] { launch_update(L); });
-            run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, false, M_FB); });
-            run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, false, M_FB); });
-            run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_FB); });
+            // one readback per Newton step: who is still iterating, who needs more
+            // Armijo trials, who will take the Sinkhorn fallback
             const Ctrl* h = readback(ctx, st, d_ctrl, count);
-            bool any = false;
-            for (int q = 0; q < count; ++q) any |= (h[q].phase == PH_NEWTON || h[q].phase == PH_FALLBACK);
+            bool any = false, pending = false, failed = false;
+            for (int q = 0; q < count; ++q) {
+                any |= h[q].phase == PH_NEWTON;
+                pending |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_PENDING;
+                failed |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_FAILED;
+            }
             if (!any) break;
+            for (int hh = 1; pending && hh < p.ls_max; hh += LS_T) {
+                run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, false); });
+                const Ctrl* h2 = readback(ctx, st, d_ctrl, count);
+                pending = false;
+                for (int q = 0; q < count; ++q) {
+                    pending |= h2[q].phase == PH_NEWTON && h2[q].ls_state == LS_PENDING;
+                    failed |= h2[q].phase == PH_NEWTON && h2[q].ls_state == LS_FAILED;
+                }
+            }
+            run(ctx, st, PINS_K_UPDATE, [&] { launch_update(L); });
+            if (failed) {
+                run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, false, M_FB); });
+                run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, false, M_FB); });
+                run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_FB); });
+            }
         }
     }
     bool want_x = false;
@@ -547,7 +563,15 @@ int solve_impl(pins_ctx* ctx, const pins_problem* probs, int count, const pins_p
         for (int kk = 0; kk < PINS_NKERN; ++kk) {
             r.kern_ms[kk] = kms[kk];
             r.kern_calls[kk] = kcalls[kk];
+            r.kern_work[kk] = 0.0;
         }
+        r.kern_work[PINS_K_ROW_LSE] = S.work[W_ROW];
+        r.kern_work[PINS_K_COL_LSE] = S.work[W_COL];
+        r.kern_work[PINS_K_GRAD] = S.work[W_GRAD];
+        r.kern_work[PINS_K_FILL] = S.work[W_FILL];
+        r.kern_work[PINS_K_CSC] = S.work[W_FILLC];
+        r.kern_work[PINS_K_LS] = S.work[W_LS];
+        r.kern_work[PINS_K_FINAL] = S.work[W_FINAL];
         if (r.status < 0 && (worst >= 0 || r.status < worst)) worst = r.status;
         if (worst >= 0 && r.status > worst) worst = r.status;
     }

@@ -55,14 +55,14 @@ struct DevInst {
     double* part2;  // row partials of tile kernels: ncb * m * LS_T
     double* blk;    // per-block scalars: >= max blocks * LS_T
     double* blk2;   // second per-block scalar area (merge kernels)
-    int* hist;      // m * NLEV Sparsify histogram
+    int* hist;      // m * NLEV Sparsify histogram (per row)
+    int* histc;     // n * NLEV Sparsify histogram (per column)
     int* rowptr;    // m+1
     int* col;       // nnz_cap
     double* val;    // nnz_cap
     int* colptr;    // n+1
     int* rowT;      // nnz_cap
     double* valT;   // nnz_cap
-    int* cfill;     // n
     double* Ck;     // materialised shifted cost (m*n) or nullptr
     double* alpha;  // outputs
     double* beta;
@@ -78,7 +78,11 @@ struct Ctrl {
     double kappa, err, resid, alpha;
     double gd, dab, fa, cost;
     double entropy, dual, scale, pad2;
+    double work[8];  // matrix entries visited per pass kind (W_* below)
 };
+
+// pass kinds counted in Ctrl::work
+enum WorkKind : int { W_ROW = 0, W_COL = 1, W_GRAD = 2, W_FILL = 3, W_FILLC = 4, W_LS = 5, W_FINAL = 6 };
 
 // Kernel-wide parameters (passed by value).
 struct KP {

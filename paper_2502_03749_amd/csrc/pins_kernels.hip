@@ -41,13 +41,19 @@ struct DenseSrc {
 };
 
 // Squared distance between pixels p = row*s + col of an s x s grid, times the
-// scale; exact integers before scaling, never stored.
+// scale; exact integers before scaling, never stored.  The row of a pixel is
+// found as (int)((p + 0.5) * (1/s)) in float, exact because p < s^2 < 2^16:
+// the relative rounding error (< 2^-22) times p/s (< s) stays far below the
+// distance 0.5/s of (p + 0.5)/s to the nearest integer.
 struct GridSrc {
     int s;
+    float inv_s;
     double sc;
-    __device__ __forceinline__ GridSrc(const DevInst& I, bool base = false) : s(I.grid_s), sc(base ? I.bscale : I.cscale) {}
+    __device__ __forceinline__ GridSrc(const DevInst& I, bool base = false)
+        : s(I.grid_s), inv_s(1.0f / (float)I.grid_s), sc(base ? I.bscale : I.cscale) {}
+    __device__ __forceinline__ int quot(int v) const { return (int)(((float)v + 0.5f) * inv_s); }
     __device__ __forceinline__ double at(int i, int j) const {
-        const int ri = i / s, ci = i - ri * s, rj = j / s, cj = j - rj * s;
+        const int ri = quot(i), ci = i - ri * s, rj = quot(j), cj = j - rj * s;
         const int dr = ri - rj, dc = ci - cj;
         return (double)(dr * dr + dc * dc) * sc;
     }
@@ -187,6 +193,11 @@ __device__ __forceinline__ bool phase_in(const Ctrl* ctrl, int b, int mask) {
     return (mask >> ctrl[b].phase) & 1;
 }
 
+// one writer per instance (its first block) records the entries a pass visits
+__device__ __forceinline__ void count_work(Ctrl* ctrl, int b, int kind, int m, int n) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[b].work[kind] += (double)m * (double)n;
+}
+
 // ---------------------------------------------------------------------------
 // a2: Sinkhorn f-update (row log-sum-exp sweep), one wave per row.
 //   F_i <- eta*log a_i - eta*LSE_j((G_j - kappa*C_ij)/eta)
@@ -203,6 +214,7 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n;
     if ((int)blockIdx.x * 4 >= m) return;
+    count_work(ctrl, b, W_ROW, m, n);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + w;
     __shared__ double serr[4];
@@ -262,6 +274,7 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
     const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
     if (rb >= I.nrb) return;
     const int m = I.m, n = I.n;
+    count_work(ctrl, b, W_COL, m, n);
     const int j = cb * TILE_C + threadIdx.x;
     if (j >= n) return;
     const int i0 = rb * I.R, i1 = min(m, i0 + I.R);
@@ -349,10 +362,13 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
     const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
     if (rb >= I.nrb) return;
     const int m = I.m, n = I.n;
+    count_work(ctrl, b, W_GRAD, m, n);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ int hist[TILE_RMAX * NLEV];
+    __shared__ int hcol[NLEV * TILE_C];  // [level][column], touched only by the column's thread
     __shared__ double red[TILE_RMAX][TILE_C + 1];
     for (int t = threadIdx.x; t < TILE_RMAX * NLEV; t += 256) hist[t] = 0;
+    for (int l = 0; l < NLEV; ++l) hcol[l * TILE_C + threadIdx.x] = 0;
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
@@ -371,6 +387,7 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
             if (q >= 0.0) {
                 const int l = (q >= (double)(nlev - 1)) ? nlev - 1 : (int)q;
                 atomicAdd(&hist[r * NLEV + l], 1);
+                hcol[l * TILE_C + threadIdx.x] += 1;
             }
         }
         colacc += e;
@@ -392,6 +409,11 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
         const int v = hist[t];
         if (v) atomicAdd(&I.hist[(long)(i0 + t / NLEV) * NLEV + (t % NLEV)], v);
     }
+    if (valid)
+        for (int l = 0; l < nlev; ++l) {
+            const int v = hcol[l * TILE_C + threadIdx.x];
+            if (v) atomicAdd(&I.histc[(long)j * NLEV + l], v);
+        }
 }
 
 // Gradient merge: r = Xt e, c = Xt^T e into rc; the last block tests
@@ -489,9 +511,18 @@ __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ 
             },
             m, I.rowptr, I.nnz_cap, ish);
         if (threadIdx.x == 0) S.nnz = (int)(total < I.nnz_cap ? total : I.nnz_cap);
+        const int* __restrict__ Hc = I.histc;
+        block_scan_excl<256>(
+            [&](int j) {
+                int c = 0;
+                for (int l = lev; l < nlev; ++l) c += Hc[(long)j * NLEV + l];
+                return c;
+            },
+            n, I.colptr, I.nnz_cap, ish);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < m * NLEV; t += 256) I.hist[t] = 0;
+    for (int t = threadIdx.x; t < n * NLEV; t += 256) I.histc[t] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -504,6 +535,8 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n;
+    if ((int)blockIdx.x * 4 >= m) return;
+    count_work(ctrl, b, W_FILL, m, n);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + w;
     if (i >= m) return;
@@ -538,56 +571,225 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     }
 }
 
-// CSC copy of S (for S^T u in the Hessian product), one block per instance:
-// column counts, scan, scatter, then each column sorted by row index so the
-// order (and the products) are deterministic.
-__global__ __launch_bounds__(1024) void k_csc(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
-    const int b = blockIdx.x;
+// CSC copy of S (for S^T u in the Hessian product): the same kept set,
+// filled column by column, one thread per column walking the rows in order,
+// so each column comes out sorted by row index without atomics or sorting.
+template <class Src>
+__global__ __launch_bounds__(256) void k_fill_csc(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n;
-    const int nnz = ctrl[b].nnz;
-    __shared__ int ish[16];
-    for (int j = threadIdx.x; j < n; j += 1024) I.cfill[j] = 0;
-    __syncthreads();
-    for (int k = threadIdx.x; k < nnz; k += 1024) atomicAdd(&I.cfill[I.col[k]], 1);
-    __syncthreads();
-    const int* cf = I.cfill;
-    block_scan_excl<1024>([&](int j) { return cf[j]; }, n, I.colptr, 0x7fffffff, ish);
-    for (int j = threadIdx.x; j < n; j += 1024) I.cfill[j] = I.colptr[j];
-    __syncthreads();
-    for (int i = threadIdx.x; i < m; i += 1024) {
-        const int k1 = I.rowptr[i + 1];
-        for (int k = I.rowptr[i]; k < k1; ++k) {
-            const int s = atomicAdd(&I.cfill[I.col[k]], 1);
-            I.rowT[s] = i;
-            I.valT[s] = I.val[k];
+    if ((int)blockIdx.x * 256 >= n) return;
+    count_work(ctrl, b, W_FILLC, m, n);
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double lev = (double)ctrl[b].level;
+    const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
+    const Src src(I);
+    int base = I.colptr[j];
+    const int end = I.colptr[j + 1];
+    const double Gj = I.G[j], lbj = I.logb[j];
+    for (int i = 0; i < m && base < end; ++i) {
+        const double x = expo(I.F[i], Gj, kap, src.at(i, j), ie);
+        if (lev_q(x, lrho, I.loga[i], lbj) >= lev) {
+            I.rowT[base] = i;
+            I.valT[base] = exp(x);
+            ++base;
         }
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += 1024) {
-        const int k0 = I.colptr[j], k1 = I.colptr[j + 1];
-        for (int k = k0 + 1; k < k1; ++k) {
-            const int r = I.rowT[k];
-            const double v = I.valT[k];
-            int q = k - 1;
-            while (q >= k0 && I.rowT[q] > r) {
-                I.rowT[q + 1] = I.rowT[q];
-                I.valT[q + 1] = I.valT[q];
-                --q;
-            }
-            I.rowT[q + 1] = r;
-            I.valT[q + 1] = v;
-        }
+    for (; base < end; ++base) {
+        I.rowT[base] = 0;
+        I.valT[base] = 0.0;
     }
 }
 
 // ---------------------------------------------------------------------------
 // a7: truncated Jacobi-preconditioned CG on M d = eta*grad P, where
 // M = [diag(r) S; S^T diag(c)] = -eta * (sparsified Hessian of eq. (eppa-hess)),
-// x0 = 0, stop at ||res||_2 <= cg_rtol*||rhs||_2 or cg_max.  One block per
-// instance.  Then the line-search inputs <grad P, d>, <a,dF>+<b,dG>.
+// x0 = 0, stop at ||res||_2 <= cg_rtol*||rhs||_2 or cg_max.  One block of 1024
+// threads per instance.  Each thread owns the vector entries k = tid + 1024 t
+// (kept in registers in the LDS variant); the products S v and S^T u are done
+// by 16-lane groups per row/column gathering p from LDS.  Afterwards the
+// line-search inputs <grad P, d>, <a,dF>+<b,dG> and the resolution test.
 // ---------------------------------------------------------------------------
+// One row of M's off-diagonal part (S v for k < m, S^T u for k >= m), summed
+// by a group of G lanes with four independent loads in flight per lane.
+template <int G>
+__device__ __forceinline__ double spmv_row(const DevInst& I, int m, int k, const double* __restrict__ pv, int lg) {
+    int q0, q1, off;
+    const int* __restrict__ idx;
+    const double* __restrict__ v;
+    if (k < m) {
+        q0 = I.rowptr[k];
+        q1 = I.rowptr[k + 1];
+        idx = I.col;
+        v = I.val;
+        off = m;
+    } else {
+        q0 = I.colptr[k - m];
+        q1 = I.colptr[k - m + 1];
+        idx = I.rowT;
+        v = I.valT;
+        off = 0;
+    }
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = q0 + lg;
+    for (; q + 3 * G < q1; q += 4 * G) {
+        const int i0 = idx[q], i1 = idx[q + G], i2 = idx[q + 2 * G], i3 = idx[q + 3 * G];
+        const double v0 = v[q], v1 = v[q + G], v2 = v[q + 2 * G], v3 = v[q + 3 * G];
+        s0 += v0 * pv[off + i0];
+        s1 += v1 * pv[off + i1];
+        s2 += v2 * pv[off + i2];
+        s3 += v3 * pv[off + i3];
+    }
+    for (; q < q1; q += G) s0 += v[q] * pv[off + idx[q]];
+    double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    return s;
+}
+
+// S v / S^T u for all N rows by groups of G lanes; results into out[k].
+template <int G>
+__device__ __forceinline__ void spmv_all(const DevInst& I, int m, int N, const double* __restrict__ pv,
+                                         double* __restrict__ out) {
+    constexpr int NG = 1024 / G;
+    const int g = threadIdx.x / G, lg = threadIdx.x % G;
+    for (int k = g; k < N; k += NG) {
+        const double s = spmv_row<G>(I, m, k, pv, lg);
+        if (lg == 0) out[k] = s;
+    }
+}
+
+__device__ __forceinline__ void spmv_dispatch(const DevInst& I, int m, int N, int nnz, const double* __restrict__ pv,
+                                              double* __restrict__ out) {
+    // lanes per row from the average row length (2 nnz entries per coupling, N rows)
+    const int avg = (2 * nnz) / (N > 0 ? N : 1);
+    if (avg <= 24)
+        spmv_all<4>(I, m, N, pv, out);
+    else if (avg <= 96)
+        spmv_all<8>(I, m, N, pv, out);
+    else
+        spmv_all<16>(I, m, N, pv, out);
+}
+
+__device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp) {
+    S.last_cg = it;
+    S.cg_total += it;
+    S.gd = gd;
+    S.dab = dab;
+    S.fa = fa;
+    S.ls_h = 0;
+    if (!(gd > 0.0)) {
+        S.ls_state = LS_FAILED;
+    } else if (kp.ls_c1 * gd <= 64.0 * DBL_EPSILON * fa) {
+        S.ls_state = LS_ACCEPTED;  // increase below the evaluation's resolution: full step
+        S.alpha = 1.0;
+    } else {
+        S.ls_state = LS_PENDING;
+    }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n, N = m + n;
+    __shared__ double sp[1024 * EPT];
+    __shared__ double sAp[1024 * EPT];
+    __shared__ double sh[16];
+    const int tid = threadIdx.x;
+    const double eta = kp.eta;
+    // register-resident iterate x, residual r, direction p and diagonal dg
+    double x[EPT], r[EPT], p[EPT], dg[EPT];
+    double bb = 0.0, rz = 0.0;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+        const int k = tid + 1024 * t;
+        x[t] = r[t] = p[t] = 0.0;
+        dg[t] = 1.0;
+        if (k < N) {
+            dg[t] = I.rc[k];
+            const double tg = (k < m) ? I.a[k] : I.b[k - m];
+            const double rh = eta * (tg - dg[t]);
+            r[t] = rh;
+            p[t] = rh / dg[t];
+            sp[k] = p[t];
+            bb += rh * rh;
+            rz += rh * p[t];
+        }
+    }
+    bb = block_sum<1024>(bb, sh);
+    rz = block_sum<1024>(rz, sh);
+    const double bn = sqrt(bb);
+    const int nnz = ctrl[b].nnz;
+    int it = 0;
+    if (bn > 0.0) {
+        while (it < kp.cg_max) {
+            __syncthreads();
+            spmv_dispatch(I, m, N, nnz, sp, sAp);
+            __syncthreads();
+            double pap = 0.0;
+#pragma unroll
+            for (int t = 0; t < EPT; ++t) {
+                const int k = tid + 1024 * t;
+                if (k < N) {
+                    const double ap = dg[t] * p[t] + sAp[k];
+                    sAp[k] = ap;
+                    pap += p[t] * ap;
+                }
+            }
+            pap = block_sum<1024>(pap, sh);
+            if (!(pap > 0.0)) break;
+            const double al = rz / pap;
+            double rr = 0.0, rz2 = 0.0;
+#pragma unroll
+            for (int t = 0; t < EPT; ++t) {
+                const int k = tid + 1024 * t;
+                if (k < N) {
+                    x[t] += al * p[t];
+                    r[t] -= al * sAp[k];
+                    rr += r[t] * r[t];
+                    rz2 += r[t] * (r[t] / dg[t]);
+                }
+            }
+            rr = block_sum<1024>(rr, sh);
+            rz2 = block_sum<1024>(rz2, sh);
+            ++it;
+            if (sqrt(rr) <= kp.cg_rtol * bn) break;
+            const double be = rz2 / rz;
+            rz = rz2;
+#pragma unroll
+            for (int t = 0; t < EPT; ++t) {
+                const int k = tid + 1024 * t;
+                if (k < N) {
+                    p[t] = r[t] / dg[t] + be * p[t];
+                    sp[k] = p[t];
+                }
+            }
+        }
+    }
+    double gd = 0.0, dab = 0.0, fa = 0.0;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+        const int k = tid + 1024 * t;
+        if (k < N) {
+            const double tg = (k < m) ? I.a[k] : I.b[k - m];
+            I.d[k] = x[t];
+            gd += (tg - dg[t]) * x[t];
+            dab += tg * x[t];
+            fa += fabs(tg * x[t]);
+        }
+    }
+    gd = block_sum<1024>(gd, sh);
+    dab = block_sum<1024>(dab, sh);
+    fa = block_sum<1024>(fa, sh);
+    if (tid == 0) ls_setup(ctrl[b], it, gd, dab, fa, kp);
+}
+
+// Same iteration with every vector in global memory (large m + n).
 __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
@@ -599,12 +801,6 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     double* __restrict__ p = I.cgw + 2 * N;
     double* __restrict__ Ap = I.cgw + 3 * N;
     const double* __restrict__ dg = I.rc;
-    const int* __restrict__ rp = I.rowptr;
-    const int* __restrict__ ci = I.col;
-    const double* __restrict__ sv = I.val;
-    const int* __restrict__ cp = I.colptr;
-    const int* __restrict__ ri = I.rowT;
-    const double* __restrict__ svT = I.valT;
     __shared__ double sh[16];
     const double eta = kp.eta;
     double bb = 0.0, rz = 0.0;
@@ -621,19 +817,16 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     bb = block_sum<1024>(bb, sh);
     rz = block_sum<1024>(rz, sh);
     const double bn = sqrt(bb);
+    const int nnz = ctrl[b].nnz;
     int it = 0;
     if (bn > 0.0) {
         while (it < kp.cg_max) {
             __syncthreads();
+            spmv_dispatch(I, m, N, nnz, p, Ap);
+            __syncthreads();
             double pap = 0.0;
             for (int k = threadIdx.x; k < N; k += 1024) {
-                double s = dg[k] * p[k];
-                if (k < m) {
-                    for (int q = rp[k]; q < rp[k + 1]; ++q) s += sv[q] * p[m + ci[q]];
-                } else {
-                    const int j = k - m;
-                    for (int q = cp[j]; q < cp[j + 1]; ++q) s += svT[q] * p[ri[q]];
-                }
+                const double s = dg[k] * p[k] + Ap[k];
                 Ap[k] = s;
                 pap += p[k] * s;
             }
@@ -660,7 +853,6 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
         }
     }
     __syncthreads();
-    // line-search inputs
     double gd = 0.0, dab = 0.0, fa = 0.0;
     for (int k = threadIdx.x; k < N; k += 1024) {
         const double tgt = (k < m) ? I.a[k] : I.b[k - m];
@@ -671,23 +863,7 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     gd = block_sum<1024>(gd, sh);
     dab = block_sum<1024>(dab, sh);
     fa = block_sum<1024>(fa, sh);
-    if (threadIdx.x == 0) {
-        Ctrl& S = ctrl[b];
-        S.last_cg = it;
-        S.cg_total += it;
-        S.gd = gd;
-        S.dab = dab;
-        S.fa = fa;
-        S.ls_h = 0;
-        if (!(gd > 0.0)) {
-            S.ls_state = LS_FAILED;
-        } else if (kp.ls_c1 * gd <= 64.0 * DBL_EPSILON * fa) {
-            S.ls_state = LS_ACCEPTED;  // increase below the evaluation's resolution: full step
-            S.alpha = 1.0;
-        } else {
-            S.ls_state = LS_PENDING;
-        }
-    }
+    if (threadIdx.x == 0) ls_setup(ctrl[b], it, gd, dab, fa, kp);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,6 +879,7 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
     const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
     if (rb >= I.nrb) return;
     const int m = I.m, n = I.n;
+    count_work(ctrl, b, W_LS, m, n);
     const int h0 = ctrl[b].ls_h;
     const int nt = min(NT, kp.ls_max - h0);
     double al[NT];
@@ -863,6 +1040,7 @@ __global__ __launch_bounds__(1024) void k_init(const DevInst* __restrict__ insts
         }
     }
     for (int t = threadIdx.x; t < m * NLEV; t += 1024) I.hist[t] = 0;
+    for (int t = threadIdx.x; t < I.n * NLEV; t += 1024) I.histc[t] = 0;
     if (threadIdx.x == 0) {
         Ctrl& S = ctrl[b];
         S.phase = S.nonfinite ? PH_DONE : (kp.T1 > 0 ? PH_WARM : PH_NEWTON);
@@ -1001,6 +1179,7 @@ __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts
     const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
     if (rb >= I.nrb) return;
     const int m = I.m, n = I.n;
+    count_work(ctrl, b, W_FINAL, m, n);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ double red[TILE_RMAX][TILE_C + 1];
     __shared__ double sh[4];
@@ -1143,12 +1322,26 @@ void launch_fill(const LaunchCtx& L, int src) {
 #undef K_
 }
 
-void launch_csc(const LaunchCtx& L) {
-    hipLaunchKernelGGL(k_csc, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl);
+void launch_fill_csc(const LaunchCtx& L, int src) {
+    const dim3 g = g2((L.max_n + 255) / 256, L.count);
+#define K_(S) hipLaunchKernelGGL((k_fill_csc<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+    PINS_SRC_DISPATCH(src, K_);
+#undef K_
 }
 
 void launch_pcg(const LaunchCtx& L) {
-    hipLaunchKernelGGL(k_pcg, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+    const int ept = (L.max_mn + 1023) / 1024;
+    const dim3 g(L.count), blk(1024);
+    if (ept <= 1)
+        hipLaunchKernelGGL(k_pcg_lds<1>, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+    else if (ept <= 2)
+        hipLaunchKernelGGL(k_pcg_lds<2>, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+    else if (ept <= 4)
+        hipLaunchKernelGGL(k_pcg_lds<4>, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+    else if (ept <= 8)
+        hipLaunchKernelGGL(k_pcg_lds<8>, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+    else
+        hipLaunchKernelGGL(k_pcg, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
 void launch_ls(const LaunchCtx& L, int src, bool first) {

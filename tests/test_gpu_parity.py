@@ -240,3 +240,18 @@ def test_caps_report_not_converged(ctx):
     r = ctx.solve(P.COST_DENSE, a, b, P.params(eta=0.01, max_outer=3, max_newton=0, max_sinkhorn=1), C=C)
     assert r["rc"] == 1 and (r["flags"] & 1)
     assert np.isfinite(r["alpha"]).all() and np.isfinite(r["cost"])
+
+
+@pytest.mark.parametrize("case", ["lds8", "global"])
+def test_large_instances_parity(ctx, case):
+    """Sizes that use the largest register/LDS CG variant (m+n <= 8192) and the
+    global-memory CG (m+n > 8192)."""
+    print("case large %s" % case, flush=True)
+    m, n = (4100, 4000) if case == "lds8" else (6000, 2300)
+    C, a, b = _rand(m, n, 4242 + m)
+    eta, K = 0.05, 1
+    prm = P.params(eta=eta, max_outer=K)
+    g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), prm)
+    g["_C"] = C
+    o = oracle.pins(C, a, b, eta=eta, K=K)
+    check_parity(g, o, a, b)
