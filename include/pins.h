@@ -146,8 +146,8 @@ typedef struct {
 #define PINS_K_COL_MERGE 2 /* Sinkhorn g-update, merge + warm-up control */
 #define PINS_K_GRAD 3      /* Newton pass: Xt row/col sums, Sparsify histogram */
 #define PINS_K_GRAD_MERGE 4 /* gradient merge, convergence, Sparsify level, CSR row pointers */
-#define PINS_K_FILL 5      /* CSR fill */
-#define PINS_K_CSC 6       /* CSC fill (column order) */
+#define PINS_K_FILL 5      /* Sparsify: counts, pointer scans, CSR+CSC fill */
+#define PINS_K_CSC 6       /* (unused) */
 #define PINS_K_PCG 7       /* preconditioned CG */
 #define PINS_K_LS 8        /* Armijo trial pass */
 #define PINS_K_UPDATE 9    /* dual update */

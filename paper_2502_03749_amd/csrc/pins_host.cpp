@@ -69,8 +69,8 @@ struct Carver {
 // Offsets of one instance's device arrays inside the workspace.
 struct InstPlan {
     int m, n, d, R, nrb, ncb, cap;
-    size_t loga, logb, F, G, Ah, Bh, rc, dir, cgw, part, part2, blk, blk2, hist, histc, rowptr, col, val, colptr,
-        rowT, valT, Ck, Cpts;
+    size_t loga, logb, F, G, Ah, Bh, rc, dir, cgw, part, part2, blk, blk2, hist, rowptr, col, val, colptr,
+        rowT, valT, cntr, cntc, Ck, Cpts;
     size_t C, x, y, a, b, alpha, beta, X;  // host-API staging
 };
 
@@ -106,8 +106,9 @@ InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, 
     q.part2 = cv.take((size_t)q.ncb * m * D);
     q.blk = cv.take((size_t)nblk * LS_T * D);
     q.blk2 = cv.take((size_t)nblk * D);
-    q.hist = cv.take((size_t)m * NLEV * I4);
-    q.histc = cv.take((size_t)n * NLEV * I4);
+    q.hist = cv.take((size_t)NLEV * I4);
+    q.cntr = cv.take((size_t)m * q.ncb * I4);
+    q.cntc = cv.take((size_t)q.nrb * n * I4);
     q.rowptr = cv.take((m + 1) * I4);
     q.col = cv.take((size_t)q.cap * I4);
     q.val = cv.take((size_t)q.cap * D);
@@ -384,7 +385,8 @@ int solve_impl(pins_ctx* ctx, const pins_problem* probs, int count, const pins_p
         I.blk = Dp(L.blk);
         I.blk2 = Dp(L.blk2);
         I.hist = Ip(L.hist);
-        I.histc = Ip(L.histc);
+        I.cntr = Ip(L.cntr);
+        I.cntc = Ip(L.cntc);
         I.rowptr = Ip(L.rowptr);
         I.col = Ip(L.col);
         I.val = Dp(L.val);
@@ -480,8 +482,7 @@ int solve_impl(pins_ctx* ctx, const pins_problem* probs, int count, const pins_p
         for (;;) {
             run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
             run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L); });
-            run(ctx, st, PINS_K_FILL, [&] { launch_fill(L, src); });
-            run(ctx, st, PINS_K_CSC, [&] { launch_fill_csc(L, src); });
+            run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
             run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
             run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
             // one readback per Newton step: who is still iterating, who needs more

@@ -55,8 +55,9 @@ struct DevInst {
     double* part2;  // row partials of tile kernels: ncb * m * LS_T
     double* blk;    // per-block scalars: >= max blocks * LS_T
     double* blk2;   // second per-block scalar area (merge kernels)
-    int* hist;      // m * NLEV Sparsify histogram (per row)
-    int* histc;     // n * NLEV Sparsify histogram (per column)
+    int* hist;      // NLEV Sparsify histogram (entries per highest kept level)
+    int* cntr;      // m * ncb kept entries per (row, column block) at the chosen level
+    int* cntc;      // nrb * n kept entries per (row block, column) at the chosen level
     int* rowptr;    // m+1
     int* col;       // nnz_cap
     double* val;    // nnz_cap

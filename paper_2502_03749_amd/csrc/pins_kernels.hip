@@ -59,6 +59,13 @@ struct GridSrc {
     }
 };
 
+// load through the global address space (the pointers live in descriptors,
+// so the compiler cannot infer it and would otherwise emit flat loads)
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // log of the recovery map, eq. (eppa_x): (F_i + G_j - kappa*C_ij)/eta
 __device__ __forceinline__ double expo(double Fi, double Gj, double kap, double c, double ie) {
     return (Fi + Gj - kap * c) * ie;
@@ -232,7 +239,7 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * 64 + lane;
-                z[u] = (j < n) ? (G[j] - kap * src.at(i, j)) * ie : -INFINITY;
+                z[u] = (j < n) ? (ldg(G + j) - kap * src.at(i, j)) * ie : -INFINITY;
                 cm = fmax(cm, z[u]);
             }
             if (cm > mx) {
@@ -275,12 +282,14 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
     if (rb >= I.nrb) return;
     const int m = I.m, n = I.n;
     count_work(ctrl, b, W_COL, m, n);
+    const int i0 = rb * I.R, i1 = min(m, i0 + I.R);
+    __shared__ double sF[TILE_RMAX + 4];
+    if ((int)threadIdx.x < TILE_RMAX + 4) sF[threadIdx.x] = (i0 + (int)threadIdx.x < i1) ? I.F[i0 + threadIdx.x] : 0.0;
+    __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     if (j >= n) return;
-    const int i0 = rb * I.R, i1 = min(m, i0 + I.R);
     const double kap = ctrl[b].kappa, ie = kp.inv_eta;
     const Src src(I);
-    const double* __restrict__ F = I.F;
     double mx = -INFINITY;
     T sm = T(0);
     constexpr int U = 4;
@@ -290,7 +299,7 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int ii = i + u;
-            z[u] = (ii < i1) ? (F[ii] - kap * src.at(ii, j)) * ie : -INFINITY;
+            z[u] = (ii < i1) ? (sF[ii - i0] - kap * src.at(ii, j)) * ie : -INFINITY;
             cm = fmax(cm, z[u]);
         }
         if (cm > mx) {
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(256) void k_col_merge(const DevInst* __restrict__ i
 // ---------------------------------------------------------------------------
 // a5: Newton pass.  Tile = R rows x 256 columns.  Xt_ij of eq. (eppa_x);
 // column partials part[rb][j], row partials part2[cb][i], and the Sparsify
-// histogram hist[i][l] (count of entries whose highest kept level is l).
+// histogram hist[l] (number of entries whose highest kept level is l).
 // ---------------------------------------------------------------------------
 template <class Src>
 __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
@@ -364,29 +373,30 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
     const int m = I.m, n = I.n;
     count_work(ctrl, b, W_GRAD, m, n);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
-    __shared__ int hist[TILE_RMAX * NLEV];
-    __shared__ int hcol[NLEV * TILE_C];  // [level][column], touched only by the column's thread
+    __shared__ int hcol[NLEV * TILE_C];  // [level][thread]: each thread counts its own entries
     __shared__ double red[TILE_RMAX][TILE_C + 1];
-    for (int t = threadIdx.x; t < TILE_RMAX * NLEV; t += 256) hist[t] = 0;
+    __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
     for (int l = 0; l < NLEV; ++l) hcol[l * TILE_C + threadIdx.x] = 0;
+    if ((int)threadIdx.x < rows) {
+        sF[threadIdx.x] = I.F[i0 + threadIdx.x];
+        sLa[threadIdx.x] = I.loga[i0 + threadIdx.x];
+    }
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
     const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
     const int nlev = kp.nlev;
     const Src src(I);
-    const double Gj = valid ? I.G[j] : 0.0, lbj = valid ? I.logb[j] : 0.0;
+    const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
     double colacc = 0.0;
     for (int r = 0; r < rows; ++r) {
-        const int i = i0 + r;
         double e = 0.0;
         if (valid) {
-            const double x = expo(I.F[i], Gj, kap, src.at(i, j), ie);
+            const double x = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
             e = exp(x);
-            const double q = lev_q(x, lrho, I.loga[i], lbj);
+            const double q = lev_q(x, lrho, sLa[r], lbj);
             if (q >= 0.0) {
                 const int l = (q >= (double)(nlev - 1)) ? nlev - 1 : (int)q;
-                atomicAdd(&hist[r * NLEV + l], 1);
                 hcol[l * TILE_C + threadIdx.x] += 1;
             }
         }
@@ -405,21 +415,26 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
         for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
         if (r < rows && s == 0) I.part2[(long)cb * m + i0 + r] = v;
     }
-    for (int t = threadIdx.x; t < rows * NLEV; t += 256) {
-        const int v = hist[t];
-        if (v) atomicAdd(&I.hist[(long)(i0 + t / NLEV) * NLEV + (t % NLEV)], v);
-    }
-    if (valid)
+    // per-level totals of the tile into the instance histogram (integer adds)
+    {
+        __shared__ int wl[NLEV][4];
+        const int w = threadIdx.x >> 6;
         for (int l = 0; l < nlev; ++l) {
-            const int v = hcol[l * TILE_C + threadIdx.x];
-            if (v) atomicAdd(&I.histc[(long)j * NLEV + l], v);
+            const int v = wave_sum_i(hcol[l * TILE_C + threadIdx.x]);
+            if ((threadIdx.x & 63) == 0) wl[l][w] = v;
         }
+        __syncthreads();
+        if ((int)threadIdx.x < nlev) {
+            const int l = threadIdx.x;
+            const int v = wl[l][0] + wl[l][1] + wl[l][2] + wl[l][3];
+            if (v) atomicAdd(&I.hist[l], v);
+        }
+    }
 }
 
 // Gradient merge: r = Xt e, c = Xt^T e into rc; the last block tests
-// convergence (||a-r||_1 + ||b-c||_1 <= tol, or the Newton cap), picks the
-// Sparsify level (densest level within the budget) and builds the CSR row
-// pointers by an exclusive scan of the per-row kept counts.
+// convergence (||a-r||_1 + ||b-c||_1 <= tol, or the Newton cap) and picks the
+// Sparsify level (densest level within the budget).
 __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
                                                     KP kp) {
     const int b = blockIdx.y;
@@ -449,8 +464,7 @@ __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ 
 
     const double res = block_sum_array<256>(I.blk2, nb, sh);
     Ctrl& S = ctrl[b];
-    __shared__ int s_go, s_lev;
-    __shared__ int ish[4];
+    __shared__ int s_go;
     if (threadIdx.x == 0) {
         S.resid = res;
         int go = 0;
@@ -469,18 +483,10 @@ __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ 
     }
     __syncthreads();
     if (s_go) {
-        // level totals: tot[l] = number of entries whose highest kept level is l
+        // tot[l] = number of entries whose highest kept level is l
         __shared__ long tot[NLEV];
         const int nlev = kp.nlev;
-        for (int l = 0; l < nlev; ++l) {
-            int c = 0;
-            for (int i = threadIdx.x; i < m; i += 256) c += I.hist[(long)i * NLEV + l];
-            c = wave_sum_i(c);
-            __syncthreads();
-            if ((threadIdx.x & 63) == 0) ish[threadIdx.x >> 6] = c;
-            __syncthreads();
-            if (threadIdx.x == 0) tot[l] = (long)ish[0] + ish[1] + ish[2] + ish[3];
-        }
+        if ((int)threadIdx.x < nlev) tot[threadIdx.x] = I.hist[threadIdx.x];
         __syncthreads();
         if (threadIdx.x == 0) {
             const double lim = kp.budget * (double)(m + n - 1);
@@ -497,110 +503,158 @@ __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ 
                     lev = l;
                     break;
                 }
-            s_lev = lev;
             S.level = lev;
         }
-        __syncthreads();
-        const int lev = s_lev;
-        const int* __restrict__ H = I.hist;
-        const long total = block_scan_excl<256>(
-            [&](int i) {
-                int c = 0;
-                for (int l = lev; l < nlev; ++l) c += H[(long)i * NLEV + l];
-                return c;
-            },
-            m, I.rowptr, I.nnz_cap, ish);
-        if (threadIdx.x == 0) S.nnz = (int)(total < I.nnz_cap ? total : I.nnz_cap);
-        const int* __restrict__ Hc = I.histc;
-        block_scan_excl<256>(
-            [&](int j) {
-                int c = 0;
-                for (int l = lev; l < nlev; ++l) c += Hc[(long)j * NLEV + l];
-                return c;
-            },
-            n, I.colptr, I.nnz_cap, ish);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < m * NLEV; t += 256) I.hist[t] = 0;
-    for (int t = threadIdx.x; t < n * NLEV; t += 256) I.histc[t] = 0;
+    if ((int)threadIdx.x < NLEV) I.hist[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
-// a6: Sparsify fill, one wave per row: entries with level >= chosen level,
-// in increasing column order (ballot compaction).
+// a6: Sparsify at the chosen level: keep Xt_ij >= rho*10^lev*min(a_i,b_j).
+// Three steps, all tile-parallel and deterministic:
+//   k_count  kept entries per (row, column block) and per (row block, column)
+//   k_scan   CSR row pointers and CSC column pointers (exclusive scans)
+//   k_fill   both copies of S in one pass: CSR rows in column order (ballot
+//            prefix within the tile row), CSC columns in row order.
+// count and fill take the keep decision with the same arithmetic, so the
+// pointers match what the fill writes.
 // ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(256) void k_count(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
+    if (rb >= I.nrb) return;
+    const int m = I.m, n = I.n;
+    count_work(ctrl, b, W_FILL, m, n);
+    const int i0 = rb * I.R, rows = min(I.R, m - i0);
+    __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
+    __shared__ int wc[TILE_RMAX][4];
+    if ((int)threadIdx.x < rows) {
+        sF[threadIdx.x] = I.F[i0 + threadIdx.x];
+        sLa[threadIdx.x] = I.loga[i0 + threadIdx.x];
+    }
+    __syncthreads();
+    const int j = cb * TILE_C + threadIdx.x;
+    const bool valid = j < n;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double lev = (double)ctrl[b].level, kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
+    const Src src(I);
+    const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
+    int cc = 0;
+    for (int r = 0; r < rows; ++r) {
+        bool keep = false;
+        if (valid) keep = lev_q(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), lrho, sLa[r], lbj) >= lev;
+        cc += keep ? 1 : 0;
+        const unsigned long long bal = __ballot(keep);
+        if (lane == 0) wc[r][w] = (int)__popcll(bal);
+    }
+    __syncthreads();
+    if (valid) I.cntc[(long)rb * n + j] = cc;
+    if ((int)threadIdx.x < rows) {
+        const int r = threadIdx.x;
+        I.cntr[(long)(i0 + r) * I.ncb + cb] = wc[r][0] + wc[r][1] + wc[r][2] + wc[r][3];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n, ncb = I.ncb, nrb = I.nrb;
+    __shared__ int ish[16];
+    const int* __restrict__ cr = I.cntr;
+    const int* __restrict__ cc = I.cntc;
+    const long total = block_scan_excl<1024>(
+        [&](int i) {
+            int c = 0;
+            for (int q = 0; q < ncb; ++q) c += cr[(long)i * ncb + q];
+            return c;
+        },
+        m, I.rowptr, I.nnz_cap, ish);
+    block_scan_excl<1024>(
+        [&](int j) {
+            int c = 0;
+            for (int q = 0; q < nrb; ++q) c += cc[(long)q * n + j];
+            return c;
+        },
+        n, I.colptr, I.nnz_cap, ish);
+    if (threadIdx.x == 0) ctrl[b].nnz = (int)(total < I.nnz_cap ? total : I.nnz_cap);
+}
+
 template <class Src>
 __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
+    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
+    if (rb >= I.nrb) return;
     const int m = I.m, n = I.n;
-    if ((int)blockIdx.x * 4 >= m) return;
-    count_work(ctrl, b, W_FILL, m, n);
+    const int i0 = rb * I.R, rows = min(I.R, m - i0);
+    __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
+    __shared__ int sRow[TILE_RMAX], sEnd[TILE_RMAX];
+    __shared__ int wc[TILE_RMAX][4];
+    if ((int)threadIdx.x < rows) {
+        const int i = i0 + threadIdx.x;
+        sF[threadIdx.x] = I.F[i];
+        sLa[threadIdx.x] = I.loga[i];
+        int base = I.rowptr[i];
+        for (int q = 0; q < cb; ++q) base += I.cntr[(long)i * I.ncb + q];
+        sRow[threadIdx.x] = base;
+        sEnd[threadIdx.x] = I.rowptr[i + 1];
+    }
+    __syncthreads();
+    const int j = cb * TILE_C + threadIdx.x;
+    const bool valid = j < n;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + w;
-    if (i >= m) return;
-    const double lev = (double)ctrl[b].level;
-    const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
+    const double lev = (double)ctrl[b].level, kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
     const Src src(I);
-    int base = I.rowptr[i];
-    const int end = I.rowptr[i + 1];
-    const double Fi = I.F[i], la = I.loga[i];
-    const unsigned long long below = (1ull << lane) - 1ull;
-    for (int j0 = 0; j0 < n && base < end; j0 += 64) {
-        const int j = j0 + lane;
+    const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
+    int cpos = 0, cend = 0;
+    if (valid) {
+        cpos = I.colptr[j];
+        for (int q = 0; q < rb; ++q) cpos += I.cntc[(long)q * n + j];
+        cend = I.colptr[j + 1];
+    }
+    double xr[TILE_RMAX];
+    unsigned keepm = 0;
+#pragma unroll
+    for (int r = 0; r < TILE_RMAX; ++r) {
+        xr[r] = 0.0;
         bool keep = false;
-        double x = 0.0;
-        if (j < n) {
-            x = expo(Fi, I.G[j], kap, src.at(i, j), ie);
-            keep = lev_q(x, lrho, la, I.logb[j]) >= lev;
+        if (r < rows && valid) {
+            xr[r] = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
+            keep = lev_q(xr[r], lrho, sLa[r], lbj) >= lev;
         }
+        if (r < rows) {
+            const unsigned long long bal = __ballot(keep);
+            if (lane == 0) wc[r][w] = (int)__popcll(bal);
+        }
+        keepm |= keep ? (1u << r) : 0u;
+    }
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int r = 0; r < TILE_RMAX; ++r) {
+        const bool keep = (keepm >> r) & 1u;
         const unsigned long long bal = __ballot(keep);
-        const int slot = base + __popcll(bal & below);
-        if (keep && slot < end) {
-            I.col[slot] = j;
-            I.val[slot] = exp(x);
+        if (keep) {
+            int woff = 0;
+            for (int q = 0; q < w; ++q) woff += wc[r][q];
+            const int slot = sRow[r] + woff + (int)__popcll(bal & below);
+            const double v = exp(xr[r]);
+            if (slot < sEnd[r]) {
+                I.col[slot] = j;
+                I.val[slot] = v;
+            }
+            if (cpos < cend) {
+                I.rowT[cpos] = i0 + r;
+                I.valT[cpos] = v;
+            }
+            ++cpos;
         }
-        base += __popcll(bal);
-    }
-    // slots left over (kept count below the histogram's) hold explicit zeros
-    // so that the CSR is always well formed
-    for (int s = base + lane; s < end; s += 64) {
-        I.col[s] = 0;
-        I.val[s] = 0.0;
-    }
-}
-
-// CSC copy of S (for S^T u in the Hessian product): the same kept set,
-// filled column by column, one thread per column walking the rows in order,
-// so each column comes out sorted by row index without atomics or sorting.
-template <class Src>
-__global__ __launch_bounds__(256) void k_fill_csc(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
-    const int b = blockIdx.y;
-    if (ctrl[b].phase != PH_NEWTON) return;
-    const DevInst& I = insts[b];
-    const int m = I.m, n = I.n;
-    if ((int)blockIdx.x * 256 >= n) return;
-    count_work(ctrl, b, W_FILLC, m, n);
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const double lev = (double)ctrl[b].level;
-    const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
-    const Src src(I);
-    int base = I.colptr[j];
-    const int end = I.colptr[j + 1];
-    const double Gj = I.G[j], lbj = I.logb[j];
-    for (int i = 0; i < m && base < end; ++i) {
-        const double x = expo(I.F[i], Gj, kap, src.at(i, j), ie);
-        if (lev_q(x, lrho, I.loga[i], lbj) >= lev) {
-            I.rowT[base] = i;
-            I.valT[base] = exp(x);
-            ++base;
-        }
-    }
-    for (; base < end; ++base) {
-        I.rowT[base] = 0;
-        I.valT[base] = 0.0;
     }
 }
 
@@ -636,14 +690,14 @@ __device__ __forceinline__ double spmv_row(const DevInst& I, int m, int k, const
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int q = q0 + lg;
     for (; q + 3 * G < q1; q += 4 * G) {
-        const int i0 = idx[q], i1 = idx[q + G], i2 = idx[q + 2 * G], i3 = idx[q + 3 * G];
-        const double v0 = v[q], v1 = v[q + G], v2 = v[q + 2 * G], v3 = v[q + 3 * G];
+        const int i0 = ldg(idx + q), i1 = ldg(idx + q + G), i2 = ldg(idx + q + 2 * G), i3 = ldg(idx + q + 3 * G);
+        const double v0 = ldg(v + q), v1 = ldg(v + q + G), v2 = ldg(v + q + 2 * G), v3 = ldg(v + q + 3 * G);
         s0 += v0 * pv[off + i0];
         s1 += v1 * pv[off + i1];
         s2 += v2 * pv[off + i2];
         s3 += v3 * pv[off + i3];
     }
-    for (; q < q1; q += G) s0 += v[q] * pv[off + idx[q]];
+    for (; q < q1; q += G) s0 += ldg(v + q) * pv[off + ldg(idx + q)];
     double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
@@ -893,6 +947,12 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
         }
     }
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
+    __shared__ double sF[TILE_RMAX], sD[TILE_RMAX];
+    if ((int)threadIdx.x < rows) {
+        sF[threadIdx.x] = I.F[i0 + threadIdx.x];
+        sD[threadIdx.x] = I.d[i0 + threadIdx.x];
+    }
+    __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
     const double kap = ctrl[b].kappa, ie = kp.inv_eta;
@@ -901,11 +961,11 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = 0.0;
     if (valid) {
-        const double Gj = I.G[j], dGj = I.d[m + j];
+        const double Gj = ldg(I.G + j), dGj = ldg(I.d + m + j);
         for (int r = 0; r < rows; ++r) {
             const int i = i0 + r;
-            const double e = exp(expo(I.F[i], Gj, kap, src.at(i, j), ie));
-            const double del = (I.d[i] + dGj) * ie;
+            const double e = exp(expo(sF[r], Gj, kap, src.at(i, j), ie));
+            const double del = (sD[r] + dGj) * ie;
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] += e * expm1(al[t] * del);
         }
@@ -1039,8 +1099,7 @@ __global__ __launch_bounds__(1024) void k_init(const DevInst* __restrict__ insts
             I.G[k - m] = mat ? 0.0 : eta * lb;
         }
     }
-    for (int t = threadIdx.x; t < m * NLEV; t += 1024) I.hist[t] = 0;
-    for (int t = threadIdx.x; t < I.n * NLEV; t += 1024) I.histc[t] = 0;
+    for (int t = threadIdx.x; t < NLEV; t += 1024) I.hist[t] = 0;
     if (threadIdx.x == 0) {
         Ctrl& S = ctrl[b];
         S.phase = S.nonfinite ? PH_DONE : (kp.T1 > 0 ? PH_WARM : PH_NEWTON);
@@ -1187,6 +1246,9 @@ __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts
     const bool valid = j < n;
     const double ieps = K * kp.inv_eta;
     const Src base(I, true);
+    __shared__ double sA[TILE_RMAX];
+    if ((int)threadIdx.x < rows) sA[threadIdx.x] = I.alpha[i0 + threadIdx.x];
+    __syncthreads();
     const double bj = valid ? I.beta[j] : 0.0;
     double colacc = 0.0, cst = 0.0, ent = 0.0;
     for (int r = 0; r < rows; ++r) {
@@ -1194,7 +1256,7 @@ __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts
         double xv = 0.0;
         if (valid) {
             const double c = base.at(i, j);
-            const double lx = (I.alpha[i] + bj - c) * ieps;
+            const double lx = (sA[r] + bj - c) * ieps;
             xv = exp(lx);
             cst += c * xv;
             if (xv > 0.0) ent -= xv * lx;
@@ -1315,16 +1377,13 @@ void launch_grad_merge(const LaunchCtx& L) {
                        L.kp);
 }
 
-void launch_fill(const LaunchCtx& L, int src) {
-    const dim3 g = g2((L.max_m + 3) / 4, L.count);
-#define K_(S) hipLaunchKernelGGL((k_fill<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+void launch_sparsify(const LaunchCtx& L, int src) {
+    const dim3 g = g2(L.max_tiles, L.count);
+#define K_(S) hipLaunchKernelGGL((k_count<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
     PINS_SRC_DISPATCH(src, K_);
 #undef K_
-}
-
-void launch_fill_csc(const LaunchCtx& L, int src) {
-    const dim3 g = g2((L.max_n + 255) / 256, L.count);
-#define K_(S) hipLaunchKernelGGL((k_fill_csc<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+    hipLaunchKernelGGL(k_scan, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl);
+#define K_(S) hipLaunchKernelGGL((k_fill<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
     PINS_SRC_DISPATCH(src, K_);
 #undef K_
 }

@@ -24,8 +24,7 @@ void launch_col_lse(const LaunchCtx& L, int src, bool f32, int mask);
 void launch_col_merge(const LaunchCtx& L, int mask);
 void launch_grad(const LaunchCtx& L, int src);
 void launch_grad_merge(const LaunchCtx& L);
-void launch_fill(const LaunchCtx& L, int src);
-void launch_fill_csc(const LaunchCtx& L, int src);
+void launch_sparsify(const LaunchCtx& L, int src);
 void launch_pcg(const LaunchCtx& L);
 void launch_ls(const LaunchCtx& L, int src, bool first);
 void launch_update(const LaunchCtx& L);
