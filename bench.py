@@ -56,6 +56,9 @@ FLOPS_PER_ENTRY = {
     # exponent (3) + exp + cost/entropy/marginal accumulations (6)
     "final": 10.0 + EXP_FLOPS,
 }
+# Algorithmic bytes per unit of the sparse kernels: CG reads each stored
+# CSR/CSC entry (4-byte index + 8-byte value) once per iteration.
+BYTES_PER_ENTRY = {"pcg": 12.0}
 
 
 def parse():
@@ -125,11 +128,13 @@ def main():
     # roofline of the dominant kernel class over the timed region
     kms, kwork, kcalls = {}, {}, {}
     for rs in results:
-        r0 = rs[0]  # kernel times are per batch (identical in every result of a batch)
-        for k, v in r0["kern_ms"].items():
-            kms[k] = kms.get(k, 0.0) + v
-            kcalls[k] = kcalls.get(k, 0) + r0["kern_calls"][k]
+        seen = set()
         for r in rs:
+            if r["group"] not in seen:  # kernel times are per lane, shared by its instances
+                seen.add(r["group"])
+                for k, v in r["kern_ms"].items():
+                    kms[k] = kms.get(k, 0.0) + v
+                    kcalls[k] = kcalls.get(k, 0) + r["kern_calls"][k]
             for k, v in r["kern_work"].items():
                 kwork[k] = kwork.get(k, 0.0) + v
     roofline = None
@@ -145,6 +150,12 @@ def main():
                             unit="TFLOP/s", frac=achieved / PEAK_FP64_VECTOR_TFLOPS,
                             traffic=_traffic(dom), avg_launch_us=1e3 * avg_ms, launches=calls,
                             entries_per_launch=kwork[dom] / calls, flops_per_entry=fpe)
+        elif dom in BYTES_PER_ENTRY and kwork.get(dom, 0) > 0:
+            bytes_per_launch = kwork[dom] * BYTES_PER_ENTRY[dom] / calls
+            achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+            roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+                            frac=achieved / PEAK_HBM_GBS, traffic=_traffic(dom), avg_launch_us=1e3 * avg_ms,
+                            launches=calls, bytes_per_launch=bytes_per_launch)
         else:
             roofline = dict(kernel=dom, bound="latency", achieved=None, peak=None, unit=None, frac=None,
                             traffic=None, avg_launch_us=1e3 * avg_ms, launches=calls)

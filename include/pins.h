@@ -93,7 +93,9 @@ typedef struct {
     int32_t precision;    /* pins_precision */
     int32_t shift_mode;   /* pins_shift_mode */
     int32_t profile;      /* nonzero: time every kernel launch with HIP events (pins_result.kern_*) */
-    int32_t reserved;
+    int32_t streams;      /* batch entry point: number of concurrent lanes (own HIP stream and host
+                             thread each, instances split into contiguous groups, at most 4);
+                             0 or 1 = one lane on the caller's stream; results do not depend on it */
 } pins_params;
 
 /* One problem instance.  For pins_solve the pointers are host pointers, for
@@ -136,8 +138,12 @@ typedef struct {
     int32_t outer_iters, sinkhorn_iters, newton_iters, cg_iters, fallbacks, nnz_last;
     double kern_ms[PINS_NKERN];   /* summed kernel time per kernel class (profile != 0) */
     int32_t kern_calls[PINS_NKERN];
-    double kern_work[PINS_NKERN]; /* matrix entries visited per kernel class by this instance
-                                     (dense passes only; always filled) */
+    double kern_work[PINS_NKERN]; /* work per kernel class by this instance, always filled:
+                                     dense passes: matrix entries visited;
+                                     PCG: stored CSR+CSC entries read (2 nnz per CG iteration) */
+    int32_t group;        /* batch entry point: lane that solved this instance (kern_* are that
+                             lane's totals, shared by the instances of the group) */
+    int32_t reserved;
 } pins_result;
 
 /* Kernel classes reported in kern_ms / kern_calls. */

@@ -36,9 +36,9 @@ void oracle_default_params(oracle_params* p)
     p->ls_beta = 0.5;
     p->ls_c1 = 1e-4;
     p->ls_max = 30;
-    p->rho = 1e-9;
+    p->rho = 1e-7;
     p->budget = 64.0;
-    p->rho_levels = 13;
+    p->rho_levels = 11;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
                 ("ls_beta", ctypes.c_double), ("ls_c1", ctypes.c_double), ("ls_max", ctypes.c_int32),
                 ("rho_levels", ctypes.c_int32), ("rho", ctypes.c_double), ("budget", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("shift_mode", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("streams", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -58,7 +58,8 @@ class Result(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("sinkhorn_iters", ctypes.c_int32),
                 ("newton_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
                 ("nnz_last", ctypes.c_int32), ("kern_ms", ctypes.c_double * NKERN),
-                ("kern_calls", ctypes.c_int32 * NKERN), ("kern_work", ctypes.c_double * NKERN)]
+                ("kern_calls", ctypes.c_int32 * NKERN), ("kern_work", ctypes.c_double * NKERN),
+                ("group", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def scalars(self) -> dict:
         out = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("alpha", "beta", "X", "kern_ms",

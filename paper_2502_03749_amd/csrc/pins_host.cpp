@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pins.h"
@@ -20,9 +21,10 @@
 
 using namespace pins;
 
-struct pins_ctx {
+// Resources of one execution lane: a device workspace, a pinned staging
+// area, a pool of profiling events and (for lanes > 0) its own HIP stream.
+struct Lane {
     int device = 0;
-    std::string err;
     void* ws = nullptr;
     size_t ws_bytes = 0;
     void* pinned = nullptr;
@@ -31,6 +33,13 @@ struct pins_ctx {
     std::vector<int> ev_kind;
     size_t ev_used = 0;
     bool profile = false;
+    hipStream_t stream = nullptr;  // owned stream (default priority)
+};
+
+struct pins_ctx {
+    int device = 0;
+    std::string err;
+    std::vector<Lane*> lanes;  // lanes[0] runs single-stream solves on the caller's stream
 };
 
 namespace {
@@ -201,10 +210,10 @@ void check_marginal(const double* v, int len, const char* name) {
 
 // One event pair per launch when profiling; summed per kernel class at the end.
 struct Prof {
-    pins_ctx* c;
+    Lane* c;
     hipStream_t st;
     int kind = -1;
-    Prof(pins_ctx* c_, hipStream_t s, int k) : c(c_), st(s) {
+    Prof(Lane* c_, hipStream_t s, int k) : c(c_), st(s) {
         if (!c->profile) return;
         kind = k;
         if (c->ev_used + 2 > c->events.size()) {
@@ -227,14 +236,14 @@ struct Prof {
 };
 
 template <class Fn>
-void run(pins_ctx* c, hipStream_t st, int kind, Fn&& fn) {
+void run(Lane* c, hipStream_t st, int kind, Fn&& fn) {
     Prof pr(c, st, kind);
     fn();
     HIPCHK(hipGetLastError());
     pr.end();
 }
 
-void* pinned(pins_ctx* c, size_t bytes) {
+void* pinned(Lane* c, size_t bytes) {
     if (bytes > c->pinned_bytes) {
         if (c->pinned) HIPCHK(hipHostFree(c->pinned));
         c->pinned = nullptr;
@@ -245,7 +254,7 @@ void* pinned(pins_ctx* c, size_t bytes) {
     return c->pinned;
 }
 
-char* workspace(pins_ctx* c, size_t bytes) {
+char* workspace(Lane* c, size_t bytes) {
     if (bytes > c->ws_bytes) {
         if (c->ws) HIPCHK(hipFree(c->ws));
         c->ws = nullptr;
@@ -261,14 +270,14 @@ char* workspace(pins_ctx* c, size_t bytes) {
 }
 
 // Read the control blocks back (synchronises the stream).
-const Ctrl* readback(pins_ctx* c, hipStream_t st, const Ctrl* d_ctrl, int count) {
+const Ctrl* readback(Lane* c, hipStream_t st, const Ctrl* d_ctrl, int count) {
     Ctrl* h = (Ctrl*)pinned(c, sizeof(Ctrl) * count + sizeof(DevInst) * count);
     HIPCHK(hipMemcpyAsync(h, d_ctrl, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return h;
 }
 
-int solve_impl(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params& p, pins_result* res,
+int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_params& p, pins_result* res,
                hipStream_t st, bool host_api) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
@@ -570,11 +579,97 @@ int solve_impl(pins_ctx* ctx, const pins_problem* probs, int count, const pins_p
         r.kern_work[PINS_K_COL_LSE] = S.work[W_COL];
         r.kern_work[PINS_K_GRAD] = S.work[W_GRAD];
         r.kern_work[PINS_K_FILL] = S.work[W_FILL];
-        r.kern_work[PINS_K_CSC] = S.work[W_FILLC];
+        r.kern_work[PINS_K_PCG] = S.work[W_CG];
         r.kern_work[PINS_K_LS] = S.work[W_LS];
         r.kern_work[PINS_K_FINAL] = S.work[W_FINAL];
+        r.group = 0;
         if (r.status < 0 && (worst >= 0 || r.status < worst)) worst = r.status;
         if (worst >= 0 && r.status > worst) worst = r.status;
+    }
+    return worst;
+}
+
+Lane* lane(pins_ctx* ctx, int q) {
+    while ((int)ctx->lanes.size() <= q) {
+        Lane* L = new Lane;
+        L->device = ctx->device;
+        if (!ctx->lanes.empty()) {
+            HIPCHK(hipSetDevice(ctx->device));
+            HIPCHK(hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking));
+        }
+        ctx->lanes.push_back(L);
+    }
+    return ctx->lanes[q];
+}
+
+void free_lane(Lane* L) {
+    for (hipEvent_t e : L->events) (void)hipEventDestroy(e);
+    if (L->ws) (void)hipFree(L->ws);
+    if (L->pinned) (void)hipHostFree(L->pinned);
+    if (L->stream) (void)hipStreamDestroy(L->stream);
+    delete L;
+}
+
+// Number of concurrent lanes for a batch: params.streams (0 or 1: one lane
+// on the caller's stream; measured faster than automatic splitting for
+// equal-size batches, whose CG phases then overlap poorly).
+int lane_count(const pins_params& p, int count, bool host_api) {
+    if (host_api || count < 2) return 1;
+    int g = p.streams > 1 ? p.streams : 1;
+    g = std::max(1, std::min({g, 4, count}));
+    return g;
+}
+
+int solve_entry(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params& p, pins_result* res,
+                hipStream_t st, bool host_api) {
+    if (count < 1) fail(PINS_EINVAL, "count must be >= 1");
+    if (!probs || !res) fail(PINS_EINVAL, "problems and results are required");
+    check_params(p);
+    const int G = lane_count(p, count, host_api);
+    if (G == 1) return solve_impl(lane(ctx, 0), probs, count, p, res, st, host_api);
+    for (int q = 0; q < count; ++q) check_problem_shape(probs[q]);
+    // contiguous groups of (nearly) equal instance count
+    std::vector<int> start(G + 1);
+    for (int g = 0; g <= G; ++g) start[g] = (int)(((long)count * g) / G);
+    // the lanes start after the caller's stream has produced the inputs
+    HIPCHK(hipSetDevice(ctx->device));
+    hipEvent_t ready;
+    HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ready, st));
+    std::vector<Lane*> L(G);
+    for (int g = 0; g < G; ++g) {
+        L[g] = lane(ctx, g + 1);
+        HIPCHK(hipStreamWaitEvent(L[g]->stream, ready, 0));
+    }
+    std::vector<int> rc(G, PINS_OK);
+    std::vector<std::string> msg(G);
+    std::vector<std::thread> th;
+    for (int g = 0; g < G; ++g) {
+        const int a = start[g], b = start[g + 1];
+        if (a >= b) continue;
+        th.emplace_back([&, g, a, b] {
+            try {
+                HIPCHK(hipSetDevice(ctx->device));
+                rc[g] = solve_impl(L[g], probs + a, b - a, p, res + a, L[g]->stream, false);
+                for (int q = a; q < b; ++q) res[q].group = g;
+            } catch (const Fail& f) {
+                rc[g] = f.code;
+                msg[g] = f.msg;
+            } catch (const HipError& e) {
+                rc[g] = PINS_EDEVICE;
+                msg[g] = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
+            } catch (...) {
+                rc[g] = PINS_EDEVICE;
+                msg[g] = "unexpected internal error";
+            }
+        });
+    }
+    for (auto& t : th) t.join();
+    (void)hipEventDestroy(ready);
+    int worst = PINS_OK;
+    for (int g = 0; g < G; ++g) {
+        if (rc[g] < 0) fail(rc[g], msg[g]);
+        worst = std::max(worst, rc[g]);
     }
     return worst;
 }
@@ -621,12 +716,13 @@ void pins_params_default(pins_params* p) {
     p->ls_beta = 0.5;
     p->ls_c1 = 1e-4;
     p->ls_max = 30;
-    p->rho_levels = 13;
-    p->rho = 1e-9;
+    p->rho_levels = 11;
+    p->rho = 1e-7;
     p->budget = 64.0;
     p->precision = PINS_FP64;
     p->shift_mode = PINS_SHIFT_IMPLICIT;
     p->profile = 0;
+    p->streams = 0;
 }
 
 int pins_create(int device, pins_ctx** out) {
@@ -647,9 +743,7 @@ int pins_create(int device, pins_ctx** out) {
 void pins_destroy(pins_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
-    if (c->ws) (void)hipFree(c->ws);
-    if (c->pinned) (void)hipHostFree(c->pinned);
+    for (Lane* L : c->lanes) free_lane(L);
     delete c;
 }
 
@@ -672,7 +766,7 @@ int pins_workspace_bytes(const pins_problem* probs, int count, const pins_params
 int pins_solve(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res) {
     return guarded(ctx, [&] {
         if (!prob || !p || !res) fail(PINS_EINVAL, "null argument");
-        return solve_impl(ctx, prob, 1, *p, res, nullptr, true);
+        return solve_entry(ctx, prob, 1, *p, res, nullptr, true);
     });
 }
 
@@ -680,7 +774,7 @@ int pins_solve_device(pins_ctx* ctx, const pins_problem* prob, const pins_params
                       void* stream) {
     return guarded(ctx, [&] {
         if (!prob || !p || !res) fail(PINS_EINVAL, "null argument");
-        return solve_impl(ctx, prob, 1, *p, res, (hipStream_t)stream, false);
+        return solve_entry(ctx, prob, 1, *p, res, (hipStream_t)stream, false);
     });
 }
 
@@ -688,7 +782,7 @@ int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count,
                             pins_result* res, void* stream) {
     return guarded(ctx, [&] {
         if (!probs || !p || !res) fail(PINS_EINVAL, "null argument");
-        return solve_impl(ctx, probs, count, *p, res, (hipStream_t)stream, false);
+        return solve_entry(ctx, probs, count, *p, res, (hipStream_t)stream, false);
     });
 }
 

@@ -75,15 +75,15 @@ struct Ctrl {
     int phase, t, ticket, ls_state;
     int level, nnz, ls_h, flags;
     int sink_total, newton_total, cg_total, fb_total;
-    int last_cg, ticket2, nonfinite, pad;
+    int last_cg, fused, nonfinite, grad_ready;  // fused: the Armijo pass also produced the next gradient
     double kappa, err, resid, alpha;
     double gd, dab, fa, cost;
     double entropy, dual, scale, pad2;
-    double work[8];  // matrix entries visited per pass kind (W_* below)
+    double work[8];  // matrix entries visited per pass kind (W_* below); W_CG: stored entries read by CG
 };
 
 // pass kinds counted in Ctrl::work
-enum WorkKind : int { W_ROW = 0, W_COL = 1, W_GRAD = 2, W_FILL = 3, W_FILLC = 4, W_LS = 5, W_FINAL = 6 };
+enum WorkKind : int { W_ROW = 0, W_COL = 1, W_GRAD = 2, W_FILL = 3, W_CG = 4, W_LS = 5, W_FINAL = 6 };
 
 // Kernel-wide parameters (passed by value).
 struct KP {

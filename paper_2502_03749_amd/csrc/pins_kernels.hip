@@ -80,16 +80,51 @@ __device__ __forceinline__ double lev_q(double x, double log_rho, double la, dou
 // reductions
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Cross-lane moves through DPP (data-parallel primitives, no LDS round trip).
+// CTRL: 0xB1 quad_perm [1,0,3,2] (lane ^ 1), 0x4E quad_perm [2,3,0,1]
+// (lane ^ 2), 0x141 row_half_mirror (lane i <-> 7-i within 8), 0x140
+// row_mirror (i <-> 15-i within 16).  Each pairs lanes symmetrically, so a
+// sum step gives every lane of the group the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+// sum over aligned groups of G lanes (G = 2, 4, 8, 16); every lane of the group gets it
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    if (G >= 2) v += dpp_f64<0xB1>(v);
+    if (G >= 4) v += dpp_f64<0x4E>(v);
+    if (G >= 8) v += dpp_f64<0x141>(v);
+    if (G >= 16) v += dpp_f64<0x140>(v);
     return v;
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes of a wave, broadcast (fixed order: 16-lane rows, then rows 0..3)
+__device__ __forceinline__ double wave_sum(double v) {
+    v = group_sum<16>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 __device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_i32<0xB1>(v);
+    v += dpp_i32<0x4E>(v);
+    v += dpp_i32<0x141>(v);
+    v += dpp_i32<0x140>(v);
+    return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+           (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
 // (max, sum) pairs of log-sum-exp; an empty pair is (-inf, 0).
@@ -109,14 +144,46 @@ __device__ __forceinline__ void lse_combine(double& mx, T& sm, double m2, T s2) 
     sm = u + v;
 }
 
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp_t(T v);
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp_t(T v) {
+    if constexpr (sizeof(T) == 8) {
+        return dpp_f64<CTRL>(v);
+    } else {
+        return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+    }
+}
+
+template <int CTRL, class T>
+__device__ __forceinline__ void lse_step(double& mx, T& sm) {
+    const double m2 = dpp_f64<CTRL>(mx);
+    const T s2 = dpp_t<CTRL>(sm);
+    lse_combine(mx, sm, m2, s2);
+}
+
+template <class T>
+__device__ __forceinline__ T readlane_t(T v, int lane) {
+    if constexpr (sizeof(T) == 8) {
+        return readlane_f64(v, lane);
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    }
+}
+
+// (max, sum) combine over a wave (in-row DPP steps, then rows 0..3 in order);
+// every lane gets the same pair
 template <class T>
 __device__ __forceinline__ void wave_lse(double& mx, T& sm) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const double m2 = __shfl_xor(mx, o);
-        const T s2 = __shfl_xor(sm, o);
-        lse_combine(mx, sm, m2, s2);
-    }
+    lse_step<0xB1>(mx, sm);
+    lse_step<0x4E>(mx, sm);
+    lse_step<0x141>(mx, sm);
+    lse_step<0x140>(mx, sm);
+    double M = readlane_f64(mx, 0);
+    T S = readlane_t(sm, 0);
+    for (int r = 16; r < 64; r += 16) lse_combine(M, S, readlane_f64(mx, r), readlane_t(sm, r));
+    mx = M;
+    sm = S;
 }
 
 // Sum over a block of NT threads, result broadcast to all; fixed order.
@@ -132,6 +199,29 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
     for (int k = 0; k < NW; ++k) t += sh[k];
     return t;
+}
+
+// Two sums over a block at once (one pair of barriers).
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+    constexpr int NW = NT / 64;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) {
+        sh[w] = a;
+        sh[NW + w] = b;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        ta += sh[k];
+        tb += sh[NW + k];
+    }
+    a = ta;
+    b = tb;
 }
 
 // Sum of p[0..len) by a block of NT threads in a fixed order.
@@ -358,6 +448,34 @@ __global__ __launch_bounds__(256) void k_col_merge(const DevInst* __restrict__ i
     }
 }
 
+// Row sums of a tile: red[r][tid] holds each thread's entry of row r; 16
+// threads per row add 16 columns each, then a 16-lane DPP sum.
+__device__ __forceinline__ void tile_row_sums(double (*red)[TILE_C + 1], int rows, int i0, int cb, int m,
+                                              double* __restrict__ part2) {
+    const int r = threadIdx.x >> 4, s = threadIdx.x & 15;
+    double v = 0.0;
+    if (r < rows)
+        for (int k = 0; k < 16; ++k) v += red[r][s * 16 + k];
+    v = group_sum<16>(v);
+    if (r < rows && s == 0) part2[(long)cb * m + i0 + r] = v;
+}
+
+// Per-level totals of a tile (hcol[l][thread]) added to the instance histogram.
+__device__ __forceinline__ void tile_level_totals(const int* hcol, int nlev, int* __restrict__ hist) {
+    __shared__ int wl[NLEV][4];
+    const int w = threadIdx.x >> 6;
+    for (int l = 0; l < nlev; ++l) {
+        const int v = wave_sum_i(hcol[l * TILE_C + threadIdx.x]);
+        if ((threadIdx.x & 63) == 0) wl[l][w] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nlev) {
+        const int l = threadIdx.x;
+        const int v = wl[l][0] + wl[l][1] + wl[l][2] + wl[l][3];
+        if (v) atomicAdd(&hist[l], v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a5: Newton pass.  Tile = R rows x 256 columns.  Xt_ij of eq. (eppa_x);
 // column partials part[rb][j], row partials part2[cb][i], and the Sparsify
@@ -366,7 +484,7 @@ __global__ __launch_bounds__(256) void k_col_merge(const DevInst* __restrict__ i
 template <class Src>
 __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.y;
-    if (ctrl[b].phase != PH_NEWTON) return;
+    if (ctrl[b].phase != PH_NEWTON || ctrl[b].grad_ready) return;
     const DevInst& I = insts[b];
     const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
     if (rb >= I.nrb) return;
@@ -405,31 +523,8 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
     }
     if (valid) I.part[(long)rb * n + j] = colacc;
     __syncthreads();
-    // row sums: 16 threads per row, 16 columns each, then a 16-lane butterfly
-    {
-        const int r = threadIdx.x >> 4, s = threadIdx.x & 15;
-        double v = 0.0;
-        if (r < rows)
-            for (int k = 0; k < 16; ++k) v += red[r][s * 16 + k];
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (r < rows && s == 0) I.part2[(long)cb * m + i0 + r] = v;
-    }
-    // per-level totals of the tile into the instance histogram (integer adds)
-    {
-        __shared__ int wl[NLEV][4];
-        const int w = threadIdx.x >> 6;
-        for (int l = 0; l < nlev; ++l) {
-            const int v = wave_sum_i(hcol[l * TILE_C + threadIdx.x]);
-            if ((threadIdx.x & 63) == 0) wl[l][w] = v;
-        }
-        __syncthreads();
-        if ((int)threadIdx.x < nlev) {
-            const int l = threadIdx.x;
-            const int v = wl[l][0] + wl[l][1] + wl[l][2] + wl[l][3];
-            if (v) atomicAdd(&I.hist[l], v);
-        }
-    }
+    tile_row_sums(red, rows, i0, cb, m, I.part2);
+    tile_level_totals(hcol, nlev, I.hist);
 }
 
 // Gradient merge: r = Xt e, c = Xt^T e into rc; the last block tests
@@ -508,6 +603,7 @@ __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ 
     }
     __syncthreads();
     if ((int)threadIdx.x < NLEV) I.hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) S.grad_ready = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -667,70 +763,104 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
 // by 16-lane groups per row/column gathering p from LDS.  Afterwards the
 // line-search inputs <grad P, d>, <a,dF>+<b,dG> and the resolution test.
 // ---------------------------------------------------------------------------
-// One row of M's off-diagonal part (S v for k < m, S^T u for k >= m), summed
-// by a group of G lanes with four independent loads in flight per lane.
+// Off-diagonal part of M times p for two rows at once (S v for a row k < m,
+// S^T u for k >= m), each by a group of G lanes.  Every lane issues its U
+// index and U value loads for both rows before using any of them (predicated
+// past the row end), so 4U loads are in flight per lane and a row of up to
+// U*G entries costs one memory round trip.  ptr arrays: CSR row pointers
+// (rp, m+1) and CSC column pointers (cp, n+1), in LDS or global memory.
 template <int G>
-__device__ __forceinline__ double spmv_row(const DevInst& I, int m, int k, const double* __restrict__ pv, int lg) {
-    int q0, q1, off;
-    const int* __restrict__ idx;
-    const double* __restrict__ v;
-    if (k < m) {
-        q0 = I.rowptr[k];
-        q1 = I.rowptr[k + 1];
-        idx = I.col;
-        v = I.val;
-        off = m;
-    } else {
-        q0 = I.colptr[k - m];
-        q1 = I.colptr[k - m + 1];
-        idx = I.rowT;
-        v = I.valT;
-        off = 0;
+__device__ __forceinline__ void spmv_pair(const DevInst& I, int m, int N, int kA, int kB, const int* rp,
+                                          const int* cp, const double* __restrict__ pv, double* __restrict__ out,
+                                          int lg) {
+    constexpr int U = 4;
+    int qa = 0, ea = 0, qb = 0, eb = 0;
+    const int* ia = I.col;
+    const double* va = I.val;
+    const int* ib = I.col;
+    const double* vb = I.val;
+    int oa = m, ob = m;
+    if (kA < N) {
+        if (kA < m) {
+            qa = rp[kA];
+            ea = rp[kA + 1];
+        } else {
+            qa = cp[kA - m];
+            ea = cp[kA - m + 1];
+            ia = I.rowT;
+            va = I.valT;
+            oa = 0;
+        }
     }
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int q = q0 + lg;
-    for (; q + 3 * G < q1; q += 4 * G) {
-        const int i0 = ldg(idx + q), i1 = ldg(idx + q + G), i2 = ldg(idx + q + 2 * G), i3 = ldg(idx + q + 3 * G);
-        const double v0 = ldg(v + q), v1 = ldg(v + q + G), v2 = ldg(v + q + 2 * G), v3 = ldg(v + q + 3 * G);
-        s0 += v0 * pv[off + i0];
-        s1 += v1 * pv[off + i1];
-        s2 += v2 * pv[off + i2];
-        s3 += v3 * pv[off + i3];
+    if (kB < N) {
+        if (kB < m) {
+            qb = rp[kB];
+            eb = rp[kB + 1];
+        } else {
+            qb = cp[kB - m];
+            eb = cp[kB - m + 1];
+            ib = I.rowT;
+            vb = I.valT;
+            ob = 0;
+        }
     }
-    for (; q < q1; q += G) s0 += ldg(v + q) * pv[off + ldg(idx + q)];
-    double s = (s0 + s1) + (s2 + s3);
+    qa += lg;
+    qb += lg;
+    double sa = 0.0, sb = 0.0;
+    while (qa < ea || qb < eb) {
+        int xa[U], xb[U];
+        double wa[U], wb[U];
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    return s;
+        for (int u = 0; u < U; ++u) {
+            const int q1 = qa + u * G, q2 = qb + u * G;
+            const bool ok1 = q1 < ea, ok2 = q2 < eb;
+            xa[u] = ok1 ? ldg(ia + q1) : 0;
+            wa[u] = ok1 ? ldg(va + q1) : 0.0;
+            xb[u] = ok2 ? ldg(ib + q2) : 0;
+            wb[u] = ok2 ? ldg(vb + q2) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            sa += wa[u] * pv[oa + xa[u]];
+            sb += wb[u] * pv[ob + xb[u]];
+        }
+        qa += U * G;
+        qb += U * G;
+    }
+    sa = group_sum<G>(sa);
+    sb = group_sum<G>(sb);
+    if (lg == 0) {
+        if (kA < N) out[kA] = sa;
+        if (kB < N) out[kB] = sb;
+    }
 }
 
-// S v / S^T u for all N rows by groups of G lanes; results into out[k].
 template <int G>
-__device__ __forceinline__ void spmv_all(const DevInst& I, int m, int N, const double* __restrict__ pv,
-                                         double* __restrict__ out) {
+__device__ __forceinline__ void spmv_all(const DevInst& I, int m, int N, const int* rp, const int* cp,
+                                         const double* __restrict__ pv, double* __restrict__ out) {
     constexpr int NG = 1024 / G;
     const int g = threadIdx.x / G, lg = threadIdx.x % G;
-    for (int k = g; k < N; k += NG) {
-        const double s = spmv_row<G>(I, m, k, pv, lg);
-        if (lg == 0) out[k] = s;
-    }
+    for (int k = g; k < N; k += 2 * NG) spmv_pair<G>(I, m, N, k, k + NG, rp, cp, pv, out, lg);
 }
 
-__device__ __forceinline__ void spmv_dispatch(const DevInst& I, int m, int N, int nnz, const double* __restrict__ pv,
-                                              double* __restrict__ out) {
-    // lanes per row from the average row length (2 nnz entries per coupling, N rows)
+// lanes per row: about a quarter of the average row length (2 nnz entries
+// over N rows), so a typical row is read in one round of 4 loads per lane
+__device__ __forceinline__ void spmv_dispatch(const DevInst& I, int m, int N, int nnz, const int* rp, const int* cp,
+                                              const double* __restrict__ pv, double* __restrict__ out) {
     const int avg = (2 * nnz) / (N > 0 ? N : 1);
-    if (avg <= 24)
-        spmv_all<4>(I, m, N, pv, out);
-    else if (avg <= 96)
-        spmv_all<8>(I, m, N, pv, out);
+    if (avg <= 16)
+        spmv_all<4>(I, m, N, rp, cp, pv, out);
+    else if (avg <= 32)
+        spmv_all<8>(I, m, N, rp, cp, pv, out);
     else
-        spmv_all<16>(I, m, N, pv, out);
+        spmv_all<16>(I, m, N, rp, cp, pv, out);
 }
 
 __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp) {
     S.last_cg = it;
     S.cg_total += it;
+    S.work[W_CG] += 2.0 * (double)S.nnz * (double)it;
+    S.fused = 0;
     S.gd = gd;
     S.dab = dab;
     S.fa = fa;
@@ -753,8 +883,18 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     const int m = I.m, n = I.n, N = m + n;
     __shared__ double sp[1024 * EPT];
     __shared__ double sAp[1024 * EPT];
-    __shared__ double sh[16];
+    __shared__ double sh[32];
+    constexpr bool PTR_LDS = EPT <= 4;  // row/column pointers staged in LDS when they fit
+    __shared__ int sptr[PTR_LDS ? 1024 * EPT + 2 : 1];
     const int tid = threadIdx.x;
+    const int* rp = I.rowptr;
+    const int* cp = I.colptr;
+    if (PTR_LDS) {
+        for (int k = tid; k <= m; k += 1024) sptr[k] = I.rowptr[k];
+        for (int k = tid; k <= n; k += 1024) sptr[m + 1 + k] = I.colptr[k];
+        rp = sptr;
+        cp = sptr + m + 1;
+    }
     const double eta = kp.eta;
     // register-resident iterate x, residual r, direction p and diagonal dg
     double x[EPT], r[EPT], p[EPT], dg[EPT];
@@ -783,7 +923,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     if (bn > 0.0) {
         while (it < kp.cg_max) {
             __syncthreads();
-            spmv_dispatch(I, m, N, nnz, sp, sAp);
+            spmv_dispatch(I, m, N, nnz, rp, cp, sp, sAp);
             __syncthreads();
             double pap = 0.0;
 #pragma unroll
@@ -809,8 +949,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
                     rz2 += r[t] * (r[t] / dg[t]);
                 }
             }
-            rr = block_sum<1024>(rr, sh);
-            rz2 = block_sum<1024>(rz2, sh);
+            block_sum2<1024>(rr, rz2, sh);
             ++it;
             if (sqrt(rr) <= kp.cg_rtol * bn) break;
             const double be = rz2 / rz;
@@ -855,7 +994,7 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     double* __restrict__ p = I.cgw + 2 * N;
     double* __restrict__ Ap = I.cgw + 3 * N;
     const double* __restrict__ dg = I.rc;
-    __shared__ double sh[16];
+    __shared__ double sh[32];
     const double eta = kp.eta;
     double bb = 0.0, rz = 0.0;
     for (int k = threadIdx.x; k < N; k += 1024) {
@@ -876,7 +1015,7 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     if (bn > 0.0) {
         while (it < kp.cg_max) {
             __syncthreads();
-            spmv_dispatch(I, m, N, nnz, p, Ap);
+            spmv_dispatch(I, m, N, nnz, I.rowptr, I.colptr, p, Ap);
             __syncthreads();
             double pap = 0.0;
             for (int k = threadIdx.x; k < N; k += 1024) {
@@ -897,8 +1036,7 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
                 rr += rk * rk;
                 rz2 += rk * zk;
             }
-            rr = block_sum<1024>(rr, sh);
-            rz2 = block_sum<1024>(rz2, sh);
+            block_sum2<1024>(rr, rz2, sh);
             ++it;
             if (sqrt(rr) <= kp.cg_rtol * bn) break;
             const double be = rz2 / rz;
@@ -925,6 +1063,81 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
 //   P(f+al df, g+al dg) - P(f,g) = al(<a,df>+<b,dg>) - eta sum_ij Xt_ij expm1(al(df_i+dg_j)/eta)
 // accept the first al = beta^h with increase >= c1*al*<grad P, d>.
 // ---------------------------------------------------------------------------
+// First Armijo trial (alpha = 1), fused with the next Newton pass: with
+// e = Xt_ij and t = e*expm1(delta_ij), Xt at the trial point is e + t, whose
+// row/column sums and Sparsify histogram are exactly what the next k_grad
+// would compute if the full step is accepted.
+template <class Src>
+__global__ __launch_bounds__(256) void k_ls_first(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+                                                  KP kp) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON || ctrl[b].ls_state != LS_PENDING) return;
+    const DevInst& I = insts[b];
+    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
+    if (rb >= I.nrb) return;
+    const int m = I.m, n = I.n;
+    count_work(ctrl, b, W_LS, m, n);
+    const int i0 = rb * I.R, rows = min(I.R, m - i0);
+    __shared__ int hcol[NLEV * TILE_C];
+    __shared__ double red[TILE_RMAX][TILE_C + 1];
+    __shared__ double sF[TILE_RMAX], sD[TILE_RMAX], sLa[TILE_RMAX];
+    for (int l = 0; l < NLEV; ++l) hcol[l * TILE_C + threadIdx.x] = 0;
+    if ((int)threadIdx.x < rows) {
+        sF[threadIdx.x] = I.F[i0 + threadIdx.x];
+        sD[threadIdx.x] = I.d[i0 + threadIdx.x];
+        sLa[threadIdx.x] = I.loga[i0 + threadIdx.x];
+    }
+    __syncthreads();
+    const int j = cb * TILE_C + threadIdx.x;
+    const bool valid = j < n;
+    const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
+    const int nlev = kp.nlev;
+    const Src src(I);
+    double acc = 0.0, colacc = 0.0;
+    const double Gj = valid ? ldg(I.G + j) : 0.0, dGj = valid ? ldg(I.d + m + j) : 0.0;
+    const double lbj = valid ? ldg(I.logb + j) : 0.0;
+    for (int r = 0; r < rows; ++r) {
+        double e1 = 0.0;
+        if (valid) {
+            const double x = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
+            const double e = exp(x);
+            const double del = (sD[r] + dGj) * ie;
+            const double t = e * expm1(del);
+            acc += t;
+            e1 = e + t;
+            const double q = lev_q(x + del, lrho, sLa[r], lbj);
+            if (q >= 0.0) {
+                const int l = (q >= (double)(nlev - 1)) ? nlev - 1 : (int)q;
+                hcol[l * TILE_C + threadIdx.x] += 1;
+            }
+        }
+        colacc += e1;
+        red[r][threadIdx.x] = e1;
+    }
+    if (valid) I.part[(long)rb * n + j] = colacc;
+    __syncthreads();
+    tile_row_sums(red, rows, i0, cb, m, I.part2);
+    tile_level_totals(hcol, nlev, I.hist);
+    __shared__ double sh[4];
+    const int nblk = I.nrb * I.ncb;
+    const double bs = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) I.blk[blockIdx.x] = bs;
+    if (!last_block(&ctrl[b].ticket, nblk)) return;
+    const double tot = block_sum_array<256>(I.blk, nblk, sh);
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        const double inc = S.dab - kp.eta * tot;
+        if (inc >= kp.ls_c1 * S.gd) {
+            S.alpha = 1.0;
+            S.ls_state = LS_ACCEPTED;
+            S.fused = 1;
+        } else {
+            S.ls_h = 1;
+            if (S.ls_h >= kp.ls_max) S.ls_state = LS_FAILED;
+        }
+    }
+}
+
 template <class Src, int NT>
 __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.y;
@@ -1014,6 +1227,8 @@ __global__ __launch_bounds__(1024) void k_update(const DevInst* __restrict__ ins
     const int m = I.m, N = I.m + I.n;
     const int st = ctrl[b].ls_state;
     const double al = ctrl[b].alpha;
+    const bool ready = st == LS_ACCEPTED && ctrl[b].fused;
+    if (!ready && (int)threadIdx.x < NLEV) I.hist[threadIdx.x] = 0;  // discard a rejected trial's histogram
     if (st == LS_ACCEPTED)
         for (int k = threadIdx.x; k < N; k += 1024) {
             if (k < m)
@@ -1026,6 +1241,7 @@ __global__ __launch_bounds__(1024) void k_update(const DevInst* __restrict__ ins
         Ctrl& S = ctrl[b];
         S.t += 1;
         S.newton_total += 1;
+        S.grad_ready = ready ? 1 : 0;
         if (st != LS_ACCEPTED) {
             S.phase = PH_FALLBACK;
             S.fb_total += 1;
@@ -1272,8 +1488,7 @@ __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts
         double v = 0.0;
         if (r < rows)
             for (int k = 0; k < 16; ++k) v += red[r][s * 16 + k];
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        v = group_sum<16>(v);
         if (r < rows && s == 0) I.part2[(long)cb * m + i0 + r] = v;
     }
     cst = block_sum<256>(cst, sh);
@@ -1405,13 +1620,15 @@ void launch_pcg(const LaunchCtx& L) {
 
 void launch_ls(const LaunchCtx& L, int src, bool first) {
     const dim3 g = g2(L.max_tiles, L.count);
-#define K_(S, NT) hipLaunchKernelGGL((k_ls<S, NT>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
     if (first) {
-        PINS_SRC_DISPATCH(src, K_, 1);
-    } else {
-        PINS_SRC_DISPATCH(src, K_, LS_T);
-    }
+#define K_(S) hipLaunchKernelGGL((k_ls_first<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+        PINS_SRC_DISPATCH(src, K_);
 #undef K_
+    } else {
+#define K_(S, NT) hipLaunchKernelGGL((k_ls<S, NT>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+        PINS_SRC_DISPATCH(src, K_, LS_T);
+#undef K_
+    }
 }
 
 void launch_update(const LaunchCtx& L) {

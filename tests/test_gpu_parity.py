@@ -189,6 +189,29 @@ def test_batch_equals_alone(ctx):
         assert rs[q]["newton_iters"] == g["newton_iters"] and rs[q]["cg_iters"] == g["cg_iters"]
 
 
+def test_multi_lane_batch_equals_alone(ctx):
+    """A batch split over three concurrent lanes (own streams and host threads)
+    gives every instance bitwise the result it gets alone."""
+    print("case multi-lane batch", flush=True)
+    shapes = [(40, 30), (64, 64), (7, 90), (120, 33), (50, 50), (9, 9), (200, 150)]
+    probs, outs, hosts = [], [], []
+    prm = P.params(eta=0.03, max_outer=5, streams=3)
+    for q, (m, n) in enumerate(shapes):
+        C, a, b = _rand(m, n, 900 + q)
+        hosts.append((C, a, b))
+        probs.append(dict(kind=P.COST_DENSE, m=m, n=n, C=_t(C), a=_t(a), b=_t(b), cost_scale=1.0))
+        outs.append(dict(alpha=torch.empty(m, dtype=torch.float64, device=DEV),
+                         beta=torch.empty(n, dtype=torch.float64, device=DEV)))
+    rc, rs = ctx.solve_batch_device(probs, prm, outs, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert rc == 0
+    assert len({r["group"] for r in rs}) == 3
+    for q, (C, a, b) in enumerate(hosts):
+        g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), P.params(eta=0.03, max_outer=5), want_plan=False)
+        assert rs[q]["cost"] == g["cost"], q
+        assert np.array_equal(outs[q]["alpha"].cpu().numpy(), g["alpha"]), q
+
+
 def test_deterministic(ctx):
     print("case determinism", flush=True)
     C, a, b = _rand(90, 70, 3)
