@@ -74,7 +74,26 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-launch HIP events")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Five launches of torch's device-to-device copy of a known size; prints the bytes per launch."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    x = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    print(json.dumps(dict(copy_calibration=True, read_bytes_per_launch=8 * n, write_bytes_per_launch=8 * n,
+                          launches=5)), flush=True)
 
 
 def main():
@@ -84,6 +103,9 @@ def main():
               "this build has no multi-GPU path (see the design notes for how it would shard); "
               "run with --gpus 1.", file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch
