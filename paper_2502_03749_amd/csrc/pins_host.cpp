@@ -79,7 +79,7 @@ struct Carver {
 struct InstPlan {
     int m, n, d, R, nrb, ncb, cap;
     size_t loga, logb, F, G, Ah, Bh, rc, dir, cgw, part, part2, blk, blk2, hist, rowptr, col, val, colptr,
-        rowT, valT, cntr, cntc, Ck, Cpts;
+        rowT, valT, rowbin, cntr, cntc, Ck, Cpts;
     size_t C, x, y, a, b, alpha, beta, X;  // host-API staging
 };
 
@@ -99,7 +99,8 @@ InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, 
     q.R = std::min(TILE_RMAX, m);
     q.nrb = (m + q.R - 1) / q.R;
     q.ncb = (n + TILE_C - 1) / TILE_C;
-    q.cap = (int)nnz_capacity(m, n, p.budget);
+    // kept entries plus up to 3 pads per row of S or S^T, rounded to quads
+    q.cap = (int)(((nnz_capacity(m, n, p.budget) + 3L * std::max(m, n)) + 3) & ~3L);
     const long tiles = (long)q.nrb * q.ncb;
     const long nblk = std::max({tiles, (long)(m + 3) / 4, (long)(N + 255) / 256});
     q.loga = cv.take(m * D);
@@ -124,6 +125,7 @@ InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, 
     q.colptr = cv.take((n + 1) * I4);
     q.rowT = cv.take((size_t)q.cap * I4);
     q.valT = cv.take((size_t)q.cap * D);
+    q.rowbin = cv.take((size_t)N * I4);
     q.Ck = (p.shift_mode == PINS_SHIFT_MATERIALIZED) ? cv.take((size_t)m * n * D) : NONE;
     q.Cpts = (P.kind == PINS_COST_POINTS) ? cv.take((size_t)m * n * D) : NONE;
     q.C = q.x = q.y = q.a = q.b = q.alpha = q.beta = q.X = NONE;
@@ -401,7 +403,8 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         I.val = Dp(L.val);
         I.colptr = Ip(L.colptr);
         I.rowT = Ip(L.rowT);
-        I.valT = Dp(L.valT);
+        I.valT = Dp(L.valT);  // reinterpreted by the kernels per LaunchCtx::sp_fmt
+        I.rowbin = Ip(L.rowbin);
         if (host_api) {
             I.alpha = Dp(L.alpha);
             I.beta = Dp(L.beta);
@@ -431,6 +434,9 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     L.max_n = B.max_n;
     L.max_mn = B.max_mn;
     L.max_tiles = B.max_tiles;
+    // the CG's copy of S: 16-bit indices whenever they fit, float values in
+    // mixed precision (the CG vectors and all sums stay double)
+    L.sp_fmt = ((B.max_m <= 65536 && B.max_n <= 65536) ? 1 : 0) | (p.precision == PINS_MIXED ? 2 : 0);
     KP& kp = L.kp;
     std::memset(&kp, 0, sizeof(kp));
     kp.eta = p.eta;

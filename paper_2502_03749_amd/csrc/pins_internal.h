@@ -22,6 +22,7 @@ constexpr int NLEV = 16;     // maximum number of Sparsify levels
 constexpr int LS_T = 8;      // trial step sizes per line-search pass (after the first)
 constexpr int TILE_C = 256;  // columns per tile (one per thread)
 constexpr int TILE_RMAX = 16;  // maximum rows per tile
+constexpr int NBIN = 6;        // CG row bins: <= 1, 2, 4, 8, 16 and more quads
 
 enum Phase : int { PH_DONE = 0, PH_WARM = 1, PH_NEWTON = 2, PH_FALLBACK = 3 };
 enum LsState : int { LS_PENDING = 0, LS_ACCEPTED = 1, LS_FAILED = 2 };
@@ -58,12 +59,19 @@ struct DevInst {
     int* hist;      // NLEV Sparsify histogram (entries per highest kept level)
     int* cntr;      // m * ncb kept entries per (row, column block) at the chosen level
     int* cntc;      // nrb * n kept entries per (row block, column) at the chosen level
+    // S (CSR) and S^T (CSC).  Every row of S and of S^T starts at a multiple
+    // of 4 entries and is padded to one with (index 0, value 0), so the CG
+    // reads them in aligned quads.  Index arrays hold uint16 when every index
+    // of the batch is < 65536, else int32; value arrays hold float in mixed
+    // precision, else double (the launch chooses; the buffers are sized for
+    // int32/double).  nnz_cap (a multiple of 4) includes the padding.
     int* rowptr;    // m+1
-    int* col;       // nnz_cap
-    double* val;    // nnz_cap
+    void* col;      // nnz_cap column indices of S
+    void* val;      // nnz_cap values of S
     int* colptr;    // n+1
-    int* rowT;      // nnz_cap
-    double* valT;   // nnz_cap
+    void* rowT;     // nnz_cap row indices of S^T
+    void* valT;     // nnz_cap values of S^T
+    int* rowbin;    // m+n rows of M = [. S; S^T .] grouped by quad count (NBIN bins)
     double* Ck;     // materialised shifted cost (m*n) or nullptr
     double* alpha;  // outputs
     double* beta;
@@ -80,6 +88,7 @@ struct Ctrl {
     double gd, dab, fa, cost;
     double entropy, dual, scale, pad2;
     double work[8];  // matrix entries visited per pass kind (W_* below); W_CG: stored entries read by CG
+    int binoff[8];   // rowbin offsets of the NBIN bins (binoff[NBIN] = m+n)
 };
 
 // pass kinds counted in Ctrl::work

@@ -103,6 +103,7 @@ __device__ __forceinline__ double group_sum(double v) {
     if (G >= 4) v += dpp_f64<0x4E>(v);
     if (G >= 8) v += dpp_f64<0x141>(v);
     if (G >= 16) v += dpp_f64<0x140>(v);
+    if (G >= 32) v += __shfl_xor(v, 16);
     return v;
 }
 
@@ -134,6 +135,31 @@ template <>
 __device__ __forceinline__ double ex<double>(double y) { return exp(y); }
 template <>
 __device__ __forceinline__ float ex<float>(double y) { return __expf((float)y); }
+
+// exp(x) in double by Tang's table-driven method (P. T. P. Tang, ACM TOMS
+// 15(2), 1989): x = (64k + j) ln2/64 + r with |r| <= ln2/128, so that
+// exp(x) = 2^k 2^(j/64) (1 + q) with q = e^r - 1 from its degree-5 Taylor
+// polynomial (truncation below 4e-17 relative).  T holds 2^(j/64),
+// j = 0..63, in LDS (texp_table).  About 1 ulp; x < -746 gives 0, x > 710
+// gives inf, NaN stays NaN.
+__device__ __forceinline__ void texp_table(double* T) {
+    if (threadIdx.x < 64) T[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 64.0));
+}
+__device__ __forceinline__ double texp(double x, const double* T) {
+    x = (x < -746.0) ? -746.0 : x;
+    x = (x > 710.0) ? 710.0 : x;
+    const double nd = rint(x * 92.33248261689366);   // 64 / ln 2
+    const int nk = (int)nd;
+    double r = fma(-nd, 0x1.62e42fefa39efp-7, x);    // ln 2 / 64, leading part
+    r = fma(-nd, 0x1.abc9e3b39803fp-62, r);          // ln 2 / 64, trailing part
+    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    q *= r;
+    const double tj = T[nk & 63];
+    return ldexp(fma(tj, q, tj), nk >> 6);
+}
 
 template <class T>
 __device__ __forceinline__ void lse_combine(double& mx, T& sm, double m2, T s2) {
@@ -448,39 +474,49 @@ __global__ __launch_bounds__(256) void k_col_merge(const DevInst* __restrict__ i
     }
 }
 
-// Row sums of a tile: red[r][tid] holds each thread's entry of row r; 16
-// threads per row add 16 columns each, then a 16-lane DPP sum.
-__device__ __forceinline__ void tile_row_sums(double (*red)[TILE_C + 1], int rows, int i0, int cb, int m,
-                                              double* __restrict__ part2) {
-    const int r = threadIdx.x >> 4, s = threadIdx.x & 15;
-    double v = 0.0;
-    if (r < rows)
-        for (int k = 0; k < 16; ++k) v += red[r][s * 16 + k];
-    v = group_sum<16>(v);
-    if (r < rows && s == 0) part2[(long)cb * m + i0 + r] = v;
+// Row totals of a tile without a tile-sized LDS array.  v[u] is this
+// thread's entry of row r0 + u.  Two exchanges across wave halves (xor 32,
+// xor 16) and a 16-lane DPP sum leave the wave's total of row r0 + (lane >> 4)
+// in lanes 0, 16, 32 and 48, which store it to wsum[row][wave].  Fixed order.
+__device__ __forceinline__ void wave_rows4(const double (&v)[4], int r0, double (*wsum)[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const bool h32 = lane >= 32, h16 = (lane & 16) != 0;
+    double a0 = h32 ? v[2] : v[0], a1 = h32 ? v[3] : v[1];
+    const double s0 = h32 ? v[0] : v[2], s1 = h32 ? v[1] : v[3];
+    a0 += __shfl_xor(s0, 32);
+    a1 += __shfl_xor(s1, 32);
+    double c = h16 ? a1 : a0;
+    const double sc = h16 ? a0 : a1;
+    c += __shfl_xor(sc, 16);
+    c = group_sum<16>(c);
+    if ((lane & 15) == 0) wsum[r0 + (lane >> 4)][w] = c;
 }
 
-// Per-level totals of a tile (hcol[l][thread]) added to the instance histogram.
-__device__ __forceinline__ void tile_level_totals(const int* hcol, int nlev, int* __restrict__ hist) {
-    __shared__ int wl[NLEV][4];
-    const int w = threadIdx.x >> 6;
-    for (int l = 0; l < nlev; ++l) {
-        const int v = wave_sum_i(hcol[l * TILE_C + threadIdx.x]);
-        if ((threadIdx.x & 63) == 0) wl[l][w] = v;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nlev) {
-        const int l = threadIdx.x;
-        const int v = wl[l][0] + wl[l][1] + wl[l][2] + wl[l][3];
-        if (v) atomicAdd(&hist[l], v);
+// Tile row totals from the per-wave totals (after a barrier): part2[cb][i].
+__device__ __forceinline__ void tile_rows_store(const double (*wsum)[4], int rows, int i0, int cb, int m,
+                                                double* __restrict__ part2) {
+    const int t = threadIdx.x;
+    if (t < rows) part2[(long)cb * m + i0 + t] = (wsum[t][0] + wsum[t][1]) + (wsum[t][2] + wsum[t][3]);
+}
+
+// Sparsify level counts of a tile: hb[level * TILE_C + thread] is one byte per
+// thread and level (at most TILE_RMAX entries each).  Wave w reads the 64
+// words of levels w, w + 4, w + 8, w + 12, adds their bytes and reduces over
+// the wave; one atomic per level and wave (integer, so order-free).
+__device__ __forceinline__ void tile_level_totals(const unsigned* hw, int nlev, int* __restrict__ hist) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s4 = 0; s4 < NLEV / 4; ++s4) {
+        const int l = w + 4 * s4;
+        if (l < nlev) {
+            unsigned x = hw[l * (TILE_C / 4) + lane];
+            x = (x & 0x00ff00ffu) + ((x >> 8) & 0x00ff00ffu);
+            const int v = wave_sum_i((int)((x & 0xffffu) + (x >> 16)));
+            if (lane == 0 && v) atomicAdd(&hist[l], v);
+        }
     }
 }
 
-// ---------------------------------------------------------------------------
-// a5: Newton pass.  Tile = R rows x 256 columns.  Xt_ij of eq. (eppa_x);
-// column partials part[rb][j], row partials part2[cb][i], and the Sparsify
-// histogram hist[l] (number of entries whose highest kept level is l).
-// ---------------------------------------------------------------------------
 template <class Src>
 __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.y;
@@ -491,10 +527,13 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
     const int m = I.m, n = I.n;
     count_work(ctrl, b, W_GRAD, m, n);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
-    __shared__ int hcol[NLEV * TILE_C];  // [level][thread]: each thread counts its own entries
-    __shared__ double red[TILE_RMAX][TILE_C + 1];
+    __shared__ unsigned hw[NLEV * TILE_C / 4];  // [level][thread] byte counters
+    __shared__ double wsum[TILE_RMAX][4];
     __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
-    for (int l = 0; l < NLEV; ++l) hcol[l * TILE_C + threadIdx.x] = 0;
+    __shared__ double sT[64];
+    texp_table(sT);
+    unsigned char* hcol = reinterpret_cast<unsigned char*>(hw);
+    for (int k = threadIdx.x; k < NLEV * TILE_C / 4; k += 256) hw[k] = 0u;
     if ((int)threadIdx.x < rows) {
         sF[threadIdx.x] = I.F[i0 + threadIdx.x];
         sLa[threadIdx.x] = I.loga[i0 + threadIdx.x];
@@ -507,24 +546,30 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
     const Src src(I);
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
     double colacc = 0.0;
-    for (int r = 0; r < rows; ++r) {
-        double e = 0.0;
-        if (valid) {
-            const double x = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
-            e = exp(x);
-            const double q = lev_q(x, lrho, sLa[r], lbj);
-            if (q >= 0.0) {
-                const int l = (q >= (double)(nlev - 1)) ? nlev - 1 : (int)q;
-                hcol[l * TILE_C + threadIdx.x] += 1;
+    for (int r0 = 0; r0 < rows; r0 += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u;
+            double e = 0.0;
+            if (valid && r < rows) {
+                const double x = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
+                e = texp(x, sT);
+                const double q = lev_q(x, lrho, sLa[r], lbj);
+                if (q >= 0.0) {
+                    const int l = (q >= (double)(nlev - 1)) ? nlev - 1 : (int)q;
+                    hcol[l * TILE_C + threadIdx.x] += 1;
+                }
             }
+            colacc += e;
+            v[u] = e;
         }
-        colacc += e;
-        red[r][threadIdx.x] = e;
+        wave_rows4(v, r0, wsum);
     }
     if (valid) I.part[(long)rb * n + j] = colacc;
     __syncthreads();
-    tile_row_sums(red, rows, i0, cb, m, I.part2);
-    tile_level_totals(hcol, nlev, I.hist);
+    tile_rows_store(wsum, rows, i0, cb, m, I.part2);
+    tile_level_totals(hw, nlev, I.hist);
 }
 
 // Gradient merge: r = Xt e, c = Xt^T e into rc; the last block tests
@@ -659,28 +704,77 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
-    const int m = I.m, n = I.n, ncb = I.ncb, nrb = I.nrb;
+    const int m = I.m, n = I.n, ncb = I.ncb, nrb = I.nrb, N = m + n;
     __shared__ int ish[16];
+    __shared__ long lsh[16];
     const int* __restrict__ cr = I.cntr;
     const int* __restrict__ cc = I.cntc;
-    const long total = block_scan_excl<1024>(
+    // kept entries of row k of M (k < m: row of S; else column k - m)
+    auto kept = [&](int k) {
+        int c = 0;
+        if (k < m)
+            for (int q = 0; q < ncb; ++q) c += cr[(long)k * ncb + q];
+        else
+            for (int q = 0; q < nrb; ++q) c += cc[(long)q * n + (k - m)];
+        return c;
+    };
+    long real = 0;
+    block_scan_excl<1024>(
         [&](int i) {
-            int c = 0;
-            for (int q = 0; q < ncb; ++q) c += cr[(long)i * ncb + q];
-            return c;
+            const int c = kept(i);
+            real += c;
+            return (c + 3) & ~3;
         },
         m, I.rowptr, I.nnz_cap, ish);
-    block_scan_excl<1024>(
-        [&](int j) {
-            int c = 0;
-            for (int q = 0; q < nrb; ++q) c += cc[(long)q * n + j];
-            return c;
-        },
-        n, I.colptr, I.nnz_cap, ish);
-    if (threadIdx.x == 0) ctrl[b].nnz = (int)(total < I.nnz_cap ? total : I.nnz_cap);
+    block_scan_excl<1024>([&](int j) { return (kept(m + j) + 3) & ~3; }, n, I.colptr, I.nnz_cap, ish);
+    // unpadded count of S (fixed-order integer sum)
+    {
+        long v = real;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0) lsh[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            long t = 0;
+            for (int w = 0; w < 16; ++w) t += lsh[w];
+            ctrl[b].nnz = (int)(t < I.nnz_cap ? t : I.nnz_cap);
+        }
+    }
+    // rows of M grouped by quad count for the CG's product, in row order
+    // within each bin (ballot prefix per wave, wave totals in LDS); the
+    // pointers written above are visible to the whole block after the barrier
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int off = 0;
+    for (int t = 0; t < NBIN; ++t) {
+        if (threadIdx.x == 0) ctrl[b].binoff[t] = off;
+        int carry = 0;
+        for (int base = 0; base < N; base += 1024) {
+            const int k = base + threadIdx.x;
+            bool f = false;
+            if (k < N) {
+                const int nq = (k < m) ? (I.rowptr[k + 1] - I.rowptr[k]) >> 2 : (I.colptr[k - m + 1] - I.colptr[k - m]) >> 2;
+                const int bin = nq <= 1 ? 0 : nq <= 2 ? 1 : nq <= 4 ? 2 : nq <= 8 ? 3 : nq <= 16 ? 4 : 5;
+                f = bin == t;
+            }
+            const unsigned long long bal = __ballot(f);
+            __syncthreads();
+            if (lane == 0) ish[w] = (int)__popcll(bal);
+            __syncthreads();
+            int woff = 0, tot = 0;
+            for (int q = 0; q < 16; ++q) {
+                if (q < w) woff += ish[q];
+                tot += ish[q];
+            }
+            if (f) I.rowbin[off + carry + woff + (int)__popcll(bal & below)] = k;
+            carry += tot;
+        }
+        off += carry;
+    }
+    if (threadIdx.x == 0) ctrl[b].binoff[NBIN] = off;
 }
 
-template <class Src>
+template <class Src, class IX, class VT>
 __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON) return;
@@ -691,6 +785,8 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
     __shared__ int sRow[TILE_RMAX], sEnd[TILE_RMAX];
+    __shared__ double sT[64];
+    texp_table(sT);
     __shared__ int wc[TILE_RMAX][4];
     if ((int)threadIdx.x < rows) {
         const int i = i0 + threadIdx.x;
@@ -740,16 +836,30 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
             int woff = 0;
             for (int q = 0; q < w; ++q) woff += wc[r][q];
             const int slot = sRow[r] + woff + (int)__popcll(bal & below);
-            const double v = exp(xr[r]);
+            const VT v = (VT)texp(xr[r], sT);
             if (slot < sEnd[r]) {
-                I.col[slot] = j;
-                I.val[slot] = v;
+                static_cast<IX*>(I.col)[slot] = (IX)j;
+                static_cast<VT*>(I.val)[slot] = v;
             }
             if (cpos < cend) {
-                I.rowT[cpos] = i0 + r;
-                I.valT[cpos] = v;
+                static_cast<IX*>(I.rowT)[cpos] = (IX)(i0 + r);
+                static_cast<VT*>(I.valT)[cpos] = v;
             }
             ++cpos;
+        }
+    }
+    // pads (index 0, value 0) up to the next quad: rows of S in the last
+    // column block, columns of S^T in the last row block
+    if (rb == I.nrb - 1 && valid)
+        for (; cpos < cend; ++cpos) {
+            static_cast<IX*>(I.rowT)[cpos] = (IX)0;
+            static_cast<VT*>(I.valT)[cpos] = (VT)0;
+        }
+    if (cb == I.ncb - 1 && (int)threadIdx.x < rows) {
+        const int r = threadIdx.x;
+        for (int q = sRow[r] + wc[r][0] + wc[r][1] + wc[r][2] + wc[r][3]; q < sEnd[r]; ++q) {
+            static_cast<IX*>(I.col)[q] = (IX)0;
+            static_cast<VT*>(I.val)[q] = (VT)0;
         }
     }
 }
@@ -763,97 +873,92 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
 // by 16-lane groups per row/column gathering p from LDS.  Afterwards the
 // line-search inputs <grad P, d>, <a,dF>+<b,dG> and the resolution test.
 // ---------------------------------------------------------------------------
-// Off-diagonal part of M times p for two rows at once (S v for a row k < m,
-// S^T u for k >= m), each by a group of G lanes.  Every lane issues its U
-// index and U value loads for both rows before using any of them (predicated
-// past the row end), so 4U loads are in flight per lane and a row of up to
-// U*G entries costs one memory round trip.  ptr arrays: CSR row pointers
-// (rp, m+1) and CSC column pointers (cp, n+1), in LDS or global memory.
-template <int G>
-__device__ __forceinline__ void spmv_pair(const DevInst& I, int m, int N, int kA, int kB, const int* rp,
-                                          const int* cp, const double* __restrict__ pv, double* __restrict__ out,
-                                          int lg) {
-    constexpr int U = 4;
-    int qa = 0, ea = 0, qb = 0, eb = 0;
-    const int* ia = I.col;
-    const double* va = I.val;
-    const int* ib = I.col;
-    const double* vb = I.val;
-    int oa = m, ob = m;
-    if (kA < N) {
-        if (kA < m) {
-            qa = rp[kA];
-            ea = rp[kA + 1];
-        } else {
-            qa = cp[kA - m];
-            ea = cp[kA - m + 1];
-            ia = I.rowT;
-            va = I.valT;
-            oa = 0;
-        }
-    }
-    if (kB < N) {
-        if (kB < m) {
-            qb = rp[kB];
-            eb = rp[kB + 1];
-        } else {
-            qb = cp[kB - m];
-            eb = cp[kB - m + 1];
-            ib = I.rowT;
-            vb = I.valT;
-            ob = 0;
-        }
-    }
-    qa += lg;
-    qb += lg;
-    double sa = 0.0, sb = 0.0;
-    while (qa < ea || qb < eb) {
-        int xa[U], xb[U];
-        double wa[U], wb[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int q1 = qa + u * G, q2 = qb + u * G;
-            const bool ok1 = q1 < ea, ok2 = q2 < eb;
-            xa[u] = ok1 ? ldg(ia + q1) : 0;
-            wa[u] = ok1 ? ldg(va + q1) : 0.0;
-            xb[u] = ok2 ? ldg(ib + q2) : 0;
-            wb[u] = ok2 ? ldg(vb + q2) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            sa += wa[u] * pv[oa + xa[u]];
-            sb += wb[u] * pv[ob + xb[u]];
-        }
-        qa += U * G;
-        qb += U * G;
-    }
-    sa = group_sum<G>(sa);
-    sb = group_sum<G>(sb);
-    if (lg == 0) {
-        if (kA < N) out[kA] = sa;
-        if (kB < N) out[kB] = sb;
-    }
+// Off-diagonal part of M times p (S v for a row k < m, S^T u for k >= m).
+// Rows are stored in aligned quads; the rows of one bin (similar quad counts)
+// are handled by groups of G lanes, each lane loading one quad (its 4 indices
+// and 4 values in one vector load each) per step, so the lanes of a wave do
+// rows of about the same length.  ptr arrays: CSR row pointers (rp, m+1) and
+// CSC column pointers (cp, n+1), in LDS or global memory; bins: the row list.
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load_ix4(const unsigned short* p, int q, int (&x)[4]) {
+    const u16x4 v = ldg(reinterpret_cast<const u16x4*>(p) + q);
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
+}
+__device__ __forceinline__ void load_ix4(const int* p, int q, int (&x)[4]) {
+    const i32x4 v = ldg(reinterpret_cast<const i32x4*>(p) + q);
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
+}
+__device__ __forceinline__ void load_v4(const float* p, int q, double (&w)[4]) {
+    const f32x4 v = ldg(reinterpret_cast<const f32x4*>(p) + q);
+    w[0] = v.x;
+    w[1] = v.y;
+    w[2] = v.z;
+    w[3] = v.w;
+}
+__device__ __forceinline__ void load_v4(const double* p, int q, double (&w)[4]) {
+    const f64x2 u = ldg(reinterpret_cast<const f64x2*>(p) + 2 * q);
+    const f64x2 v = ldg(reinterpret_cast<const f64x2*>(p) + 2 * q + 1);
+    w[0] = u.x;
+    w[1] = u.y;
+    w[2] = v.x;
+    w[3] = v.y;
 }
 
-template <int G>
-__device__ __forceinline__ void spmv_all(const DevInst& I, int m, int N, const int* rp, const int* cp,
-                                         const double* __restrict__ pv, double* __restrict__ out) {
+template <int G, class IX, class VT>
+__device__ __forceinline__ void spmv_bin(const DevInst& I, int m, const int* bins, int lo, int hi, const int* rp,
+                                         const int* cp, const double* __restrict__ pv, double* __restrict__ out) {
     constexpr int NG = 1024 / G;
     const int g = threadIdx.x / G, lg = threadIdx.x % G;
-    for (int k = g; k < N; k += 2 * NG) spmv_pair<G>(I, m, N, k, k + NG, rp, cp, pv, out, lg);
+    for (int t = lo + g; t < hi; t += NG) {
+        const int k = bins[t];
+        const IX* ix;
+        const VT* vl;
+        int q0, q1, o;
+        if (k < m) {
+            ix = static_cast<const IX*>(I.col);
+            vl = static_cast<const VT*>(I.val);
+            q0 = rp[k] >> 2;
+            q1 = rp[k + 1] >> 2;
+            o = m;
+        } else {
+            ix = static_cast<const IX*>(I.rowT);
+            vl = static_cast<const VT*>(I.valT);
+            q0 = cp[k - m] >> 2;
+            q1 = cp[k - m + 1] >> 2;
+            o = 0;
+        }
+        double s = 0.0;
+        for (int q = q0 + lg; q < q1; q += G) {
+            int x[4];
+            double w[4];
+            load_ix4(ix, q, x);
+            load_v4(vl, q, w);
+            s += ((w[0] * pv[o + x[0]] + w[1] * pv[o + x[1]]) + (w[2] * pv[o + x[2]] + w[3] * pv[o + x[3]]));
+        }
+        s = group_sum<G>(s);
+        if (lg == 0) out[k] = s;
+    }
 }
 
-// lanes per row: about a quarter of the average row length (2 nnz entries
-// over N rows), so a typical row is read in one round of 4 loads per lane
-__device__ __forceinline__ void spmv_dispatch(const DevInst& I, int m, int N, int nnz, const int* rp, const int* cp,
-                                              const double* __restrict__ pv, double* __restrict__ out) {
-    const int avg = (2 * nnz) / (N > 0 ? N : 1);
-    if (avg <= 16)
-        spmv_all<4>(I, m, N, rp, cp, pv, out);
-    else if (avg <= 32)
-        spmv_all<8>(I, m, N, rp, cp, pv, out);
-    else
-        spmv_all<16>(I, m, N, rp, cp, pv, out);
+template <class IX, class VT>
+__device__ __forceinline__ void spmv_binned(const DevInst& I, int m, const int* bins, const int* bo, const int* rp,
+                                            const int* cp, const double* __restrict__ pv, double* __restrict__ out) {
+    spmv_bin<1, IX, VT>(I, m, bins, bo[0], bo[1], rp, cp, pv, out);
+    spmv_bin<2, IX, VT>(I, m, bins, bo[1], bo[2], rp, cp, pv, out);
+    spmv_bin<4, IX, VT>(I, m, bins, bo[2], bo[3], rp, cp, pv, out);
+    spmv_bin<8, IX, VT>(I, m, bins, bo[3], bo[4], rp, cp, pv, out);
+    spmv_bin<16, IX, VT>(I, m, bins, bo[4], bo[5], rp, cp, pv, out);
+    spmv_bin<32, IX, VT>(I, m, bins, bo[5], bo[6], rp, cp, pv, out);
 }
 
 __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp) {
@@ -875,7 +980,7 @@ __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab,
     }
 }
 
-template <int EPT>
+template <int EPT, class IX, class VT>
 __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
@@ -884,17 +989,23 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     __shared__ double sp[1024 * EPT];
     __shared__ double sAp[1024 * EPT];
     __shared__ double sh[32];
-    constexpr bool PTR_LDS = EPT <= 4;  // row/column pointers staged in LDS when they fit
+    constexpr bool PTR_LDS = EPT <= 4;  // pointers and the binned row list staged in LDS when they fit
     __shared__ int sptr[PTR_LDS ? 1024 * EPT + 2 : 1];
+    __shared__ int sbin[PTR_LDS ? 1024 * EPT : 1];
+    __shared__ int sbo[NBIN + 1];
     const int tid = threadIdx.x;
     const int* rp = I.rowptr;
     const int* cp = I.colptr;
+    const int* bins = I.rowbin;
     if (PTR_LDS) {
         for (int k = tid; k <= m; k += 1024) sptr[k] = I.rowptr[k];
         for (int k = tid; k <= n; k += 1024) sptr[m + 1 + k] = I.colptr[k];
+        for (int k = tid; k < N; k += 1024) sbin[k] = I.rowbin[k];
         rp = sptr;
         cp = sptr + m + 1;
+        bins = sbin;
     }
+    if (tid <= NBIN) sbo[tid] = ctrl[b].binoff[tid];
     const double eta = kp.eta;
     // register-resident iterate x, residual r, direction p and diagonal dg
     double x[EPT], r[EPT], p[EPT], dg[EPT];
@@ -918,12 +1029,11 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     bb = block_sum<1024>(bb, sh);
     rz = block_sum<1024>(rz, sh);
     const double bn = sqrt(bb);
-    const int nnz = ctrl[b].nnz;
     int it = 0;
     if (bn > 0.0) {
         while (it < kp.cg_max) {
             __syncthreads();
-            spmv_dispatch(I, m, N, nnz, rp, cp, sp, sAp);
+            spmv_binned<IX, VT>(I, m, bins, sbo, rp, cp, sp, sAp);
             __syncthreads();
             double pap = 0.0;
 #pragma unroll
@@ -983,6 +1093,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
 }
 
 // Same iteration with every vector in global memory (large m + n).
+template <class IX, class VT>
 __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
@@ -995,6 +1106,8 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     double* __restrict__ Ap = I.cgw + 3 * N;
     const double* __restrict__ dg = I.rc;
     __shared__ double sh[32];
+    __shared__ int sbo[NBIN + 1];
+    if (threadIdx.x <= NBIN) sbo[threadIdx.x] = ctrl[b].binoff[threadIdx.x];
     const double eta = kp.eta;
     double bb = 0.0, rz = 0.0;
     for (int k = threadIdx.x; k < N; k += 1024) {
@@ -1010,12 +1123,11 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     bb = block_sum<1024>(bb, sh);
     rz = block_sum<1024>(rz, sh);
     const double bn = sqrt(bb);
-    const int nnz = ctrl[b].nnz;
     int it = 0;
     if (bn > 0.0) {
         while (it < kp.cg_max) {
             __syncthreads();
-            spmv_dispatch(I, m, N, nnz, I.rowptr, I.colptr, p, Ap);
+            spmv_binned<IX, VT>(I, m, I.rowbin, sbo, I.rowptr, I.colptr, p, Ap);
             __syncthreads();
             double pap = 0.0;
             for (int k = threadIdx.x; k < N; k += 1024) {
@@ -1078,14 +1190,21 @@ __global__ __launch_bounds__(256) void k_ls_first(const DevInst* __restrict__ in
     const int m = I.m, n = I.n;
     count_work(ctrl, b, W_LS, m, n);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
-    __shared__ int hcol[NLEV * TILE_C];
-    __shared__ double red[TILE_RMAX][TILE_C + 1];
-    __shared__ double sF[TILE_RMAX], sD[TILE_RMAX], sLa[TILE_RMAX];
-    for (int l = 0; l < NLEV; ++l) hcol[l * TILE_C + threadIdx.x] = 0;
+    __shared__ unsigned hw[NLEV * TILE_C / 4];  // [level][thread] byte counters
+    __shared__ double wsum[TILE_RMAX][4];
+    __shared__ double sF[TILE_RMAX], sD[TILE_RMAX], sLa[TILE_RMAX], sA[TILE_RMAX], sA1[TILE_RMAX];
+    __shared__ double sT[64];
+    texp_table(sT);
+    unsigned char* hcol = reinterpret_cast<unsigned char*>(hw);
+    for (int k = threadIdx.x; k < NLEV * TILE_C / 4; k += 256) hw[k] = 0u;
     if ((int)threadIdx.x < rows) {
-        sF[threadIdx.x] = I.F[i0 + threadIdx.x];
-        sD[threadIdx.x] = I.d[i0 + threadIdx.x];
-        sLa[threadIdx.x] = I.loga[i0 + threadIdx.x];
+        const int i = i0 + threadIdx.x;
+        sF[threadIdx.x] = I.F[i];
+        sD[threadIdx.x] = I.d[i] * kp.inv_eta;
+        sLa[threadIdx.x] = I.loga[i];
+        const double A = expm1(I.d[i] * kp.inv_eta);
+        sA[threadIdx.x] = A;
+        sA1[threadIdx.x] = 1.0 + A;
     }
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
@@ -1094,36 +1213,52 @@ __global__ __launch_bounds__(256) void k_ls_first(const DevInst* __restrict__ in
     const int nlev = kp.nlev;
     const Src src(I);
     double acc = 0.0, colacc = 0.0;
-    const double Gj = valid ? ldg(I.G + j) : 0.0, dGj = valid ? ldg(I.d + m + j) : 0.0;
+    const double Gj = valid ? ldg(I.G + j) : 0.0, dGj = valid ? ldg(I.d + m + j) * ie : 0.0;
     const double lbj = valid ? ldg(I.logb + j) : 0.0;
-    for (int r = 0; r < rows; ++r) {
-        double e1 = 0.0;
-        if (valid) {
-            const double x = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
-            const double e = exp(x);
-            const double del = (sD[r] + dGj) * ie;
-            const double t = e * expm1(del);
-            acc += t;
-            e1 = e + t;
-            const double q = lev_q(x + del, lrho, sLa[r], lbj);
-            if (q >= 0.0) {
-                const int l = (q >= (double)(nlev - 1)) ? nlev - 1 : (int)q;
-                hcol[l * TILE_C + threadIdx.x] += 1;
+    // expm1(a_i + b_j) = A_i + B_j (1 + A_i) with A_i = expm1(a_i), B_j = expm1(b_j)
+    const double Bj = expm1(dGj);
+    for (int r0 = 0; r0 < rows; r0 += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u;
+            double e1 = 0.0;
+            if (valid && r < rows) {
+                const double x = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
+                const double e = texp(x, sT);
+                const double del = sD[r] + dGj;
+                const double t = e * fma(Bj, sA1[r], sA[r]);
+                acc += t;
+                e1 = e + t;
+                const double q = lev_q(x + del, lrho, sLa[r], lbj);
+                if (q >= 0.0) {
+                    const int l = (q >= (double)(nlev - 1)) ? nlev - 1 : (int)q;
+                    hcol[l * TILE_C + threadIdx.x] += 1;
+                }
             }
+            colacc += e1;
+            v[u] = e1;
         }
-        colacc += e1;
-        red[r][threadIdx.x] = e1;
+        wave_rows4(v, r0, wsum);
     }
     if (valid) I.part[(long)rb * n + j] = colacc;
     __syncthreads();
-    tile_row_sums(red, rows, i0, cb, m, I.part2);
-    tile_level_totals(hcol, nlev, I.hist);
+    tile_rows_store(wsum, rows, i0, cb, m, I.part2);
+    tile_level_totals(hw, nlev, I.hist);
     __shared__ double sh[4];
-    const int nblk = I.nrb * I.ncb;
     const double bs = block_sum<256>(acc, sh);
     if (threadIdx.x == 0) I.blk[blockIdx.x] = bs;
-    if (!last_block(&ctrl[b].ticket, nblk)) return;
-    const double tot = block_sum_array<256>(I.blk, nblk, sh);
+}
+
+// Armijo test of the first trial: the block partials in fixed order (a kernel
+// of its own, so the tile kernel needs no device-scope fence per block).
+__global__ __launch_bounds__(256) void k_ls_first_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+                                                        KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON || ctrl[b].ls_state != LS_PENDING) return;
+    const DevInst& I = insts[b];
+    __shared__ double sh[4];
+    const double tot = block_sum_array<256>(I.blk, I.nrb * I.ncb, sh);
     if (threadIdx.x == 0) {
         Ctrl& S = ctrl[b];
         const double inc = S.dab - kp.eta * tot;
@@ -1148,7 +1283,6 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
     const int m = I.m, n = I.n;
     count_work(ctrl, b, W_LS, m, n);
     const int h0 = ctrl[b].ls_h;
-    const int nt = min(NT, kp.ls_max - h0);
     double al[NT];
     {
         double a0 = 1.0;
@@ -1160,11 +1294,17 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
         }
     }
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
-    __shared__ double sF[TILE_RMAX], sD[TILE_RMAX];
-    if ((int)threadIdx.x < rows) {
-        sF[threadIdx.x] = I.F[i0 + threadIdx.x];
-        sD[threadIdx.x] = I.d[i0 + threadIdx.x];
+    // trial t: expm1(al_t (a_i + b_j)) = A_it + B_jt (1 + A_it)
+    __shared__ double sF[TILE_RMAX], sA[TILE_RMAX][NT], sA1[TILE_RMAX][NT];
+    __shared__ double sT[64];
+    texp_table(sT);
+    if ((int)threadIdx.x < rows * NT) {
+        const int r = threadIdx.x / NT, t = threadIdx.x - r * NT;
+        const double A = expm1(al[t] * (I.d[i0 + r] * kp.inv_eta));
+        sA[r][t] = A;
+        sA1[r][t] = 1.0 + A;
     }
+    if ((int)threadIdx.x < rows) sF[threadIdx.x] = I.F[i0 + threadIdx.x];
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
@@ -1174,23 +1314,45 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = 0.0;
     if (valid) {
-        const double Gj = ldg(I.G + j), dGj = ldg(I.d + m + j);
+        const double Gj = ldg(I.G + j), bj = ldg(I.d + m + j) * ie;
+        double B[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) B[t] = expm1(al[t] * bj);
         for (int r = 0; r < rows; ++r) {
             const int i = i0 + r;
-            const double e = exp(expo(sF[r], Gj, kap, src.at(i, j), ie));
-            const double del = (sD[r] + dGj) * ie;
+            const double e = texp(expo(sF[r], Gj, kap, src.at(i, j), ie), sT);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] += e * expm1(al[t] * del);
+            for (int t = 0; t < NT; ++t) acc[t] += e * fma(B[t], sA1[r][t], sA[r][t]);
         }
     }
     __shared__ double sh[4];
-    const int nblk = I.nrb * I.ncb;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const double s = block_sum<256>(acc[t], sh);
         if (threadIdx.x == 0) I.blk[(long)blockIdx.x * NT + t] = s;
     }
-    if (!last_block(&ctrl[b].ticket, nblk)) return;
+}
+
+// Armijo tests of a pass of NT trials, first acceptable step size wins.
+template <int NT>
+__global__ __launch_bounds__(256) void k_ls_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON || ctrl[b].ls_state != LS_PENDING) return;
+    const DevInst& I = insts[b];
+    const int nblk = I.nrb * I.ncb;
+    const int h0 = ctrl[b].ls_h;
+    const int nt = min(NT, kp.ls_max - h0);
+    double al[NT];
+    {
+        double a0 = 1.0;
+        for (int h = 0; h < h0; ++h) a0 *= kp.ls_beta;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            al[t] = a0;
+            a0 *= kp.ls_beta;
+        }
+    }
+    __shared__ double sh[4];
     double tot[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -1592,30 +1754,50 @@ void launch_grad_merge(const LaunchCtx& L) {
                        L.kp);
 }
 
+template <class IX, class VT>
+static void launch_fill_t(const LaunchCtx& L, int src, dim3 g) {
+#define K_(S) hipLaunchKernelGGL((k_fill<S, IX, VT>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+    PINS_SRC_DISPATCH(src, K_);
+#undef K_
+}
+
 void launch_sparsify(const LaunchCtx& L, int src) {
     const dim3 g = g2(L.max_tiles, L.count);
 #define K_(S) hipLaunchKernelGGL((k_count<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
     PINS_SRC_DISPATCH(src, K_);
 #undef K_
     hipLaunchKernelGGL(k_scan, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl);
-#define K_(S) hipLaunchKernelGGL((k_fill<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
-    PINS_SRC_DISPATCH(src, K_);
-#undef K_
+    switch (L.sp_fmt) {
+        case 0: launch_fill_t<int, double>(L, src, g); break;
+        case 1: launch_fill_t<unsigned short, double>(L, src, g); break;
+        case 2: launch_fill_t<int, float>(L, src, g); break;
+        default: launch_fill_t<unsigned short, float>(L, src, g); break;
+    }
 }
 
-void launch_pcg(const LaunchCtx& L) {
+template <class IX, class VT>
+static void launch_pcg_t(const LaunchCtx& L) {
     const int ept = (L.max_mn + 1023) / 1024;
     const dim3 g(L.count), blk(1024);
     if (ept <= 1)
-        hipLaunchKernelGGL(k_pcg_lds<1>, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<1, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else if (ept <= 2)
-        hipLaunchKernelGGL(k_pcg_lds<2>, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<2, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else if (ept <= 4)
-        hipLaunchKernelGGL(k_pcg_lds<4>, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<4, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else if (ept <= 8)
-        hipLaunchKernelGGL(k_pcg_lds<8>, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<8, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else
-        hipLaunchKernelGGL(k_pcg, g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg<IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+}
+
+void launch_pcg(const LaunchCtx& L) {
+    switch (L.sp_fmt) {
+        case 0: launch_pcg_t<int, double>(L); break;
+        case 1: launch_pcg_t<unsigned short, double>(L); break;
+        case 2: launch_pcg_t<int, float>(L); break;
+        default: launch_pcg_t<unsigned short, float>(L); break;
+    }
 }
 
 void launch_ls(const LaunchCtx& L, int src, bool first) {
@@ -1629,6 +1811,10 @@ void launch_ls(const LaunchCtx& L, int src, bool first) {
         PINS_SRC_DISPATCH(src, K_, LS_T);
 #undef K_
     }
+    if (first)
+        hipLaunchKernelGGL(k_ls_first_merge, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp);
+    else
+        hipLaunchKernelGGL(k_ls_merge<LS_T>, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
 void launch_update(const LaunchCtx& L) {

@@ -17,6 +17,7 @@ struct LaunchCtx {
     int count;
     int max_m, max_n, max_mn;  // maxima over the batch (max_mn = max m+n)
     int max_tiles;             // max nrb*ncb
+    int sp_fmt;                // storage of S: bit 0 uint16 indices, bit 1 float values
 };
 
 void launch_row_lse(const LaunchCtx& L, int src, bool f32, int mask);

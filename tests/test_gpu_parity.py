@@ -278,3 +278,22 @@ def test_large_instances_parity(ctx, case):
     g["_C"] = C
     o = oracle.pins(C, a, b, eta=eta, K=K)
     check_parity(g, o, a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_int32_index_storage_parity(ctx, precision):
+    """m > 65535 makes the CG's copy of S use 32-bit indices (16-bit otherwise),
+    with double (FP64) or float (mixed) values; parity in both precisions."""
+    print("case tall 70000x3 %s" % precision, flush=True)
+    m, n = 70000, 3
+    C, a, b = _rand(m, n, 515)
+    eta, K = 0.05, 3
+    prm = P.params(eta=eta, max_outer=K, precision=P.FP64 if precision == "fp64" else P.MIXED)
+    g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), prm)
+    g["_C"] = C
+    o = oracle.pins(C, a, b, eta=eta, K=K)
+    if precision == "fp64":
+        check_parity(g, o, a, b)
+    else:
+        rel = abs(g["cost"] - o["cost"]) / o["cost"]
+        assert g["rc"] == 0 and rel <= 1e-6 and g["resid"] <= 1e-10
