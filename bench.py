@@ -45,8 +45,8 @@ EXP_FLOPS = 26.0
 FLOPS_PER_ENTRY = {
     # exponent (3) + exp + scale of the grid cost (1) + row/col accumulation (2) + level test (3)
     "grad": 9.0 + EXP_FLOPS,
-    # exponent (3) + exp + expm1 for one trial + product/accumulate (3)
-    "ls": 7.0 + 2.0 * EXP_FLOPS,
+    # exponent (3) + exp + factored expm1 (2) + product/accumulate (4)
+    "ls": 9.0 + EXP_FLOPS,
     # exponent (3) + online max/rescale/accumulate (3) + exp
     "row_lse": 7.0 + EXP_FLOPS,
     "col_lse": 7.0 + EXP_FLOPS,
@@ -57,8 +57,9 @@ FLOPS_PER_ENTRY = {
     "final": 10.0 + EXP_FLOPS,
 }
 # Algorithmic bytes per unit of the sparse kernels: CG reads each stored
-# CSR/CSC entry (4-byte index + 8-byte value) once per iteration.
-BYTES_PER_ENTRY = {"pcg": 12.0}
+# CSR/CSC entry once per iteration: a 2-byte index (m, n <= 65536) and a
+# 4-byte (mixed precision) or 8-byte (FP64) value.
+BYTES_PER_ENTRY = {"mixed": {"pcg": 6.0}, "fp64": {"pcg": 10.0}}
 
 
 def parse():
@@ -172,8 +173,8 @@ def main():
                             unit="TFLOP/s", frac=achieved / PEAK_FP64_VECTOR_TFLOPS,
                             traffic=_traffic(dom), avg_launch_us=1e3 * avg_ms, launches=calls,
                             entries_per_launch=kwork[dom] / calls, flops_per_entry=fpe)
-        elif dom in BYTES_PER_ENTRY and kwork.get(dom, 0) > 0:
-            bytes_per_launch = kwork[dom] * BYTES_PER_ENTRY[dom] / calls
+        elif dom in BYTES_PER_ENTRY[args.precision] and kwork.get(dom, 0) > 0:
+            bytes_per_launch = kwork[dom] * BYTES_PER_ENTRY[args.precision][dom] / calls
             achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
             roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
                             frac=achieved / PEAK_HBM_GBS, traffic=_traffic(dom), avg_launch_us=1e3 * avg_ms,

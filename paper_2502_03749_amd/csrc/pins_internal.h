@@ -61,7 +61,8 @@ struct DevInst {
     int* cntc;      // nrb * n kept entries per (row block, column) at the chosen level
     // S (CSR) and S^T (CSC).  Every row of S and of S^T starts at a multiple
     // of 4 entries and is padded to one with (index 0, value 0), so the CG
-    // reads them in aligned quads.  Index arrays hold uint16 when every index
+    // reads them in aligned quads; within a row of nq quads the quads are
+    // stored transposed (component u of quad q holds the row's entry u*nq + q).  Index arrays hold uint16 when every index
     // of the batch is < 65536, else int32; value arrays hold float in mixed
     // precision, else double (the launch chooses; the buffers are sized for
     // int32/double).  nnz_cap (a multiple of 4) includes the padding.
@@ -71,7 +72,7 @@ struct DevInst {
     int* colptr;    // n+1
     void* rowT;     // nnz_cap row indices of S^T
     void* valT;     // nnz_cap values of S^T
-    int* rowbin;    // m+n rows of M = [. S; S^T .] grouped by quad count (NBIN bins)
+    int* rowbin;    // m+n rows of M = [. S; S^T .]: rows of S by quad count (NBIN bins), then rows of S^T
     double* Ck;     // materialised shifted cost (m*n) or nullptr
     double* alpha;  // outputs
     double* beta;
@@ -88,7 +89,7 @@ struct Ctrl {
     double gd, dab, fa, cost;
     double entropy, dual, scale, pad2;
     double work[8];  // matrix entries visited per pass kind (W_* below); W_CG: stored entries read by CG
-    int binoff[8];   // rowbin offsets of the NBIN bins (binoff[NBIN] = m+n)
+    int binoff[16];  // rowbin offsets: NBIN bins of rows of S, then NBIN bins of rows of S^T; [2 NBIN] = m+n
 };
 
 // pass kinds counted in Ctrl::work

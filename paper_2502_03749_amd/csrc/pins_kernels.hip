@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void k_col_merge(const DevInst* __restrict__ i
     const int b = blockIdx.y;
     if (!phase_in(ctrl, b, mask)) return;
     const DevInst& I = insts[b];
-    const int n = I.n, m = I.m;
+    const int n = I.n;
     const int nb = (n + 255) / 256;
     if ((int)blockIdx.x >= nb) return;
     const int j = blockIdx.x * 256 + threadIdx.x;
@@ -451,9 +451,18 @@ __global__ __launch_bounds__(256) void k_col_merge(const DevInst* __restrict__ i
         }
         I.G[j] = kp.eta * (I.logb[j] - (mx + log(s)));
     }
-    if (last_block(&ctrl[b].ticket, nb)) {
+}
+
+// Warm-up control after a g-update (one block per instance; a kernel of its
+// own so that no block of k_col_merge sees the phase change).
+__global__ __launch_bounds__(256) void k_col_decide(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                    int mask) {
+    const int b = blockIdx.x;
+    if (!phase_in(ctrl, b, mask)) return;
+    const DevInst& I = insts[b];
+    {
         __shared__ double sh[4];
-        const double err = block_sum_array<256>(I.blk, (m + 3) / 4, sh);
+        const double err = block_sum_array<256>(I.blk, (I.m + 3) / 4, sh);
         if (threadIdx.x == 0) {
             Ctrl& S = ctrl[b];
             if (S.phase == PH_WARM) {
@@ -600,9 +609,17 @@ __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ 
     }
     const double bs = block_sum<256>(dev, sh);
     if (threadIdx.x == 0) I.blk2[blockIdx.x] = bs;
-    if (!last_block(&ctrl[b].ticket, nb)) return;
+}
 
-    const double res = block_sum_array<256>(I.blk2, nb, sh);
+// Newton control: residual, convergence, Sparsify level (one block per instance).
+__global__ __launch_bounds__(256) void k_grad_decide(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+                                                     KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n;
+    __shared__ double sh[4];
+    const double res = block_sum_array<256>(I.blk2, (m + n + 255) / 256, sh);
     Ctrl& S = ctrl[b];
     __shared__ int s_go;
     if (threadIdx.x == 0) {
@@ -661,6 +678,15 @@ __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ 
 // count and fill take the keep decision with the same arithmetic, so the
 // pointers match what the fill writes.
 // ---------------------------------------------------------------------------
+// Position of the e-th entry (in index order) of a row of nq quads starting at
+// entry `start`: quads are stored transposed, component u of quad q holding
+// entry u*nq + q, so that the lanes reading quads q, q+1, ... of a row gather
+// consecutive entries (nearby columns) for each component.
+__device__ __forceinline__ int quad_slot(int start, int nq, int e) {
+    const unsigned q = (unsigned)e % (unsigned)nq, u = (unsigned)e / (unsigned)nq;
+    return start + 4 * (int)q + (int)u;
+}
+
 template <class Src>
 __global__ __launch_bounds__(256) void k_count(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.y;
@@ -746,13 +772,14 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     int off = 0;
-    for (int t = 0; t < NBIN; ++t) {
-        if (threadIdx.x == 0) ctrl[b].binoff[t] = off;
+    for (int g = 0; g < 2 * NBIN; ++g) {
+        const int part = g / NBIN, t = g - part * NBIN;
+        if (threadIdx.x == 0) ctrl[b].binoff[g] = off;
         int carry = 0;
-        for (int base = 0; base < N; base += 1024) {
+        for (int base = part ? m : 0; base < (part ? N : m); base += 1024) {
             const int k = base + threadIdx.x;
             bool f = false;
-            if (k < N) {
+            if (k < (part ? N : m)) {
                 const int nq = (k < m) ? (I.rowptr[k + 1] - I.rowptr[k]) >> 2 : (I.colptr[k - m + 1] - I.colptr[k - m]) >> 2;
                 const int bin = nq <= 1 ? 0 : nq <= 2 ? 1 : nq <= 4 ? 2 : nq <= 8 ? 3 : nq <= 16 ? 4 : 5;
                 f = bin == t;
@@ -771,7 +798,7 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
         }
         off += carry;
     }
-    if (threadIdx.x == 0) ctrl[b].binoff[NBIN] = off;
+    if (threadIdx.x == 0) ctrl[b].binoff[2 * NBIN] = off;
 }
 
 template <class Src, class IX, class VT>
@@ -784,7 +811,7 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     const int m = I.m, n = I.n;
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
-    __shared__ int sRow[TILE_RMAX], sEnd[TILE_RMAX];
+    __shared__ int sStart[TILE_RMAX], sNq[TILE_RMAX], sE0[TILE_RMAX];
     __shared__ double sT[64];
     texp_table(sT);
     __shared__ int wc[TILE_RMAX][4];
@@ -792,10 +819,11 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
         const int i = i0 + threadIdx.x;
         sF[threadIdx.x] = I.F[i];
         sLa[threadIdx.x] = I.loga[i];
-        int base = I.rowptr[i];
-        for (int q = 0; q < cb; ++q) base += I.cntr[(long)i * I.ncb + q];
-        sRow[threadIdx.x] = base;
-        sEnd[threadIdx.x] = I.rowptr[i + 1];
+        int e0 = 0;
+        for (int q = 0; q < cb; ++q) e0 += I.cntr[(long)i * I.ncb + q];
+        sE0[threadIdx.x] = e0;
+        sStart[threadIdx.x] = I.rowptr[i];
+        sNq[threadIdx.x] = (I.rowptr[i + 1] - I.rowptr[i]) >> 2;
     }
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
@@ -804,11 +832,11 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     const double lev = (double)ctrl[b].level, kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
     const Src src(I);
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
-    int cpos = 0, cend = 0;
+    int ce = 0, cstart = 0, cnq = 0;  // entry index within column j, its start and quad count
     if (valid) {
-        cpos = I.colptr[j];
-        for (int q = 0; q < rb; ++q) cpos += I.cntc[(long)q * n + j];
-        cend = I.colptr[j + 1];
+        for (int q = 0; q < rb; ++q) ce += I.cntc[(long)q * n + j];
+        cstart = I.colptr[j];
+        cnq = (I.colptr[j + 1] - cstart) >> 2;
     }
     double xr[TILE_RMAX];
     unsigned keepm = 0;
@@ -835,46 +863,60 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
         if (keep) {
             int woff = 0;
             for (int q = 0; q < w; ++q) woff += wc[r][q];
-            const int slot = sRow[r] + woff + (int)__popcll(bal & below);
+            const int e = sE0[r] + woff + (int)__popcll(bal & below);
             const VT v = (VT)texp(xr[r], sT);
-            if (slot < sEnd[r]) {
+            const int nq = sNq[r];
+            if (e < 4 * nq) {
+                const int slot = quad_slot(sStart[r], nq, e);
                 static_cast<IX*>(I.col)[slot] = (IX)j;
                 static_cast<VT*>(I.val)[slot] = v;
             }
-            if (cpos < cend) {
-                static_cast<IX*>(I.rowT)[cpos] = (IX)(i0 + r);
-                static_cast<VT*>(I.valT)[cpos] = v;
+            if (ce < 4 * cnq) {
+                const int slot = quad_slot(cstart, cnq, ce);
+                static_cast<IX*>(I.rowT)[slot] = (IX)(i0 + r);
+                static_cast<VT*>(I.valT)[slot] = v;
             }
-            ++cpos;
+            ++ce;
         }
     }
-    // pads (index 0, value 0) up to the next quad: rows of S in the last
-    // column block, columns of S^T in the last row block
+    // pads (index 0, value 0) up to a whole number of quads: rows of S in the
+    // last column block, columns of S^T in the last row block
     if (rb == I.nrb - 1 && valid)
-        for (; cpos < cend; ++cpos) {
-            static_cast<IX*>(I.rowT)[cpos] = (IX)0;
-            static_cast<VT*>(I.valT)[cpos] = (VT)0;
+        for (; ce < 4 * cnq; ++ce) {
+            const int slot = quad_slot(cstart, cnq, ce);
+            static_cast<IX*>(I.rowT)[slot] = (IX)0;
+            static_cast<VT*>(I.valT)[slot] = (VT)0;
         }
     if (cb == I.ncb - 1 && (int)threadIdx.x < rows) {
-        const int r = threadIdx.x;
-        for (int q = sRow[r] + wc[r][0] + wc[r][1] + wc[r][2] + wc[r][3]; q < sEnd[r]; ++q) {
-            static_cast<IX*>(I.col)[q] = (IX)0;
-            static_cast<VT*>(I.val)[q] = (VT)0;
+        const int r = threadIdx.x, nq = sNq[r];
+        for (int e = sE0[r] + wc[r][0] + wc[r][1] + wc[r][2] + wc[r][3]; e < 4 * nq; ++e) {
+            const int slot = quad_slot(sStart[r], nq, e);
+            static_cast<IX*>(I.col)[slot] = (IX)0;
+            static_cast<VT*>(I.val)[slot] = (VT)0;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// a7: truncated Jacobi-preconditioned CG on M d = eta*grad P, where
-// M = [diag(r) S; S^T diag(c)] = -eta * (sparsified Hessian of eq. (eppa-hess)),
-// x0 = 0, stop at ||res||_2 <= cg_rtol*||rhs||_2 or cg_max.  One block of 1024
-// threads per instance.  Each thread owns the vector entries k = tid + 1024 t
-// (kept in registers in the LDS variant); the products S v and S^T u are done
-// by 16-lane groups per row/column gathering p from LDS.  Afterwards the
+// a7: truncated CG on the Newton system M d = eta*grad P, where
+// M = [D_r S; S^T D_c] = -eta * (sparsified Hessian of eq. (eppa-hess)),
+// D_r = diag(r), D_c = diag(c).  CG runs on the Schur complement of the
+// column block,
+//   (D_r - S D_c^-1 S^T) x = b_1 - S D_c^-1 b_2,   y = D_c^-1 (b_2 - S^T x),
+// with the preconditioner D_r and x0 = 0.  M couples rows only to columns
+// (property A), so CG on the reduced system reaches a residual in half the
+// iterations CG on M with diag(M) needs, at the same cost per iteration (one
+// product with S^T, one with S).  With y eliminated exactly the residual of
+// M's system is (reduced residual, 0), so the stop ||res||_2 <= cg_rtol *
+// ||b||_2 (or cg_max iterations) is the rule for M's system itself.  One block
+// of 1024 threads per instance; each thread owns the vector entries
+// k = tid + 1024 t (registers in the LDS variant); the products are done by
+// lane groups over the binned rows, gathering from LDS.  Afterwards the
 // line-search inputs <grad P, d>, <a,dF>+<b,dG> and the resolution test.
 // ---------------------------------------------------------------------------
 // Off-diagonal part of M times p (S v for a row k < m, S^T u for k >= m).
-// Rows are stored in aligned quads; the rows of one bin (similar quad counts)
+// Rows are stored in aligned, transposed quads (see quad_slot); the entry
+// order inside a row does not matter for the product.  The rows of one bin (similar quad counts)
 // are handled by groups of G lanes, each lane loading one quad (its 4 indices
 // and 4 values in one vector load each) per step, so the lanes of a wave do
 // rows of about the same length.  ptr arrays: CSR row pointers (rp, m+1) and
@@ -950,9 +992,12 @@ __device__ __forceinline__ void spmv_bin(const DevInst& I, int m, const int* bin
     }
 }
 
+// One half of M's off-diagonal product: bo = the NBIN + 1 bin offsets of the
+// rows of S (out[i] = (S v)_i, v = pv[m..]) or of the rows of S^T
+// (out[m + j] = (S^T u)_j, u = pv[0..m)).
 template <class IX, class VT>
-__device__ __forceinline__ void spmv_binned(const DevInst& I, int m, const int* bins, const int* bo, const int* rp,
-                                            const int* cp, const double* __restrict__ pv, double* __restrict__ out) {
+__device__ __forceinline__ void spmv_part(const DevInst& I, int m, const int* bins, const int* bo, const int* rp,
+                                          const int* cp, const double* __restrict__ pv, double* __restrict__ out) {
     spmv_bin<1, IX, VT>(I, m, bins, bo[0], bo[1], rp, cp, pv, out);
     spmv_bin<2, IX, VT>(I, m, bins, bo[1], bo[2], rp, cp, pv, out);
     spmv_bin<4, IX, VT>(I, m, bins, bo[2], bo[3], rp, cp, pv, out);
@@ -986,13 +1031,15 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
+    // sp: the direction p on the rows, D_c^-1 S^T p on the columns;
+    // sAp: products of the current half
     __shared__ double sp[1024 * EPT];
     __shared__ double sAp[1024 * EPT];
     __shared__ double sh[32];
     constexpr bool PTR_LDS = EPT <= 4;  // pointers and the binned row list staged in LDS when they fit
     __shared__ int sptr[PTR_LDS ? 1024 * EPT + 2 : 1];
     __shared__ int sbin[PTR_LDS ? 1024 * EPT : 1];
-    __shared__ int sbo[NBIN + 1];
+    __shared__ int sbo[2 * NBIN + 1];
     const int tid = threadIdx.x;
     const int* rp = I.rowptr;
     const int* cp = I.colptr;
@@ -1005,54 +1052,74 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
         cp = sptr + m + 1;
         bins = sbin;
     }
-    if (tid <= NBIN) sbo[tid] = ctrl[b].binoff[tid];
+    if (tid <= 2 * NBIN) sbo[tid] = ctrl[b].binoff[tid];
     const double eta = kp.eta;
-    // register-resident iterate x, residual r, direction p and diagonal dg
-    double x[EPT], r[EPT], p[EPT], dg[EPT];
-    double bb = 0.0, rz = 0.0;
+    // registers: rhs bv, diagonal dg; on rows the iterate x, residual r, direction p
+    double x[EPT], r[EPT], p[EPT], dg[EPT], bv[EPT];
+    double bb = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const int k = tid + 1024 * t;
-        x[t] = r[t] = p[t] = 0.0;
+        x[t] = r[t] = p[t] = bv[t] = 0.0;
         dg[t] = 1.0;
         if (k < N) {
             dg[t] = I.rc[k];
             const double tg = (k < m) ? I.a[k] : I.b[k - m];
-            const double rh = eta * (tg - dg[t]);
-            r[t] = rh;
-            p[t] = rh / dg[t];
-            sp[k] = p[t];
-            bb += rh * rh;
-            rz += rh * p[t];
+            bv[t] = eta * (tg - dg[t]);
+            bb += bv[t] * bv[t];
+            if (k >= m) sp[k] = bv[t] / dg[t];  // D_c^-1 b_2
         }
     }
-    bb = block_sum<1024>(bb, sh);
-    rz = block_sum<1024>(rz, sh);
+    bb = block_sum<1024>(bb, sh);  // also orders the LDS writes above
     const double bn = sqrt(bb);
+    spmv_part<IX, VT>(I, m, bins, sbo, rp, cp, sp, sAp);  // S D_c^-1 b_2 on the rows
+    __syncthreads();
+    double rr = 0.0, rz = 0.0;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+        const int k = tid + 1024 * t;
+        if (k < m) {
+            r[t] = bv[t] - sAp[k];
+            p[t] = r[t] / dg[t];
+            sp[k] = p[t];
+            rr += r[t] * r[t];
+            rz += r[t] * p[t];
+        }
+    }
+    block_sum2<1024>(rr, rz, sh);
     int it = 0;
-    if (bn > 0.0) {
+    if (bn > 0.0 && sqrt(rr) > kp.cg_rtol * bn) {
         while (it < kp.cg_max) {
             __syncthreads();
-            spmv_binned<IX, VT>(I, m, bins, sbo, rp, cp, sp, sAp);
+            spmv_part<IX, VT>(I, m, bins, sbo + NBIN, rp, cp, sp, sAp);  // S^T p
             __syncthreads();
-            double pap = 0.0;
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
-                if (k < N) {
-                    const double ap = dg[t] * p[t] + sAp[k];
-                    sAp[k] = ap;
-                    pap += p[t] * ap;
+                if (k >= m && k < N) sp[k] = sAp[k] / dg[t];
+            }
+            __syncthreads();
+            spmv_part<IX, VT>(I, m, bins, sbo, rp, cp, sp, sAp);  // S D_c^-1 S^T p
+            __syncthreads();
+            double pq = 0.0;
+#pragma unroll
+            for (int t = 0; t < EPT; ++t) {
+                const int k = tid + 1024 * t;
+                if (k < m) {
+                    const double q = dg[t] * p[t] - sAp[k];
+                    sAp[k] = q;
+                    pq += p[t] * q;
                 }
             }
-            pap = block_sum<1024>(pap, sh);
-            if (!(pap > 0.0)) break;
-            const double al = rz / pap;
-            double rr = 0.0, rz2 = 0.0;
+            pq = block_sum<1024>(pq, sh);
+            if (!(pq > 0.0)) break;
+            const double al = rz / pq;
+            double rz2 = 0.0;
+            rr = 0.0;
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
-                if (k < N) {
+                if (k < m) {
                     x[t] += al * p[t];
                     r[t] -= al * sAp[k];
                     rr += r[t] * r[t];
@@ -1067,18 +1134,29 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
-                if (k < N) {
+                if (k < m) {
                     p[t] = r[t] / dg[t] + be * p[t];
                     sp[k] = p[t];
                 }
             }
         }
     }
+    // the column part y = D_c^-1 (b_2 - S^T x)
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+        const int k = tid + 1024 * t;
+        if (k < m) sp[k] = x[t];
+    }
+    __syncthreads();
+    spmv_part<IX, VT>(I, m, bins, sbo + NBIN, rp, cp, sp, sAp);
+    __syncthreads();
     double gd = 0.0, dab = 0.0, fa = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const int k = tid + 1024 * t;
         if (k < N) {
+            if (k >= m) x[t] = (bv[t] - sAp[k]) / dg[t];
             const double tg = (k < m) ? I.a[k] : I.b[k - m];
             I.d[k] = x[t];
             gd += (tg - dg[t]) * x[t];
@@ -1099,66 +1177,83 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
-    double* __restrict__ x = I.d;
-    double* __restrict__ res = I.cgw;
-    double* __restrict__ z = I.cgw + N;
-    double* __restrict__ p = I.cgw + 2 * N;
+    double* __restrict__ x = I.d;            // [x; y]
+    double* __restrict__ res = I.cgw;        // residual on the rows, rhs on the columns
+    double* __restrict__ bv = I.cgw + N;     // rhs
+    double* __restrict__ p = I.cgw + 2 * N;  // direction on the rows, D_c^-1 S^T p on the columns
     double* __restrict__ Ap = I.cgw + 3 * N;
     const double* __restrict__ dg = I.rc;
     __shared__ double sh[32];
-    __shared__ int sbo[NBIN + 1];
-    if (threadIdx.x <= NBIN) sbo[threadIdx.x] = ctrl[b].binoff[threadIdx.x];
+    __shared__ int sbo[2 * NBIN + 1];
+    if (threadIdx.x <= 2 * NBIN) sbo[threadIdx.x] = ctrl[b].binoff[threadIdx.x];
     const double eta = kp.eta;
-    double bb = 0.0, rz = 0.0;
+    double bb = 0.0;
     for (int k = threadIdx.x; k < N; k += 1024) {
         const double tgt = (k < m) ? I.a[k] : I.b[k - m];
         const double rh = eta * (tgt - dg[k]);
+        bv[k] = rh;
         x[k] = 0.0;
-        res[k] = rh;
-        const double zz = rh / dg[k];
-        p[k] = zz;
         bb += rh * rh;
-        rz += rh * zz;
+        if (k >= m) p[k] = rh / dg[k];
     }
     bb = block_sum<1024>(bb, sh);
-    rz = block_sum<1024>(rz, sh);
     const double bn = sqrt(bb);
+    spmv_part<IX, VT>(I, m, I.rowbin, sbo, I.rowptr, I.colptr, p, Ap);
+    __syncthreads();
+    double rr = 0.0, rz = 0.0;
+    for (int k = threadIdx.x; k < m; k += 1024) {
+        const double rk = bv[k] - Ap[k];
+        res[k] = rk;
+        const double zk = rk / dg[k];
+        p[k] = zk;
+        rr += rk * rk;
+        rz += rk * zk;
+    }
+    block_sum2<1024>(rr, rz, sh);
     int it = 0;
-    if (bn > 0.0) {
+    if (bn > 0.0 && sqrt(rr) > kp.cg_rtol * bn) {
         while (it < kp.cg_max) {
             __syncthreads();
-            spmv_binned<IX, VT>(I, m, I.rowbin, sbo, I.rowptr, I.colptr, p, Ap);
+            spmv_part<IX, VT>(I, m, I.rowbin, sbo + NBIN, I.rowptr, I.colptr, p, Ap);
             __syncthreads();
-            double pap = 0.0;
-            for (int k = threadIdx.x; k < N; k += 1024) {
-                const double s = dg[k] * p[k] + Ap[k];
-                Ap[k] = s;
-                pap += p[k] * s;
+            for (int k = m + threadIdx.x; k < N; k += 1024) p[k] = Ap[k] / dg[k];
+            __syncthreads();
+            spmv_part<IX, VT>(I, m, I.rowbin, sbo, I.rowptr, I.colptr, p, Ap);
+            __syncthreads();
+            double pq = 0.0;
+            for (int k = threadIdx.x; k < m; k += 1024) {
+                const double q = dg[k] * p[k] - Ap[k];
+                Ap[k] = q;
+                pq += p[k] * q;
             }
-            pap = block_sum<1024>(pap, sh);
-            if (!(pap > 0.0)) break;
-            const double al = rz / pap;
-            double rr = 0.0, rz2 = 0.0;
-            for (int k = threadIdx.x; k < N; k += 1024) {
+            pq = block_sum<1024>(pq, sh);
+            if (!(pq > 0.0)) break;
+            const double al = rz / pq;
+            double rz2 = 0.0;
+            rr = 0.0;
+            for (int k = threadIdx.x; k < m; k += 1024) {
                 x[k] += al * p[k];
                 const double rk = res[k] - al * Ap[k];
                 res[k] = rk;
-                const double zk = rk / dg[k];
-                z[k] = zk;
                 rr += rk * rk;
-                rz2 += rk * zk;
+                rz2 += rk * (rk / dg[k]);
             }
             block_sum2<1024>(rr, rz2, sh);
             ++it;
             if (sqrt(rr) <= kp.cg_rtol * bn) break;
             const double be = rz2 / rz;
             rz = rz2;
-            for (int k = threadIdx.x; k < N; k += 1024) p[k] = z[k] + be * p[k];
+            for (int k = threadIdx.x; k < m; k += 1024) p[k] = res[k] / dg[k] + be * p[k];
         }
     }
     __syncthreads();
+    for (int k = threadIdx.x; k < m; k += 1024) p[k] = x[k];
+    __syncthreads();
+    spmv_part<IX, VT>(I, m, I.rowbin, sbo + NBIN, I.rowptr, I.colptr, p, Ap);
+    __syncthreads();
     double gd = 0.0, dab = 0.0, fa = 0.0;
     for (int k = threadIdx.x; k < N; k += 1024) {
+        if (k >= m) x[k] = (bv[k] - Ap[k]) / dg[k];
         const double tgt = (k < m) ? I.a[k] : I.b[k - m];
         gd += (tgt - dg[k]) * x[k];
         dab += tgt * x[k];
@@ -1740,6 +1835,7 @@ void launch_col_lse(const LaunchCtx& L, int src, bool f32, int mask) {
 void launch_col_merge(const LaunchCtx& L, int mask) {
     hipLaunchKernelGGL(k_col_merge, g2((L.max_n + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
                        L.kp, mask);
+    hipLaunchKernelGGL(k_col_decide, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, mask);
 }
 
 void launch_grad(const LaunchCtx& L, int src) {
@@ -1752,6 +1848,7 @@ void launch_grad(const LaunchCtx& L, int src) {
 void launch_grad_merge(const LaunchCtx& L) {
     hipLaunchKernelGGL(k_grad_merge, g2((L.max_mn + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
                        L.kp);
+    hipLaunchKernelGGL(k_grad_decide, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
 template <class IX, class VT>
