@@ -297,3 +297,32 @@ def test_int32_index_storage_parity(ctx, precision):
     else:
         rel = abs(g["cost"] - o["cost"]) / o["cost"]
         assert g["rc"] == 0 and rel <= 1e-6 and g["resid"] <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_full_size_batch_sampled_parity(ctx, precision):
+    """The benchmarked configuration itself: 64 pairs of 28x28 histograms, grid
+    cost, eta = 0.1, K = 250, one batched call.  Every instance converges
+    (status OK, marginal residual <= 1e-10, gauge); two sampled pairs match the
+    oracle at the same K (mixed <= 1e-6, FP64 <= 1e-9 relative cost)."""
+    s, K, eta = 28, 250, 0.1
+    n = s * s
+    print("case full-size batch 64 x %dx%d %s" % (n, n, precision), flush=True)
+    pairs = [W.blob_pair(i, s=s) for i in range(64)]
+    probs = [dict(kind=P.COST_GRID, m=n, n=n, grid_s=s, a=_t(p["a"]), b=_t(p["b"])) for p in pairs]
+    outs = [dict(alpha=torch.empty(n, dtype=torch.float64, device=DEV),
+                 beta=torch.empty(n, dtype=torch.float64, device=DEV)) for _ in pairs]
+    prm = P.params(eta=eta, max_outer=K, precision=P.MIXED if precision == "mixed" else P.FP64)
+    rc, rs = ctx.solve_batch_device(probs, prm, outs, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for q, r in enumerate(rs):
+        assert r["status"] == 0 and r["resid"] <= 1e-10, (q, r["status"], r["resid"])
+        al, be = outs[q]["alpha"].cpu().numpy(), outs[q]["beta"].cpu().numpy()
+        assert abs(pairs[q]["a"] @ al - pairs[q]["b"] @ be) <= 1e-12
+    C = oracle.cost_grid(s)
+    bar = 1e-6 if precision == "mixed" else 1e-9
+    for q in (0, 37):
+        o = oracle.pins(C, pairs[q]["a"], pairs[q]["b"], want_plan=False, eta=eta, K=K)
+        rel = abs(rs[q]["cost"] - o["cost"]) / o["cost"]
+        assert rel <= bar, (q, rel)
