@@ -1593,18 +1593,46 @@ __global__ __launch_bounds__(256) void k_init_ck(const DevInst* __restrict__ ins
     }
 }
 
-// a0: dense squared-Euclidean cost of point clouds (unscaled), one thread per entry.
+// a0 for point clouds: C_ij = |x_i|^2 + |y_j|^2 - 2 <x_i, y_j> with the inner
+// products on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  Block = 4 waves,
+// a 32x32 tile of C; each wave a 16x16 tile, k in steps of 4 (zero-padded past
+// d).  Operand layout of the instruction: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; it receives D[4r + l/16][l%16] in its r-th result, r = 0..3.  The squared norms
+// come from the same operand loads (partial over the lane's k slots, summed
+// over the 4 lanes sharing l%16).  Rounding of nearly equal points can make
+// the expansion slightly negative; it is clamped at 0.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_points_cost(const double* __restrict__ x, const double* __restrict__ y,
                                                      int m, int n, int d, double* __restrict__ C) {
-    const long mn = (long)m * n;
-    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < mn; q += (long)gridDim.x * 256) {
-        const int i = (int)(q / n), j = (int)(q - (long)i * n);
-        double s = 0.0;
-        for (int k = 0; k < d; ++k) {
-            const double t = x[(long)i * d + k] - y[(long)j * d + k];
-            s += t * t;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i0 = blockIdx.y * 32 + (w >> 1) * 16, j0 = blockIdx.x * 32 + (w & 1) * 16;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ia = i0 + lr, jb = j0 + lr;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    double xn = 0.0, yn = 0.0;
+    for (int k0 = 0; k0 < d; k0 += 4) {
+        const int k = k0 + lk;
+        const double av = (ia < m && k < d) ? x[(long)ia * d + k] : 0.0;
+        const double bv = (jb < n && k < d) ? y[(long)jb * d + k] : 0.0;
+        xn += av * av;
+        yn += bv * bv;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    // |x_ia|^2, |y_jb|^2: sum over the four lanes with the same l % 16
+    xn += __shfl_xor(xn, 16);
+    xn += __shfl_xor(xn, 32);
+    yn += __shfl_xor(yn, 16);
+    yn += __shfl_xor(yn, 32);
+    double xr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) xr[r] = __shfl(xn, 4 * r + lk);  // norm of row i0 + 4 r + lk
+    const int j = j0 + lr;
+    if (j < n) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 4 * r + lk;
+            if (i < m) C[(long)i * n + j] = fmax(0.0, (xr[r] + yn) - 2.0 * acc[r]);
         }
-        C[q] = s;
     }
 }
 
@@ -1941,10 +1969,7 @@ void launch_init(const LaunchCtx& L, int base_src) {
 }
 
 void launch_points_cost(hipStream_t st, const double* x, const double* y, int m, int n, int d, double* C) {
-    const long mn = (long)m * n;
-    int blocks = (int)((mn + 255) / 256);
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_points_cost, dim3(blocks), dim3(256), 0, st, x, y, m, n, d, C);
+    hipLaunchKernelGGL(k_points_cost, dim3((n + 31) / 32, (m + 31) / 32), dim3(256), 0, st, x, y, m, n, d, C);
 }
 
 void launch_cost_max(const LaunchCtx& L, double* scratch, int nblk, int exponent_uses_base) {

@@ -326,3 +326,21 @@ def test_full_size_batch_sampled_parity(ctx, precision):
         o = oracle.pins(C, pairs[q]["a"], pairs[q]["b"], want_plan=False, eta=eta, K=K)
         rel = abs(rs[q]["cost"] - o["cost"]) / o["cost"]
         assert rel <= bar, (q, rel)
+
+
+@pytest.mark.parametrize("m,n,d", [(77, 50, 2), (45, 130, 8), (100, 64, 32), (33, 17, 3)])
+def test_points_cost_on_matrix_cores_parity(ctx, m, n, d):
+    """Point-cloud cost built with the FP64 matrix cores (ragged 32x32 tiles,
+    d not a multiple of 4): parity with the oracle's direct sum of squares."""
+    print("case points m=%d n=%d d=%d" % (m, n, d), flush=True)
+    g = np.random.default_rng(900 + d)
+    x, y = g.uniform(0, 1, (m, d)), g.uniform(0, 1, (n, d))
+    a, b = g.uniform(0.2, 1, m), g.uniform(0.2, 1, n)
+    a, b = a / a.sum(), b / b.sum()
+    C = oracle.cost_points(x, y)
+    eta, K = 0.02, 6
+    prm = P.params(eta=eta, max_outer=K)
+    gr = gpu_solve(ctx, dict(kind=P.COST_POINTS, x=x, y=y, a=a, b=b), prm)
+    gr["_C"] = C
+    o = oracle.pins(C, a, b, eta=eta, K=K)
+    check_parity(gr, o, a, b)
