@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-launch HIP events")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the materialised-cost Sinkhorn sweep measurement (16384 x 16384 FP64 cost)")
+    ap.add_argument("--sweep-only", action="store_true", help="only run the materialised-cost sweep measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
@@ -125,6 +128,10 @@ def main():
                  beta=torch.empty(n, dtype=torch.float64, device=dev)) for _ in pairs]
     prec = P.MIXED if args.precision == "mixed" else P.FP64
     ctx = P.Context(0)
+    if args.sweep_only:
+        print(json.dumps(dict(sinkhorn_sweep=sweep_roofline(P, ctx, torch, np, dev))), flush=True)
+        ctx.close()
+        return
     stream = torch.cuda.current_stream()
     st = stream.cuda_stream
 
@@ -223,6 +230,9 @@ def main():
         variants["plain_single_instance_ms"] = [round(1e3 * v, 2) for v in lat]
         line["variants"] = variants
 
+    if not args.no_sweep:
+        line["sinkhorn_sweep"] = sweep_roofline(P, ctx, torch, np, dev)
+
     if not args.no_cpu_baseline:
         import oracle
 
@@ -239,6 +249,60 @@ def main():
                                 gpu_resid=g0["resid"], oracle_resid=ref["resid"], bar=1e-6)
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def sweep_roofline(P, ctx, torch, np, dev, side=16384, sweeps=7):
+    """HBM rate of the Sinkhorn half-sweeps on a materialised cost.
+
+    A dense side x side FP64 cost (2.15 GB at 16384) with random marginals;
+    `sweeps` warm-up iterations (warm-up tolerance 0, no Newton steps), K = 1,
+    timed per launch by the library's HIP events.  The library launches the
+    warm-up in chunks of 1, 2, 4, ... iterations between readbacks, so 7 = 1+2+4
+    iterations make every launch a full sweep.  Algorithmic bytes per
+    half-sweep: the cost once (8 B per entry) plus the potentials (2 (m + n)
+    8-byte words); the dual vectors are negligible at this size.
+    """
+    m = n = side
+    g = torch.Generator(device=dev)
+    g.manual_seed(250203749)
+    C = torch.rand((m, n), dtype=torch.float64, device=dev, generator=g)
+    a = torch.rand(m, dtype=torch.float64, device=dev, generator=g) + 0.01
+    b = torch.rand(n, dtype=torch.float64, device=dev, generator=g) + 0.01
+    a /= a.sum()
+    b /= b.sum()
+    prob = dict(kind=P.COST_DENSE, m=m, n=n, C=C, a=a, b=b, cost_scale=1.0)
+    out = dict(alpha=torch.empty(m, dtype=torch.float64, device=dev), beta=torch.empty(n, dtype=torch.float64, device=dev))
+    res = {}
+    bytes_per_sweep = 8.0 * m * n + 16.0 * (m + n)
+    # a practical read ceiling on the same tensor: torch's own reduction over it
+    best = None
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        C.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    res["torch_sum_same_tensor"] = dict(ms=round(best, 3), achieved_GBs=round(8.0 * m * n / (best * 1e-3) / 1e9, 1))
+    for name, prec in (("mixed", P.MIXED), ("fp64", P.FP64)):
+        prm = P.params(eta=0.1, max_outer=1, max_sinkhorn=sweeps, max_newton=0, warm_tol=0.0, precision=prec,
+                       profile=1)
+        _, r = ctx.solve_device(prob, prm, out, stream=torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        ent = {}
+        for k in ("row_lse", "col_lse"):
+            calls = r["kern_calls"][k]
+            if calls:
+                us = 1e3 * r["kern_ms"][k] / calls
+                gbs = bytes_per_sweep / (us * 1e-6) / 1e9
+                ent[k] = dict(avg_launch_us=round(us, 2), achieved_GBs=round(gbs, 1),
+                              frac=round(gbs / PEAK_HBM_GBS, 4), launches=calls)
+        res[name] = ent
+    del C
+    torch.cuda.empty_cache()
+    return dict(workload="dense %dx%d FP64 cost (%.2f GB), %d warm-up iterations" % (m, n, 8.0 * m * n / 1e9, sweeps),
+                bytes_per_half_sweep=bytes_per_sweep, peak_GBs=PEAK_HBM_GBS, **res)
 
 
 def _traffic(kernel):

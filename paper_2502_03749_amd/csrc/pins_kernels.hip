@@ -129,12 +129,22 @@ __device__ __forceinline__ int wave_sum_i(int v) {
 }
 
 // (max, sum) pairs of log-sum-exp; an empty pair is (-inf, 0).
+// ex<T>(y, T64): exp in the sweep's precision (float: hardware exp; double:
+// the table-driven texp below with its table T64 in LDS).
+__device__ __forceinline__ double texp(double x, const double* T);
 template <class T>
-__device__ __forceinline__ T ex(double y);
+__device__ __forceinline__ T ex(double y, const double* T64);
 template <>
-__device__ __forceinline__ double ex<double>(double y) { return exp(y); }
+__device__ __forceinline__ double ex<double>(double y, const double* T64) { return texp(y, T64); }
 template <>
-__device__ __forceinline__ float ex<float>(double y) { return __expf((float)y); }
+__device__ __forceinline__ float ex<float>(double y, const double*) { return __expf((float)y); }
+// the same without a table (the few merges of partial pairs)
+template <class T>
+__device__ __forceinline__ T exs(double y);
+template <>
+__device__ __forceinline__ double exs<double>(double y) { return exp(y); }
+template <>
+__device__ __forceinline__ float exs<float>(double y) { return __expf((float)y); }
 
 // exp(x) in double by Tang's table-driven method (P. T. P. Tang, ACM TOMS
 // 15(2), 1989): x = (64k + j) ln2/64 + r with |r| <= ln2/128, so that
@@ -164,8 +174,8 @@ __device__ __forceinline__ double texp(double x, const double* T) {
 template <class T>
 __device__ __forceinline__ void lse_combine(double& mx, T& sm, double m2, T s2) {
     const double M = fmax(mx, m2);
-    const T u = (mx == -INFINITY) ? T(0) : sm * ex<T>(mx - M);
-    const T v = (m2 == -INFINITY) ? T(0) : s2 * ex<T>(m2 - M);
+    const T u = (mx == -INFINITY) ? T(0) : sm * exs<T>(mx - M);
+    const T v = (m2 == -INFINITY) ? T(0) : s2 * exs<T>(m2 - M);
     mx = M;
     sm = u + v;
 }
@@ -341,6 +351,9 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + w;
     __shared__ double serr[4];
+    __shared__ double sT[64];
+    texp_table(sT);
+    __syncthreads();
     double err = 0.0;
     if (i < m) {
         const double kap = ctrl[b].kappa, ie = kp.inv_eta;
@@ -359,13 +372,13 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
                 cm = fmax(cm, z[u]);
             }
             if (cm > mx) {
-                sm *= ex<T>(mx - cm);
+                sm *= ex<T>(mx - cm, sT);
                 mx = cm;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * 64 + lane;
-                if (j < n) sm += ex<T>(z[u] - mx);
+                if (j < n) sm += ex<T>(z[u] - mx, sT);
             }
         }
         wave_lse(mx, sm);
@@ -400,6 +413,8 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
     count_work(ctrl, b, W_COL, m, n);
     const int i0 = rb * I.R, i1 = min(m, i0 + I.R);
     __shared__ double sF[TILE_RMAX + 4];
+    __shared__ double sT[64];
+    texp_table(sT);
     if ((int)threadIdx.x < TILE_RMAX + 4) sF[threadIdx.x] = (i0 + (int)threadIdx.x < i1) ? I.F[i0 + threadIdx.x] : 0.0;
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
@@ -419,12 +434,12 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
             cm = fmax(cm, z[u]);
         }
         if (cm > mx) {
-            sm *= ex<T>(mx - cm);
+            sm *= ex<T>(mx - cm, sT);
             mx = cm;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (i + u < i1) sm += ex<T>(z[u] - mx);
+            if (i + u < i1) sm += ex<T>(z[u] - mx, sT);
     }
     reinterpret_cast<double2*>(I.part)[(long)rb * n + j] = make_double2(mx, (double)sm);
 }
