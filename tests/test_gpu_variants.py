@@ -1,0 +1,74 @@
+"""The paper's comparison variants, run by the same HIP kernels through the C ABI
+(Section 5.1, methods (1)-(4)): each is a parameter setting of Alg. 2.
+
+* Sinkhorn (no EPPA): K = 1, Sinkhorn iterations to a tight marginal error, no
+  Newton steps (the entropic plan at eps = eta);
+* Newton (no EPPA): K = 1, the default warm-up and sparse Newton;
+* Sinkhorn + EPPA: K outer iterations, every subproblem solved by Sinkhorn;
+* PINS: the defaults.
+
+Each variant is compared with the oracle run with the same parameters, and the
+finite-K equivalence (the plan of K outer iterations at eta is the entropic
+plan at eta / K) is checked across variants on the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2502_03749_amd as P  # noqa: E402
+
+from test_gpu_parity import _rand, check_parity, gpu_solve  # noqa: E402
+
+VARIANTS = {
+    "sinkhorn": dict(gpu=dict(max_outer=1, max_sinkhorn=200000, max_newton=0, warm_tol=1e-12, final_tol=1e-10),
+                     orc=dict(K=1, T1=200000, T2=0, warm_tol=1e-12, final_tol=1e-10)),
+    "newton": dict(gpu=dict(max_outer=1), orc=dict(K=1)),
+    "sinkhorn_eppa": dict(gpu=dict(max_outer=8, max_sinkhorn=200000, max_newton=0, warm_tol=1e-12, final_tol=1e-10),
+                          orc=dict(K=8, T1=200000, T2=0, warm_tol=1e-12, final_tol=1e-10)),
+    "pins": dict(gpu=dict(max_outer=8), orc=dict(K=8)),
+}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_variant_parity(ctx, variant):
+    print("case variant %s" % variant, flush=True)
+    C, a, b = _rand(40, 30, 2024)
+    eta = 0.05
+    v = VARIANTS[variant]
+    g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), P.params(eta=eta, **v["gpu"]))
+    g["_C"] = C
+    o = oracle.pins(C, a, b, eta=eta, **v["orc"])
+    assert o["status"] == 0
+    check_parity(g, o, a, b)
+
+
+def test_variants_reach_the_same_finite_K_plan(ctx):
+    """Sinkhorn at eta/K, Sinkhorn + EPPA and PINS at (eta, K): one plan."""
+    print("case variant equivalence", flush=True)
+    C, a, b = _rand(40, 30, 2025)
+    eta, K = 0.05, 8
+    prob = dict(kind=P.COST_DENSE, C=C, a=a, b=b)
+    sk = gpu_solve(ctx, prob, P.params(eta=eta / K, max_outer=1, max_sinkhorn=200000, max_newton=0, warm_tol=1e-12,
+                                       final_tol=1e-10))
+    se = gpu_solve(ctx, prob, P.params(eta=eta, max_outer=K, max_sinkhorn=200000, max_newton=0, warm_tol=1e-12,
+                                       final_tol=1e-10))
+    pn = gpu_solve(ctx, prob, P.params(eta=eta, max_outer=K))
+    for r in (sk, se, pn):
+        assert r["rc"] == 0 and r["resid"] <= 1e-10
+    assert np.abs(sk["X"] - pn["X"]).sum() <= 1e-9
+    assert np.abs(se["X"] - pn["X"]).sum() <= 1e-9
+    assert abs(sk["cost"] - pn["cost"]) / pn["cost"] <= 1e-9
