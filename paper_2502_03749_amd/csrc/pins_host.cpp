@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -146,8 +148,9 @@ InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, 
 
 struct Batch {
     std::vector<InstPlan> plans;
-    size_t insts = 0, ctrl = 0, scratch = 0, total = 0;
+    size_t insts = 0, ctrl = 0, scratch = 0, offs = 0, total = 0;
     int max_m = 0, max_n = 0, max_mn = 0, max_tiles = 0;
+    std::vector<int> toff, roff;  // prefix sums of tiles and row blocks (count + 1 each)
 };
 
 constexpr int SCRATCH_BLK = 512;
@@ -158,6 +161,9 @@ Batch plan_batch(const pins_problem* probs, int count, const pins_params& p, boo
     B.insts = cv.take(sizeof(DevInst) * count);
     B.ctrl = cv.take(sizeof(Ctrl) * count);
     B.scratch = cv.take(sizeof(double) * (size_t)SCRATCH_BLK * count);
+    B.offs = cv.take(sizeof(int) * 2 * (size_t)(count + 1));
+    B.toff.assign(1, 0);
+    B.roff.assign(1, 0);
     for (int q = 0; q < count; ++q) {
         const bool want_x = host_api && res && res[q].X;
         B.plans.push_back(plan_instance(cv, probs[q], p, host_api, want_x));
@@ -166,6 +172,10 @@ Batch plan_batch(const pins_problem* probs, int count, const pins_params& p, boo
         B.max_n = std::max(B.max_n, P.n);
         B.max_mn = std::max(B.max_mn, P.m + P.n);
         B.max_tiles = std::max(B.max_tiles, P.nrb * P.ncb);
+        const long nt = (long)B.toff.back() + (long)P.nrb * P.ncb, nr = (long)B.roff.back() + (P.m + 3) / 4;
+        if (nt > INT32_MAX || nr > INT32_MAX) fail(PINS_EINVAL, "batch too large for one launch");
+        B.toff.push_back((int)nt);
+        B.roff.push_back((int)nr);
     }
     B.total = cv.off;
     return B;
@@ -416,10 +426,15 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         }
     }
     {
-        DevInst* h = (DevInst*)((char*)pinned(ctx, sizeof(Ctrl) * count + sizeof(DevInst) * count) +
-                                sizeof(Ctrl) * count);
+        char* pin = (char*)pinned(ctx, sizeof(Ctrl) * count + sizeof(DevInst) * count +
+                                           sizeof(int) * 2 * (size_t)(count + 1));
+        DevInst* h = (DevInst*)(pin + sizeof(Ctrl) * count);
         std::memcpy(h, hI.data(), sizeof(DevInst) * count);
         HIPCHK(hipMemcpyAsync(d_insts, h, sizeof(DevInst) * count, hipMemcpyHostToDevice, st));
+        int* ho = (int*)(pin + sizeof(Ctrl) * count + sizeof(DevInst) * count);
+        std::memcpy(ho, B.toff.data(), sizeof(int) * (count + 1));
+        std::memcpy(ho + count + 1, B.roff.data(), sizeof(int) * (count + 1));
+        HIPCHK(hipMemcpyAsync(ws + B.offs, ho, sizeof(int) * 2 * (count + 1), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemsetAsync(d_ctrl, 0, sizeof(Ctrl) * count, st));
         HIPCHK(hipStreamSynchronize(st));  // the pinned staging area is reused by readback()
     }
@@ -434,6 +449,8 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     L.max_n = B.max_n;
     L.max_mn = B.max_mn;
     L.max_tiles = B.max_tiles;
+    L.total_tiles = B.toff.back();
+    L.total_rowblk = B.roff.back();
     // the CG's copy of S: 16-bit indices whenever they fit, float values in
     // mixed precision (the CG vectors and all sums stay double)
     L.sp_fmt = ((B.max_m <= 65536 && B.max_n <= 65536) ? 1 : 0) | (p.precision == PINS_MIXED ? 2 : 0);
@@ -454,6 +471,9 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     kp.ls_max = p.ls_max;
     kp.nlev = p.rho_levels;
     kp.shift_mode = p.shift_mode;
+    kp.count = count;
+    kp.toff = (const int*)(ws + B.offs);
+    kp.roff = kp.toff + count + 1;
     kp.last = 0;
 
     // a0: cost scale (1/max over the dense cost unless given) and finiteness

@@ -102,7 +102,11 @@ struct KP {
     double cg_rtol, ls_beta, ls_c1, log_rho;
     double budget;
     int T1, T2, cg_max, ls_max;
-    int nlev, shift_mode, last, pad;
+    int nlev, shift_mode, last, count;  // count: instances in the batch
+    // flat grids over uneven batches: toff / roff hold count + 1 prefix sums of
+    // the per-instance tile counts (nrb * ncb) and row-block counts (ceil(m/4))
+    const int* toff;
+    const int* roff;
 };
 
 }  // namespace pins

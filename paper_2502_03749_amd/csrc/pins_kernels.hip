@@ -1,8 +1,10 @@
 // pins_kernels.hip -- HIP kernels of the PINS hot path for MI355X (gfx950).
 //
-// Every kernel covers a batch of independent instances: blockIdx.y is the
-// instance, and each instance's control block (Ctrl::phase) decides whether
-// the instance takes part in a launch.  An instance's arithmetic never
+// Every kernel covers a batch of independent instances: the tile and row
+// kernels run a flat grid whose blocks map to (instance, block) through
+// per-instance prefix sums (uneven sizes waste no blocks); the per-instance
+// merges and setup kernels use blockIdx.y as the instance.  Each instance's
+// control block (Ctrl::phase) decides whether it takes part in a launch.  An instance's arithmetic never
 // depends on which other instances are in the batch, so a batched result is
 // bitwise the result of the same problem solved alone.
 //
@@ -327,8 +329,28 @@ __device__ __forceinline__ bool phase_in(const Ctrl* ctrl, int b, int mask) {
 }
 
 // one writer per instance (its first block) records the entries a pass visits
-__device__ __forceinline__ void count_work(Ctrl* ctrl, int b, int kind, int m, int n) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[b].work[kind] += (double)m * (double)n;
+// l: the block's index inside its instance
+__device__ __forceinline__ void count_work(Ctrl* ctrl, int b, int kind, int m, int n, int l) {
+    if (l == 0 && threadIdx.x == 0) ctrl[b].work[kind] += (double)m * (double)n;
+}
+
+// Flat grids over an uneven batch: block blockIdx.x belongs to the instance b
+// with off[b] <= blockIdx.x < off[b + 1] and is its block l = blockIdx.x - off[b]
+// (off: count + 1 prefix sums of the per-instance block counts).
+struct BlkRef {
+    int b, l;
+};
+__device__ __forceinline__ BlkRef blk_ref(const int* __restrict__ off, int count) {
+    const int x = blockIdx.x;
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return BlkRef{lo, x - off[lo]};
 }
 
 // ---------------------------------------------------------------------------
@@ -342,14 +364,14 @@ __device__ __forceinline__ void count_work(Ctrl* ctrl, int b, int kind, int m, i
 template <class Src, class T>
 __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
                                                  int mask) {
-    const int b = blockIdx.y;
+    const BlkRef br = blk_ref(kp.roff, kp.count);
+    const int b = br.b, rl = br.l;
     if (!phase_in(ctrl, b, mask)) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n;
-    if ((int)blockIdx.x * 4 >= m) return;
-    count_work(ctrl, b, W_ROW, m, n);
+    count_work(ctrl, b, W_ROW, m, n, rl);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + w;
+    const int i = rl * 4 + w;
     __shared__ double serr[4];
     __shared__ double sT[64];
     texp_table(sT);
@@ -393,7 +415,7 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
     }
     if (lane == 0) serr[w] = err;
     __syncthreads();
-    if (threadIdx.x == 0) I.blk[blockIdx.x] = ((serr[0] + serr[1]) + serr[2]) + serr[3];
+    if (threadIdx.x == 0) I.blk[rl] = ((serr[0] + serr[1]) + serr[2]) + serr[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -404,13 +426,13 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
 template <class Src, class T>
 __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
                                                  int mask) {
-    const int b = blockIdx.y;
+    const BlkRef br = blk_ref(kp.toff, kp.count);
+    const int b = br.b, tl = br.l;
     if (!phase_in(ctrl, b, mask)) return;
     const DevInst& I = insts[b];
-    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
-    if (rb >= I.nrb) return;
+    const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
     const int m = I.m, n = I.n;
-    count_work(ctrl, b, W_COL, m, n);
+    count_work(ctrl, b, W_COL, m, n, tl);
     const int i0 = rb * I.R, i1 = min(m, i0 + I.R);
     __shared__ double sF[TILE_RMAX + 4];
     __shared__ double sT[64];
@@ -543,13 +565,13 @@ __device__ __forceinline__ void tile_level_totals(const unsigned* hw, int nlev, 
 
 template <class Src>
 __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
-    const int b = blockIdx.y;
+    const BlkRef br = blk_ref(kp.toff, kp.count);
+    const int b = br.b, tl = br.l;
     if (ctrl[b].phase != PH_NEWTON || ctrl[b].grad_ready) return;
     const DevInst& I = insts[b];
-    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
-    if (rb >= I.nrb) return;
+    const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
     const int m = I.m, n = I.n;
-    count_work(ctrl, b, W_GRAD, m, n);
+    count_work(ctrl, b, W_GRAD, m, n, tl);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ unsigned hw[NLEV * TILE_C / 4];  // [level][thread] byte counters
     __shared__ double wsum[TILE_RMAX][4];
@@ -704,13 +726,13 @@ __device__ __forceinline__ int quad_slot(int start, int nq, int e) {
 
 template <class Src>
 __global__ __launch_bounds__(256) void k_count(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
-    const int b = blockIdx.y;
+    const BlkRef br = blk_ref(kp.toff, kp.count);
+    const int b = br.b, tl = br.l;
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
-    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
-    if (rb >= I.nrb) return;
+    const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
     const int m = I.m, n = I.n;
-    count_work(ctrl, b, W_FILL, m, n);
+    count_work(ctrl, b, W_FILL, m, n, tl);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
     __shared__ int wc[TILE_RMAX][4];
@@ -818,11 +840,11 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
 
 template <class Src, class IX, class VT>
 __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
-    const int b = blockIdx.y;
+    const BlkRef br = blk_ref(kp.toff, kp.count);
+    const int b = br.b, tl = br.l;
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
-    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
-    if (rb >= I.nrb) return;
+    const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
     const int m = I.m, n = I.n;
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
@@ -1292,13 +1314,13 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
 template <class Src>
 __global__ __launch_bounds__(256) void k_ls_first(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
                                                   KP kp) {
-    const int b = blockIdx.y;
+    const BlkRef br = blk_ref(kp.toff, kp.count);
+    const int b = br.b, tl = br.l;
     if (ctrl[b].phase != PH_NEWTON || ctrl[b].ls_state != LS_PENDING) return;
     const DevInst& I = insts[b];
-    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
-    if (rb >= I.nrb) return;
+    const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
     const int m = I.m, n = I.n;
-    count_work(ctrl, b, W_LS, m, n);
+    count_work(ctrl, b, W_LS, m, n, tl);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ unsigned hw[NLEV * TILE_C / 4];  // [level][thread] byte counters
     __shared__ double wsum[TILE_RMAX][4];
@@ -1357,7 +1379,7 @@ __global__ __launch_bounds__(256) void k_ls_first(const DevInst* __restrict__ in
     tile_level_totals(hw, nlev, I.hist);
     __shared__ double sh[4];
     const double bs = block_sum<256>(acc, sh);
-    if (threadIdx.x == 0) I.blk[blockIdx.x] = bs;
+    if (threadIdx.x == 0) I.blk[tl] = bs;
 }
 
 // Armijo test of the first trial: the block partials in fixed order (a kernel
@@ -1385,13 +1407,13 @@ __global__ __launch_bounds__(256) void k_ls_first_merge(const DevInst* __restric
 
 template <class Src, int NT>
 __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
-    const int b = blockIdx.y;
+    const BlkRef br = blk_ref(kp.toff, kp.count);
+    const int b = br.b, tl = br.l;
     if (ctrl[b].phase != PH_NEWTON || ctrl[b].ls_state != LS_PENDING) return;
     const DevInst& I = insts[b];
-    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
-    if (rb >= I.nrb) return;
+    const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
     const int m = I.m, n = I.n;
-    count_work(ctrl, b, W_LS, m, n);
+    count_work(ctrl, b, W_LS, m, n, tl);
     const int h0 = ctrl[b].ls_h;
     double al[NT];
     {
@@ -1439,7 +1461,7 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const double s = block_sum<256>(acc[t], sh);
-        if (threadIdx.x == 0) I.blk[(long)blockIdx.x * NT + t] = s;
+        if (threadIdx.x == 0) I.blk[(long)tl * NT + t] = s;
     }
 }
 
@@ -1749,12 +1771,12 @@ __global__ __launch_bounds__(1024) void k_potentials(const DevInst* __restrict__
 template <class Src>
 __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
                                                double K, int write_x) {
-    const int b = blockIdx.y;
+    const BlkRef br = blk_ref(kp.toff, kp.count);
+    const int b = br.b, tl = br.l;
     const DevInst& I = insts[b];
-    const int rb = blockIdx.x / I.ncb, cb = blockIdx.x - rb * I.ncb;
-    if (rb >= I.nrb) return;
+    const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
     const int m = I.m, n = I.n;
-    count_work(ctrl, b, W_FINAL, m, n);
+    count_work(ctrl, b, W_FINAL, m, n, tl);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ double red[TILE_RMAX][TILE_C + 1];
     __shared__ double sh[4];
@@ -1794,8 +1816,8 @@ __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts
     cst = block_sum<256>(cst, sh);
     ent = block_sum<256>(ent, sh);
     if (threadIdx.x == 0) {
-        I.blk[(long)blockIdx.x * 2] = cst;
-        I.blk[(long)blockIdx.x * 2 + 1] = ent;
+        I.blk[(long)tl * 2] = cst;
+        I.blk[(long)tl * 2 + 1] = ent;
     }
 }
 
@@ -1854,7 +1876,7 @@ static inline dim3 g2(int x, int y) { return dim3((unsigned)(x > 0 ? x : 1), (un
     } while (0)
 
 void launch_row_lse(const LaunchCtx& L, int src, bool f32, int mask) {
-    const dim3 g = g2((L.max_m + 3) / 4, L.count);
+    const dim3 g(L.total_rowblk);
 #define K_(S, T) hipLaunchKernelGGL((k_row_lse<S, T>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, mask)
     if (f32) {
         PINS_SRC_DISPATCH(src, K_, float);
@@ -1865,7 +1887,7 @@ void launch_row_lse(const LaunchCtx& L, int src, bool f32, int mask) {
 }
 
 void launch_col_lse(const LaunchCtx& L, int src, bool f32, int mask) {
-    const dim3 g = g2(L.max_tiles, L.count);
+    const dim3 g(L.total_tiles);
 #define K_(S, T) hipLaunchKernelGGL((k_col_lse<S, T>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, mask)
     if (f32) {
         PINS_SRC_DISPATCH(src, K_, float);
@@ -1882,7 +1904,7 @@ void launch_col_merge(const LaunchCtx& L, int mask) {
 }
 
 void launch_grad(const LaunchCtx& L, int src) {
-    const dim3 g = g2(L.max_tiles, L.count);
+    const dim3 g(L.total_tiles);
 #define K_(S) hipLaunchKernelGGL((k_grad<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
     PINS_SRC_DISPATCH(src, K_);
 #undef K_
@@ -1902,7 +1924,7 @@ static void launch_fill_t(const LaunchCtx& L, int src, dim3 g) {
 }
 
 void launch_sparsify(const LaunchCtx& L, int src) {
-    const dim3 g = g2(L.max_tiles, L.count);
+    const dim3 g(L.total_tiles);
 #define K_(S) hipLaunchKernelGGL((k_count<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
     PINS_SRC_DISPATCH(src, K_);
 #undef K_
@@ -1941,7 +1963,7 @@ void launch_pcg(const LaunchCtx& L) {
 }
 
 void launch_ls(const LaunchCtx& L, int src, bool first) {
-    const dim3 g = g2(L.max_tiles, L.count);
+    const dim3 g(L.total_tiles);
     if (first) {
 #define K_(S) hipLaunchKernelGGL((k_ls_first<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
         PINS_SRC_DISPATCH(src, K_);
@@ -1995,7 +2017,7 @@ void launch_cost_max(const LaunchCtx& L, double* scratch, int nblk, int exponent
 
 void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x) {
     hipLaunchKernelGGL(k_potentials, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, K);
-    const dim3 g = g2(L.max_tiles, L.count);
+    const dim3 g(L.total_tiles);
 #define K_(S) hipLaunchKernelGGL((k_final<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, K, write_x ? 1 : 0)
     PINS_SRC_DISPATCH(base_src, K_);
 #undef K_

@@ -17,6 +17,7 @@ struct LaunchCtx {
     int count;
     int max_m, max_n, max_mn;  // maxima over the batch (max_mn = max m+n)
     int max_tiles;             // max nrb*ncb
+    int total_tiles, total_rowblk;  // sums over the batch (flat grids of the tile and row kernels)
     int sp_fmt;                // storage of S: bit 0 uint16 indices, bit 1 float values
 };
 
