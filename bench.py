@@ -228,6 +228,7 @@ def main():
             lat.append(time.perf_counter() - t1)
         variants["plain_single_instance_solves_per_s"] = nplain / sum(lat)
         variants["plain_single_instance_ms"] = [round(1e3 * v, 2) for v in lat]
+        variants["batched_uneven_points"] = uneven_points(P, ctx, torch, np, dev, W, st)
         line["variants"] = variants
 
     if not args.no_sweep:
@@ -249,6 +250,29 @@ def main():
                                 gpu_resid=g0["resid"], oracle_resid=ref["resid"], bar=1e-6)
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def uneven_points(P, ctx, torch, np, dev, W, st, count=256, K=20):
+    """Uneven batch: 256 point-cloud instances, m and n log-uniform in
+    [64, 2048], d cycling over 2, 8, 32 (cost on the FP64 matrix cores),
+    Dirichlet(1) + 1e-8 marginals, eta = 1e-2, K = 20, mixed precision, one call."""
+    insts = [W.batch_instance(i) for i in range(count)]
+    t = lambda v: torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev)
+    probs = [dict(kind=P.COST_POINTS, m=x["x"].shape[0], n=x["y"].shape[0], d=x["d"], x=t(x["x"]), y=t(x["y"]),
+                  a=t(x["a"]), b=t(x["b"])) for x in insts]
+    outs = [dict(alpha=torch.empty(p["m"], dtype=torch.float64, device=dev),
+                 beta=torch.empty(p["n"], dtype=torch.float64, device=dev)) for p in probs]
+    prm = P.params(eta=1e-2, max_outer=K, precision=P.MIXED)
+    ctx.solve_batch_device(probs, prm, outs, stream=st)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, rs = ctx.solve_batch_device(probs, prm, outs, stream=st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if rc < 0 or any(r["status"] != 0 for r in rs):
+        raise RuntimeError("uneven batch: a solve did not converge")
+    return dict(instances=count, K=K, eta=1e-2, sum_mn=int(sum(p["m"] * p["n"] for p in probs)),
+                solves_per_s=count / dt, ms=1e3 * dt)
 
 
 def sweep_roofline(P, ctx, torch, np, dev, side=16384, sweeps=7):

@@ -344,3 +344,39 @@ def test_points_cost_on_matrix_cores_parity(ctx, m, n, d):
     gr["_C"] = C
     o = oracle.pins(C, a, b, eta=eta, K=K)
     check_parity(gr, o, a, b)
+
+
+def test_uneven_batch_of_point_clouds(ctx):
+    """256 uneven point-cloud instances (m, n log-uniform in [64, 2048], d cycling
+    over 2, 8, 32, Dirichlet marginals, eta = 1e-2, K = 20, mixed precision) in one
+    call: every instance converges (status OK, residual <= 1e-10, gauge); the
+    three smallest match the oracle (<= 1e-6); two instances solved alone give
+    bitwise the batched potentials."""
+    print("case uneven batch 256 point clouds", flush=True)
+    insts = [W.batch_instance(i) for i in range(256)]
+    probs = [dict(kind=P.COST_POINTS, m=x["x"].shape[0], n=x["y"].shape[0], d=x["d"], x=_t(x["x"]), y=_t(x["y"]),
+                  a=_t(x["a"]), b=_t(x["b"])) for x in insts]
+    outs = [dict(alpha=torch.empty(p["m"], dtype=torch.float64, device=DEV),
+                 beta=torch.empty(p["n"], dtype=torch.float64, device=DEV)) for p in probs]
+    eta, K = 1e-2, 20
+    prm = P.params(eta=eta, max_outer=K, precision=P.MIXED)
+    st = torch.cuda.current_stream().cuda_stream
+    rc, rs = ctx.solve_batch_device(probs, prm, outs, stream=st)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for q, r in enumerate(rs):
+        assert r["status"] == 0 and r["resid"] <= 1e-10, (q, r["status"], r["resid"])
+        al, be = outs[q]["alpha"].cpu().numpy(), outs[q]["beta"].cpu().numpy()
+        assert abs(insts[q]["a"] @ al - insts[q]["b"] @ be) <= 1e-12
+    small = sorted(range(256), key=lambda q: insts[q]["x"].shape[0] * insts[q]["y"].shape[0])[:3]
+    for q in small:
+        C = oracle.cost_points(insts[q]["x"], insts[q]["y"])
+        o = oracle.pins(C, insts[q]["a"], insts[q]["b"], want_plan=False, eta=eta, K=K)
+        assert abs(rs[q]["cost"] - o["cost"]) / o["cost"] <= 1e-6, q
+    for q in (small[0], 101):
+        out1 = dict(alpha=torch.empty(probs[q]["m"], dtype=torch.float64, device=DEV),
+                    beta=torch.empty(probs[q]["n"], dtype=torch.float64, device=DEV))
+        _, r1 = ctx.solve_device(probs[q], prm, out1, stream=st)
+        torch.cuda.synchronize()
+        assert torch.equal(out1["alpha"], outs[q]["alpha"]) and torch.equal(out1["beta"], outs[q]["beta"]), q
+        assert r1["cost"] == rs[q]["cost"]
