@@ -57,8 +57,9 @@ struct DevInst {
     double* blk;    // per-block scalars: >= max blocks * LS_T
     double* blk2;   // second per-block scalar area (merge kernels)
     int* hist;      // NLEV Sparsify histogram (entries per highest kept level)
-    int* cntr;      // m * ncb kept entries per (row, column block) at the chosen level
-    int* cntc;      // nrb * n kept entries per (row block, column) at the chosen level
+    int* cntr;      // m * ncb kept entries per (row, column block) at the chosen level,
+                    // turned by the scan into exclusive prefix sums over the column blocks
+    int* cntc;      // nrb * n the same per (row block, column), prefix sums over the row blocks
     // S (CSR) and S^T (CSC).  Every row of S and of S^T starts at a multiple
     // of 4 entries and is padded to one with (index 0, value 0), so the CG
     // reads them in aligned quads; within a row of nq quads the quads are

@@ -770,15 +770,25 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
     const int m = I.m, n = I.n, ncb = I.ncb, nrb = I.nrb, N = m + n;
     __shared__ int ish[16];
     __shared__ long lsh[16];
-    const int* __restrict__ cr = I.cntr;
-    const int* __restrict__ cc = I.cntc;
-    // kept entries of row k of M (k < m: row of S; else column k - m)
+    int* __restrict__ cr = I.cntr;
+    int* __restrict__ cc = I.cntc;
+    // kept entries of row k of M (k < m: row of S; else column k - m); the
+    // per-block counts become exclusive prefix sums in place, which the fill
+    // reads as the entry index of its first kept entry (called once per k)
     auto kept = [&](int k) {
         int c = 0;
         if (k < m)
-            for (int q = 0; q < ncb; ++q) c += cr[(long)k * ncb + q];
+            for (int q = 0; q < ncb; ++q) {
+                const int v = cr[(long)k * ncb + q];
+                cr[(long)k * ncb + q] = c;
+                c += v;
+            }
         else
-            for (int q = 0; q < nrb; ++q) c += cc[(long)q * n + (k - m)];
+            for (int q = 0; q < nrb; ++q) {
+                const int v = cc[(long)q * n + (k - m)];
+                cc[(long)q * n + (k - m)] = c;
+                c += v;
+            }
         return c;
     };
     long real = 0;
@@ -856,9 +866,7 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
         const int i = i0 + threadIdx.x;
         sF[threadIdx.x] = I.F[i];
         sLa[threadIdx.x] = I.loga[i];
-        int e0 = 0;
-        for (int q = 0; q < cb; ++q) e0 += I.cntr[(long)i * I.ncb + q];
-        sE0[threadIdx.x] = e0;
+        sE0[threadIdx.x] = I.cntr[(long)i * I.ncb + cb];  // prefix over the column blocks (k_scan)
         sStart[threadIdx.x] = I.rowptr[i];
         sNq[threadIdx.x] = (I.rowptr[i + 1] - I.rowptr[i]) >> 2;
     }
@@ -871,7 +879,7 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
     int ce = 0, cstart = 0, cnq = 0;  // entry index within column j, its start and quad count
     if (valid) {
-        for (int q = 0; q < rb; ++q) ce += I.cntc[(long)q * n + j];
+        ce = I.cntc[(long)rb * n + j];  // prefix over the row blocks (k_scan)
         cstart = I.colptr[j];
         cnq = (I.colptr[j + 1] - cstart) >> 2;
     }
