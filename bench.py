@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-launch HIP events")
+    ap.add_argument("--lanes", type=int, default=2,
+                    help="concurrent lanes of the batched call (params.streams); results do not depend on it")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the materialised-cost Sinkhorn sweep measurement (16384 x 16384 FP64 cost)")
     ap.add_argument("--sweep-only", action="store_true", help="only run the materialised-cost sweep measurement")
@@ -141,7 +143,27 @@ def main():
             raise RuntimeError("solve failed: rc=%d statuses=%s" % (rc, [r["status"] for r in rs]))
         return rs
 
-    prm = P.params(eta=args.eta, max_outer=args.K, precision=prec, profile=0 if args.no_profile else 1)
+    # One untimed step with every launch timed gives the kernel classes' shares
+    # and the dominant class; the timed steps then record HIP events around
+    # that class's launches only (timing every launch costs ~7% of the step).
+    def aggregate(results):
+        kms, kwork, kcalls = {}, {}, {}
+        for rs in results:
+            seen = set()
+            for r in rs:
+                if r["group"] not in seen:  # kernel times are per lane, shared by its instances
+                    seen.add(r["group"])
+                    for k, v in r["kern_ms"].items():
+                        kms[k] = kms.get(k, 0.0) + v
+                        kcalls[k] = kcalls.get(k, 0) + r["kern_calls"][k]
+                for k, v in r["kern_work"].items():
+                    kwork[k] = kwork.get(k, 0.0) + v
+        return kms, kwork, kcalls
+
+    base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=args.lanes)
+    share_ms, _, _ = aggregate([step(P.params(profile=1, **base))])
+    dom = max(share_ms, key=share_ms.get)
+    prm = P.params(profile=0 if args.no_profile else 1, profile_mask=1 << P.KERNEL_NAMES.index(dom), **base)
     for _ in range(args.warmup):
         step(prm)
     torch.cuda.synchronize()
@@ -156,20 +178,9 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
 
     # roofline of the dominant kernel class over the timed region
-    kms, kwork, kcalls = {}, {}, {}
-    for rs in results:
-        seen = set()
-        for r in rs:
-            if r["group"] not in seen:  # kernel times are per lane, shared by its instances
-                seen.add(r["group"])
-                for k, v in r["kern_ms"].items():
-                    kms[k] = kms.get(k, 0.0) + v
-                    kcalls[k] = kcalls.get(k, 0) + r["kern_calls"][k]
-            for k, v in r["kern_work"].items():
-                kwork[k] = kwork.get(k, 0.0) + v
+    kms, kwork, kcalls = aggregate(results)
     roofline = None
-    if kms and sum(kms.values()) > 0:
-        dom = max(kms, key=kms.get)
+    if kms.get(dom, 0.0) > 0:
         calls = max(kcalls.get(dom, 0), 1)
         avg_ms = kms[dom] / calls
         fpe = FLOPS_PER_ENTRY.get(dom)
@@ -189,8 +200,9 @@ def main():
         else:
             roofline = dict(kernel=dom, bound="latency", achieved=None, peak=None, unit=None, frac=None,
                             traffic=None, avg_launch_us=1e3 * avg_ms, launches=calls)
-        roofline["kernel_ms_share"] = {k: round(v / sum(kms.values()), 4) for k, v in
-                                       sorted(kms.items(), key=lambda kv: -kv[1]) if v > 0}
+        roofline["kernel_ms_share"] = {k: round(v / sum(share_ms.values()), 4) for k, v in
+                                       sorted(share_ms.items(), key=lambda kv: -kv[1]) if v > 0}
+        roofline["kernel_ms_share_from"] = "one untimed step with every launch timed"
 
     line = dict(metric="OT solves/sec at rel. cost error <=1e-6 (plain vs batched/served); p50/p99 latency",
                 value=value, unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -199,7 +211,7 @@ def main():
                 config=dict(workload="image-histogram pairs, 28x28 grid (m=n=784), squared grid distance/max "
                                      "streamed, eta=0.1, K=250, batched (one call per step)",
                             pairs=args.pairs, m=n, n=n, eta=args.eta, K=args.K, precision=args.precision,
-                            mode="batched"),
+                            mode="batched", lanes=args.lanes),
                 roofline=roofline)
 
     last = results[-1]

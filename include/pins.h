@@ -96,6 +96,8 @@ typedef struct {
     int32_t streams;      /* batch entry point: number of concurrent lanes (own HIP stream and host
                              thread each, instances split into contiguous groups, at most 4);
                              0 or 1 = one lane on the caller's stream; results do not depend on it */
+    int32_t profile_mask; /* with profile: bit k set = time the launches of kernel class k
+                             (PINS_K_*); 0 = every class.  Fewer timed classes, less overhead */
 } pins_params;
 
 /* One problem instance.  For pins_solve the pointers are host pointers, for

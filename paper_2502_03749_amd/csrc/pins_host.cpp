@@ -35,6 +35,7 @@ struct Lane {
     std::vector<int> ev_kind;
     size_t ev_used = 0;
     bool profile = false;
+    int profile_mask = 0;          // kernel classes timed (0 = all)
     hipStream_t stream = nullptr;  // owned stream (default priority)
 };
 
@@ -226,7 +227,7 @@ struct Prof {
     hipStream_t st;
     int kind = -1;
     Prof(Lane* c_, hipStream_t s, int k) : c(c_), st(s) {
-        if (!c->profile) return;
+        if (!c->profile || (c->profile_mask && !((c->profile_mask >> k) & 1))) return;
         kind = k;
         if (c->ev_used + 2 > c->events.size()) {
             for (int q = 0; q < 512; ++q) {
@@ -306,6 +307,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     }
     HIPCHK(hipSetDevice(ctx->device));
     ctx->profile = p.profile != 0;
+    ctx->profile_mask = p.profile_mask;
     ctx->ev_used = 0;
 
     // marginals are validated on the host (device arrays are copied back first)
@@ -749,6 +751,7 @@ void pins_params_default(pins_params* p) {
     p->shift_mode = PINS_SHIFT_IMPLICIT;
     p->profile = 0;
     p->streams = 0;
+    p->profile_mask = 0;
 }
 
 int pins_create(int device, pins_ctx** out) {
