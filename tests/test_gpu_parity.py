@@ -380,3 +380,44 @@ def test_uneven_batch_of_point_clouds(ctx):
         torch.cuda.synchronize()
         assert torch.equal(out1["alpha"], outs[q]["alpha"]) and torch.equal(out1["beta"], outs[q]["beta"]), q
         assert r1["cost"] == rs[q]["cost"]
+
+
+@pytest.mark.parametrize("cls", ["white", "gmm", "cauchy"])
+def test_large_grid_properties(ctx, cls):
+    """64x64 grids (m = n = 4096, cost streamed), eta = 1e-3, K = 10, mixed
+    precision, one pair per histogram class.  The oracle is far too slow at this
+    size, so the checks are properties that hold at any size: status and
+    marginal residual; the gauge; the returned plan equals
+    exp((alpha_i + beta_j - C_ij)/eps) on sampled entries (C from the grid
+    formula on the host); cost = <C, X> recomputed on the host; and the gap
+    identity cost - <a,alpha> - <b,beta> = eps*H(X) + <alpha, Xe - a> + <beta, X^T e - b>."""
+    s, eta, K = 64, 1e-3, 10
+    n = s * s
+    print("case grid64 %s" % cls, flush=True)
+    pr = W.grid_pair(cls, 0, s=s)
+    a, b = pr["a"], pr["b"]
+    prm = P.params(eta=eta, max_outer=K, precision=P.MIXED)
+    g = gpu_solve(ctx, dict(kind=P.COST_GRID, grid_s=s, a=a, b=b), prm)
+    assert g["rc"] == 0 and g["resid"] <= 1e-10
+    al, be, X, eps = g["alpha"], g["beta"], g["X"], g["eps"]
+    assert abs(eps - eta / K) <= 1e-15
+    assert abs(a @ al - b @ be) <= 1e-12
+    coords = np.array([(p // s, p % s) for p in range(n)], dtype=np.float64)
+    scale = 1.0 / (2.0 * (s - 1) ** 2)
+    rng = np.random.default_rng(7)
+    ii, jj = rng.integers(0, n, 4000), rng.integers(0, n, 4000)
+    Cs = ((coords[ii] - coords[jj]) ** 2).sum(1) * scale
+    Xs = np.exp((al[ii] + be[jj] - Cs) / eps)
+    assert np.all(np.abs(Xs - X[ii, jj]) <= 1e-12 + 1e-11 * X[ii, jj])
+    d0 = coords[:, 0][:, None] - coords[:, 0][None, :]
+    d1 = coords[:, 1][:, None] - coords[:, 1][None, :]
+    C = (d0 * d0 + d1 * d1) * scale
+    cost = float((C * X).sum())
+    assert abs(cost - g["cost"]) <= 1e-12 * cost
+    r, c = X.sum(1), X.sum(0)
+    assert np.abs(r - a).sum() + np.abs(c - b).sum() <= 1e-10
+    pos = X > 0
+    H = -float((X[pos] * np.log(X[pos])).sum())
+    gap = cost - (a @ al + b @ be)
+    rhs = eps * H + al @ (r - a) + be @ (c - b)
+    assert abs(gap - rhs) <= 1e-9 * abs(cost)
