@@ -200,6 +200,36 @@ int pins_solve_device(pins_ctx* ctx, const pins_problem* prob, const pins_params
 int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
                             pins_result* res, void* stream);
 
+/* ---- Serving (continuous admission of requests onto concurrent batches) ----
+ * A server owns `workers` (1..4) solver threads on HIP device `device`, each
+ * with its own context and HIP stream.  A worker that becomes free takes every
+ * queued request it can -- in arrival order, of the same cost-kind family
+ * (grid, or dense/points) as the oldest one, at most max_batch of them, with
+ * the batch's workspace (pins_workspace_bytes) within hbm_budget bytes
+ * (0 = no limit; the oldest request is always admitted) -- and solves them as
+ * one batch with the parameters *p (p->streams is ignored).  Requests that
+ * arrive while other batches run are admitted as workers free up; batches of
+ * different workers overlap on the device.  Each result is bitwise the one
+ * its problem gets alone.  The server is used from any number of host threads. */
+typedef struct pins_server pins_server;
+int pins_server_create(int device, int workers, int max_batch, size_t hbm_budget, const pins_params* p,
+                       pins_server** out);
+/* Queue one problem given by HOST pointers (copied before the call returns);
+ * *ticket identifies it.  PINS_EINVAL for an invalid problem (shape, kind,
+ * marginals not positive, finite and summing to 1 within 1e-10) or a stopping
+ * server; the dense cost's finiteness is checked when its batch runs. */
+int pins_server_submit(pins_server* s, const pins_problem* prob, int64_t* ticket);
+/* Block until the ticket's solve has finished; fill *res (scalars; alpha and
+ * beta copied to res->alpha / res->beta when non-NULL, HOST arrays of m and n
+ * doubles; X is not returned) and *latency_ms (submit to completion) when
+ * non-NULL.  Returns the solve's status (or a negative error of its batch);
+ * the ticket is released. */
+int pins_server_wait(pins_server* s, int64_t ticket, pins_result* res, double* latency_ms);
+/* Message of the last failed batch (valid while no other batch fails). */
+const char* pins_server_last_error(const pins_server* s);
+/* Finish every queued request, stop the workers and free the server. */
+void pins_server_destroy(pins_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -103,6 +103,14 @@ def lib():
                                         vp]
         L.pins_solve_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
                                               ctypes.POINTER(Result), vp]
+        L.pins_server_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                         ctypes.POINTER(Params), ctypes.POINTER(vp)]
+        L.pins_server_submit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_int64)]
+        L.pins_server_wait.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_double)]
+        L.pins_server_last_error.argtypes = [vp]
+        L.pins_server_last_error.restype = ctypes.c_char_p
+        L.pins_server_destroy.argtypes = [vp]
+        L.pins_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -211,6 +219,65 @@ class Context:
     def solve_device(self, problem, prm: Params, out, stream=None):
         cnt_rc, res = self.solve_batch_device([problem], prm, [out], stream)
         return cnt_rc, res[0]
+
+
+class Server:
+    """pins_server: continuous admission of host-side requests onto concurrent
+    batched solves (workers threads, each with its own context and stream)."""
+
+    def __init__(self, prm: Params, device: int = 0, workers: int = 2, max_batch: int = 64, hbm_budget: int = 0):
+        h = ctypes.c_void_p()
+        self._prm = prm
+        rc = lib().pins_server_create(device, workers, max_batch, hbm_budget, ctypes.byref(prm), ctypes.byref(h))
+        if rc != PINS_OK:
+            raise PinsError(rc, "pins_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, kind, a, b, C=None, x=None, y=None, grid_s=0, cost_scale=0.0) -> int:
+        a = np.ascontiguousarray(a, np.float64)
+        b = np.ascontiguousarray(b, np.float64)
+        P = Problem(kind=kind, m=a.size, n=b.size, d=0, grid_s=grid_s, cost_scale=cost_scale, a=a.ctypes.data,
+                    b=b.ctypes.data)
+        keep = [a, b]
+        if C is not None:
+            C = np.ascontiguousarray(C, np.float64)
+            keep.append(C)
+            P.C = C.ctypes.data
+        if x is not None:
+            x = np.ascontiguousarray(x, np.float64)
+            y = np.ascontiguousarray(y, np.float64)
+            keep += [x, y]
+            P.x, P.y, P.d = x.ctypes.data, y.ctypes.data, x.shape[1]
+        t = ctypes.c_int64(0)
+        rc = lib().pins_server_submit(self.h, ctypes.byref(P), ctypes.byref(t))
+        if rc != PINS_OK:
+            raise PinsError(rc, "pins_server_submit failed")
+        self._keep[t.value] = (a.size, b.size)
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        m, n = self._keep.pop(ticket)
+        alpha, beta = np.empty(m), np.empty(n)
+        R = Result(alpha=alpha.ctypes.data, beta=beta.ctypes.data)
+        lat = ctypes.c_double(0.0)
+        rc = lib().pins_server_wait(self.h, ticket, ctypes.byref(R), ctypes.byref(lat))
+        if rc < 0:
+            raise PinsError(rc, lib().pins_server_last_error(self.h).decode())
+        out = R.scalars()
+        out.update(alpha=alpha, beta=beta, rc=rc, latency_ms=lat.value)
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pins_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _ptr(t):

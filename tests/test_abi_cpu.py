@@ -66,3 +66,16 @@ def test_create_without_gpu_reports_device_error():
     with pytest.raises(B.PinsError) as e:
         P.Context(0)
     assert e.value.code == B.PINS_EDEVICE
+
+
+def test_server_without_gpu_reports_device_error():
+    """On a host without a usable GPU the server refuses to start (no crash)."""
+    import ctypes
+    import paper_2502_03749_amd as P
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    prm = P.params(eta=0.1)
+    assert P.lib().pins_server_create(0, 2, 8, 0, ctypes.byref(prm), ctypes.byref(h)) == P._binding.PINS_EDEVICE
+    assert P.lib().pins_server_create(0, 0, 8, 0, ctypes.byref(prm), ctypes.byref(h)) == P._binding.PINS_EINVAL
