@@ -80,6 +80,10 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the materialised-cost Sinkhorn sweep measurement (16384 x 16384 FP64 cost)")
     ap.add_argument("--sweep-only", action="store_true", help="only run the materialised-cost sweep measurement")
+    ap.add_argument("--served", type=int, default=0, metavar="N",
+                    help="only run the served measurement: N Poisson-arriving grid requests (60%% 32x32, 30%% 64x64, "
+                         "10%% 128x128, eta = 1e-3, K = 10) through pins_server")
+    ap.add_argument("--rate", type=float, default=1.0, help="arrival rate of --served (requests per second)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
@@ -106,7 +110,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PINS hot path runs independent instances per GPU and "
-              "this build has no multi-GPU path (see the design notes for how it would shard); "
+              "this library has no multi-GPU path (see the design notes for how it would shard); "
               "run with --gpus 1.", file=sys.stderr, flush=True)
         sys.exit(2)
     if args.copy_calibration:
@@ -129,6 +133,9 @@ def main():
     outs = [dict(alpha=torch.empty(n, dtype=torch.float64, device=dev),
                  beta=torch.empty(n, dtype=torch.float64, device=dev)) for _ in pairs]
     prec = P.MIXED if args.precision == "mixed" else P.FP64
+    if args.served:
+        print(json.dumps(dict(served=served(P, W, args.served, args.rate))), flush=True)
+        return
     ctx = P.Context(0)
     if args.sweep_only:
         print(json.dumps(dict(sinkhorn_sweep=sweep_roofline(P, ctx, torch, np, dev))), flush=True)
@@ -285,6 +292,47 @@ def uneven_points(P, ctx, torch, np, dev, W, st, count=256, K=20):
         raise RuntimeError("uneven batch: a solve did not converge")
     return dict(instances=count, K=K, eta=1e-2, sum_mn=int(sum(p["m"] * p["n"] for p in probs)),
                 solves_per_s=count / dt, ms=1e3 * dt)
+
+
+def served(P, W, count, rate, K=10, workers=2, max_batch=32):
+    """Poisson arrivals through pins_server: a submitter thread sleeps until each
+    request's arrival time and submits it; latency is submit -> completion as the
+    server measures it; throughput = requests / (last completion - first arrival)."""
+    import threading
+
+    import numpy as np
+
+    reqs = W.serve_requests(count, rate)
+    srv = P.Server(P.params(eta=1e-3, max_outer=K, precision=P.MIXED), workers=workers, max_batch=max_batch)
+    tickets = [None] * count
+    t0 = time.perf_counter()
+
+    def submitter():
+        for q, r in enumerate(reqs):
+            delay = r["t"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[q] = srv.submit(P.COST_GRID, r["a"], r["b"], grid_s=r["s"])
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    out = [srv.wait(t) for t in tickets]
+    t_end = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([o["latency_ms"] for o in out])
+    by = {}
+    for s_ in (32, 64, 128):
+        sel = [o["latency_ms"] for o, r in zip(out, reqs) if r["s"] == s_]
+        if sel:
+            by["%dx%d" % (s_, s_)] = dict(count=len(sel), p50_ms=float(np.percentile(sel, 50)),
+                                          p99_ms=float(np.percentile(sel, 99)))
+    return dict(workload="%d requests, Poisson rate %.2f/s, 60%% 32x32 / 30%% 64x64 / 10%% 128x128 grids, "
+                         "Gaussian-mixture or white-noise histograms, eta = 1e-3, K = %d, mixed precision" %
+                         (count, rate, K),
+                workers=workers, max_batch=max_batch, solves_per_s=count / (t_end - reqs[0]["t"]),
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)), by_size=by,
+                statuses=sorted(set(int(o["rc"]) for o in out)), max_resid=float(max(o["resid"] for o in out)))
 
 
 def sweep_roofline(P, ctx, torch, np, dev, side=16384, sweeps=7):

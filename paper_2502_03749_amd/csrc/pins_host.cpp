@@ -520,7 +520,20 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
             run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
             run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L); });
             run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
-            run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
+            if (!wide_cg(L)) {
+                run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
+            } else {
+                // wide CG: iterations in chunks between readbacks of cg_on
+                run(ctx, st, PINS_K_PCG, [&] { launch_wcg_begin(L); });
+                for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
+                    const Ctrl* hc = readback(ctx, st, d_ctrl, count);
+                    bool on = false;
+                    for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
+                    if (!on) break;
+                    for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG, [&] { launch_wcg_iter(L); });
+                }
+                run(ctx, st, PINS_K_PCG, [&] { launch_wcg_end(L); });
+            }
             run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
             // one readback per Newton step: who is still iterating, who needs more
             // Armijo trials, who will take the Sinkhorn fallback

@@ -1003,7 +1003,8 @@ __device__ __forceinline__ void load_v4(const double* p, int q, double (&w)[4]) 
 
 template <int G, class IX, class VT>
 __device__ __forceinline__ void spmv_bin(const DevInst& I, int m, const int* bins, int lo, int hi, const int* rp,
-                                         const int* cp, const double* __restrict__ pv, double* __restrict__ out) {
+                                         const int* cp, const double* __restrict__ pv, double* __restrict__ out,
+                                         const double* __restrict__ rdiv = nullptr) {
     constexpr int NG = 1024 / G;
     const int g = threadIdx.x / G, lg = threadIdx.x % G;
     for (int t = lo + g; t < hi; t += NG) {
@@ -1033,7 +1034,7 @@ __device__ __forceinline__ void spmv_bin(const DevInst& I, int m, const int* bin
             s += ((w[0] * pv[o + x[0]] + w[1] * pv[o + x[1]]) + (w[2] * pv[o + x[2]] + w[3] * pv[o + x[3]]));
         }
         s = group_sum<G>(s);
-        if (lg == 0) out[k] = s;
+        if (lg == 0) out[k] = rdiv ? s / rdiv[k] : s;
     }
 }
 
@@ -1308,6 +1309,181 @@ __global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts,
     dab = block_sum<1024>(dab, sh);
     fa = block_sum<1024>(fa, sh);
     if (threadIdx.x == 0) ls_setup(ctrl[b], it, gd, dab, fa, kp);
+}
+
+// ---------------------------------------------------------------------------
+// Wide CG for instances with m + n > WCG_MAX_N: the same Schur-complement CG,
+// with each product spread over many blocks (WCG_ROWS rows of one half of M
+// per block, over the binned row list) and the vector work in one block per
+// instance.  Kernel boundaries order the memory (no device fences); the host
+// runs iterations in chunks between readbacks, and an instance that has
+// stopped (cg_on = 0) makes every later launch return at once.
+// Vectors (global): x = I.d, res = cgw[0..m), bv = cgw[N..2N) (rhs),
+// p = cgw[2N..3N) (direction on the rows, D_c^-1 S^T p on the columns),
+// q = cgw[3N..4N).
+// ---------------------------------------------------------------------------
+// One half of M's product for the blocks of rows [lo, hi) of the part's list.
+template <class IX, class VT>
+__device__ __forceinline__ void spmv_range(const DevInst& I, int m, const int* bins, const int* bo, int lo, int hi,
+                                           const double* __restrict__ pv, double* __restrict__ out,
+                                           const double* __restrict__ rdiv) {
+#define WB_(G, g)                                                                                              \
+    {                                                                                                          \
+        const int a_ = max(lo, bo[g]), b_ = min(hi, bo[g + 1]);                                               \
+        if (a_ < b_) spmv_bin<G, IX, VT>(I, m, bins, a_, b_, I.rowptr, I.colptr, pv, out, rdiv);              \
+    }
+    WB_(1, 0) WB_(2, 1) WB_(4, 2) WB_(8, 3) WB_(16, 4) WB_(32, 5)
+#undef WB_
+}
+
+// rhs, x = 0, D_c^-1 b_2 into p's column part; ||rhs||
+__global__ __launch_bounds__(1024) void k_wcg_begin(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n, N = m + n;
+    double* __restrict__ bv = I.cgw + N;
+    double* __restrict__ p = I.cgw + 2 * N;
+    __shared__ double sh[32];
+    double bb = 0.0;
+    for (int k = threadIdx.x; k < N; k += 1024) {
+        const double tg = (k < m) ? I.a[k] : I.b[k - m];
+        const double rh = kp.eta * (tg - I.rc[k]);
+        bv[k] = rh;
+        I.d[k] = 0.0;
+        if (k >= m) p[k] = rh / I.rc[k];
+        bb += rh * rh;
+    }
+    bb = block_sum<1024>(bb, sh);
+    if (threadIdx.x == 0) {
+        ctrl[b].cg_bnorm = sqrt(bb);
+        ctrl[b].cg_it = 0;
+        ctrl[b].cg_on = 1;
+    }
+}
+
+// rows: q[i] = (S p_cols)_i; columns: p[m + j] = (S^T p_rows)_j / c_j, or
+// q[m + j] = (S^T x)_j when `final` (after the iterations)
+template <class IX, class VT>
+__global__ __launch_bounds__(1024) void k_wcg_half(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+                                                   int cols, int final) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON || (!final && !ctrl[b].cg_on)) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = m + I.n;
+    const int* bo = ctrl[b].binoff + (cols ? NBIN : 0);
+    const int lo = bo[0] + blockIdx.x * WCG_ROWS;
+    const int hi = min(bo[NBIN], lo + WCG_ROWS);
+    if (lo >= hi) return;
+    double* __restrict__ p = I.cgw + 2 * N;
+    double* __restrict__ q = I.cgw + 3 * N;
+    if (!cols)
+        spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, p, q, nullptr);
+    else if (final)
+        spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, I.d, q, nullptr);
+    else
+        spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, p, p, I.rc);
+}
+
+// after S D_c^-1 b_2: residual, preconditioned residual, first direction
+__global__ __launch_bounds__(1024) void k_wcg_start(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = m + I.n;
+    double* __restrict__ res = I.cgw;
+    const double* __restrict__ bv = I.cgw + N;
+    double* __restrict__ p = I.cgw + 2 * N;
+    const double* __restrict__ q = I.cgw + 3 * N;
+    __shared__ double sh[32];
+    double rr = 0.0, rz = 0.0;
+    for (int i = threadIdx.x; i < m; i += 1024) {
+        const double r = bv[i] - q[i];
+        res[i] = r;
+        const double z = r / I.rc[i];
+        p[i] = z;
+        rr += r * r;
+        rz += r * z;
+    }
+    block_sum2<1024>(rr, rz, sh);
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        S.cg_rz = rz;
+        if (!(S.cg_bnorm > 0.0) || sqrt(rr) <= kp.cg_rtol * S.cg_bnorm || kp.cg_max <= 0) S.cg_on = 0;
+    }
+}
+
+// one iteration's vector work: q = D_r p - S D_c^-1 S^T p, step, residual, stop test, next direction
+__global__ __launch_bounds__(1024) void k_wcg_step(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON || !ctrl[b].cg_on) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = m + I.n;
+    double* __restrict__ res = I.cgw;
+    double* __restrict__ p = I.cgw + 2 * N;
+    double* __restrict__ q = I.cgw + 3 * N;
+    double* __restrict__ x = I.d;
+    const double* __restrict__ dg = I.rc;
+    __shared__ double sh[32];
+    __shared__ int s_go;
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < m; i += 1024) {
+        const double v = dg[i] * p[i] - q[i];
+        q[i] = v;
+        pq += p[i] * v;
+    }
+    pq = block_sum<1024>(pq, sh);
+    if (!(pq > 0.0)) {
+        if (threadIdx.x == 0) ctrl[b].cg_on = 0;
+        return;
+    }
+    const double al = ctrl[b].cg_rz / pq;
+    double rr = 0.0, rz2 = 0.0;
+    for (int i = threadIdx.x; i < m; i += 1024) {
+        x[i] += al * p[i];
+        const double r = res[i] - al * q[i];
+        res[i] = r;
+        rr += r * r;
+        rz2 += r * (r / dg[i]);
+    }
+    block_sum2<1024>(rr, rz2, sh);
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        S.cg_it += 1;
+        const int go = !(sqrt(rr) <= kp.cg_rtol * S.cg_bnorm) && S.cg_it < kp.cg_max;
+        s_go = go;
+        if (!go) S.cg_on = 0;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const double be = rz2 / ctrl[b].cg_rz;
+    __syncthreads();  // every thread has read cg_rz before it changes
+    if (threadIdx.x == 0) ctrl[b].cg_rz = rz2;
+    for (int i = threadIdx.x; i < m; i += 1024) p[i] = res[i] / dg[i] + be * p[i];
+}
+
+// y = D_c^-1 (b_2 - S^T x) and the line-search inputs
+__global__ __launch_bounds__(1024) void k_wcg_finish(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+    const int b = blockIdx.x;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = m + I.n;
+    const double* __restrict__ bv = I.cgw + N;
+    const double* __restrict__ q = I.cgw + 3 * N;
+    __shared__ double sh[32];
+    double gd = 0.0, dab = 0.0, fa = 0.0;
+    for (int k = threadIdx.x; k < N; k += 1024) {
+        if (k >= m) I.d[k] = (bv[k] - q[k]) / I.rc[k];
+        const double x = I.d[k];
+        const double tg = (k < m) ? I.a[k] : I.b[k - m];
+        gd += (tg - I.rc[k]) * x;
+        dab += tg * x;
+        fa += fabs(tg * x);
+    }
+    gd = block_sum<1024>(gd, sh);
+    dab = block_sum<1024>(dab, sh);
+    fa = block_sum<1024>(fa, sh);
+    if (threadIdx.x == 0) ls_setup(ctrl[b], ctrl[b].cg_it, gd, dab, fa, kp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1960,6 +2136,41 @@ static void launch_pcg_t(const LaunchCtx& L) {
     else
         hipLaunchKernelGGL((k_pcg<IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
 }
+
+template <class IX, class VT>
+static void launch_wcg_half_t(const LaunchCtx& L, int cols, int final) {
+    const int rows = cols ? L.max_n : L.max_m;
+    const dim3 g((rows + WCG_ROWS - 1) / WCG_ROWS, L.count);
+    hipLaunchKernelGGL((k_wcg_half<IX, VT>), g, dim3(1024), 0, L.stream, L.insts, L.ctrl, cols, final);
+}
+
+static void launch_wcg_half(const LaunchCtx& L, int cols, int final) {
+    switch (L.sp_fmt) {
+        case 0: launch_wcg_half_t<int, double>(L, cols, final); break;
+        case 1: launch_wcg_half_t<unsigned short, double>(L, cols, final); break;
+        case 2: launch_wcg_half_t<int, float>(L, cols, final); break;
+        default: launch_wcg_half_t<unsigned short, float>(L, cols, final); break;
+    }
+}
+
+void launch_wcg_begin(const LaunchCtx& L) {
+    hipLaunchKernelGGL(k_wcg_begin, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+    launch_wcg_half(L, 0, 0);
+    hipLaunchKernelGGL(k_wcg_start, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+}
+
+void launch_wcg_iter(const LaunchCtx& L) {
+    launch_wcg_half(L, 1, 0);
+    launch_wcg_half(L, 0, 0);
+    hipLaunchKernelGGL(k_wcg_step, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+}
+
+void launch_wcg_end(const LaunchCtx& L) {
+    launch_wcg_half(L, 1, 1);
+    hipLaunchKernelGGL(k_wcg_finish, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+}
+
+bool wide_cg(const LaunchCtx& L) { return L.max_mn > WCG_MAX_N; }
 
 void launch_pcg(const LaunchCtx& L) {
     switch (L.sp_fmt) {

@@ -27,6 +27,13 @@ void launch_col_merge(const LaunchCtx& L, int mask);
 void launch_grad(const LaunchCtx& L, int src);
 void launch_grad_merge(const LaunchCtx& L);
 void launch_sparsify(const LaunchCtx& L, int src);
+// wide CG (batches whose largest m+n exceeds WCG_MAX_N): begin, one iteration
+// (no-op for instances that stopped), end; the host repeats launch_wcg_iter
+// until no instance has Ctrl::cg_on set
+bool wide_cg(const LaunchCtx& L);
+void launch_wcg_begin(const LaunchCtx& L);
+void launch_wcg_iter(const LaunchCtx& L);
+void launch_wcg_end(const LaunchCtx& L);
 void launch_pcg(const LaunchCtx& L);
 void launch_ls(const LaunchCtx& L, int src, bool first);
 void launch_update(const LaunchCtx& L);
