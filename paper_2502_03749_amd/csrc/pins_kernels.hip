@@ -470,23 +470,37 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
 // runs the warm-up control (row error of the sweep, exit test).
 __global__ __launch_bounds__(256) void k_col_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
                                                    int mask) {
+    // 32 columns per block, 8 lanes per column: lane s merges the row blocks
+    // s, s + 8, ... (two passes: maximum, then rescaled sum), then the 8
+    // (max, sum) pairs of a column are combined in lane order
     const int b = blockIdx.y;
     if (!phase_in(ctrl, b, mask)) return;
     const DevInst& I = insts[b];
     const int n = I.n;
-    const int nb = (n + 255) / 256;
-    if ((int)blockIdx.x >= nb) return;
-    const int j = blockIdx.x * 256 + threadIdx.x;
+    if ((int)blockIdx.x * 32 >= n) return;
+    const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int j = blockIdx.x * 32 + c;
+    __shared__ double smx[8][32], ssm[8][32];
+    double mx = -INFINITY, sm = 0.0;
     if (j < n) {
         const double2* __restrict__ P = reinterpret_cast<const double2*>(I.part);
-        double mx = -INFINITY;
-        for (int rb = 0; rb < I.nrb; ++rb) mx = fmax(mx, P[(long)rb * n + j].x);
-        double s = 0.0;
-        for (int rb = 0; rb < I.nrb; ++rb) {
-            const double2 q = P[(long)rb * n + j];
-            if (q.x != -INFINITY) s += q.y * exp(q.x - mx);
-        }
-        I.G[j] = kp.eta * (I.logb[j] - (mx + log(s)));
+        for (int rb = sl; rb < I.nrb; rb += 8) mx = fmax(mx, P[(long)rb * n + j].x);
+        if (mx != -INFINITY)
+            for (int rb = sl; rb < I.nrb; rb += 8) {
+                const double2 q = P[(long)rb * n + j];
+                if (q.x != -INFINITY) sm += q.y * exp(q.x - mx);
+            }
+    }
+    smx[sl][c] = mx;
+    ssm[sl][c] = sm;
+    __syncthreads();
+    if (sl == 0 && j < n) {
+        double M = -INFINITY;
+        for (int k = 0; k < 8; ++k) M = fmax(M, smx[k][c]);
+        double S = 0.0;
+        for (int k = 0; k < 8; ++k)
+            if (smx[k][c] != -INFINITY) S += ssm[k][c] * exp(smx[k][c] - M);
+        I.G[j] = kp.eta * (I.logb[j] - (M + log(S)));
     }
 }
 
@@ -763,34 +777,46 @@ __global__ __launch_bounds__(256) void k_count(const DevInst* __restrict__ insts
     }
 }
 
+// Per row of M (CSR row, then CSC column): the kept count over the column
+// (row) blocks, and those per-block counts turned into exclusive prefix sums in
+// place (the fill reads them as the entry index of its first kept entry).
+// The totals go to rowbin, which k_scan reads before it writes the row list.
+__global__ __launch_bounds__(256) void k_scan_totals(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= m + n) return;
+    int c = 0;
+    if (k < m) {
+        int* __restrict__ cr = I.cntr + (long)k * I.ncb;
+        for (int q = 0; q < I.ncb; ++q) {
+            const int v = cr[q];
+            cr[q] = c;
+            c += v;
+        }
+    } else {
+        int* __restrict__ cc = I.cntc + (k - m);
+        for (int q = 0; q < I.nrb; ++q) {
+            const int v = cc[(long)q * n];
+            cc[(long)q * n] = c;
+            c += v;
+        }
+    }
+    I.rowbin[k] = c;
+}
+
 __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
-    const int m = I.m, n = I.n, ncb = I.ncb, nrb = I.nrb, N = m + n;
+    const int m = I.m, n = I.n, N = m + n;
     __shared__ int ish[16];
     __shared__ long lsh[16];
-    int* __restrict__ cr = I.cntr;
-    int* __restrict__ cc = I.cntc;
-    // kept entries of row k of M (k < m: row of S; else column k - m); the
-    // per-block counts become exclusive prefix sums in place, which the fill
-    // reads as the entry index of its first kept entry (called once per k)
-    auto kept = [&](int k) {
-        int c = 0;
-        if (k < m)
-            for (int q = 0; q < ncb; ++q) {
-                const int v = cr[(long)k * ncb + q];
-                cr[(long)k * ncb + q] = c;
-                c += v;
-            }
-        else
-            for (int q = 0; q < nrb; ++q) {
-                const int v = cc[(long)q * n + (k - m)];
-                cc[(long)q * n + (k - m)] = c;
-                c += v;
-            }
-        return c;
-    };
+    // kept entries of row k of M (k < m: row of S; else column k - m), from k_scan_totals
+    const int* __restrict__ tot = I.rowbin;
+    auto kept = [&](int k) { return tot[k]; };
     long real = 0;
     block_scan_excl<1024>(
         [&](int i) {
@@ -2082,7 +2108,7 @@ void launch_col_lse(const LaunchCtx& L, int src, bool f32, int mask) {
 }
 
 void launch_col_merge(const LaunchCtx& L, int mask) {
-    hipLaunchKernelGGL(k_col_merge, g2((L.max_n + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
+    hipLaunchKernelGGL(k_col_merge, g2((L.max_n + 31) / 32, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
                        L.kp, mask);
     hipLaunchKernelGGL(k_col_decide, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, mask);
 }
@@ -2112,6 +2138,7 @@ void launch_sparsify(const LaunchCtx& L, int src) {
 #define K_(S) hipLaunchKernelGGL((k_count<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
     PINS_SRC_DISPATCH(src, K_);
 #undef K_
+    hipLaunchKernelGGL(k_scan_totals, g2((L.max_mn + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl);
     hipLaunchKernelGGL(k_scan, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl);
     switch (L.sp_fmt) {
         case 0: launch_fill_t<int, double>(L, src, g); break;
