@@ -24,7 +24,7 @@ constexpr int TILE_C = 256;  // columns per tile (one per thread)
 constexpr int TILE_RMAX = 16;  // maximum rows per tile
 constexpr int NBIN = 6;        // CG row bins: <= 1, 2, 4, 8, 16 and more quads
 constexpr int WCG_ROWS = 128;  // wide CG: rows of one half of M per block
-constexpr int WCG_MAX_N = 8192;  // instances with m+n above this take the wide CG
+constexpr int WCG_MAX_N = 4096;  // instances with m+n above this take the wide CG
 
 enum Phase : int { PH_DONE = 0, PH_WARM = 1, PH_NEWTON = 2, PH_FALLBACK = 3 };
 enum LsState : int { LS_PENDING = 0, LS_ACCEPTED = 1, LS_FAILED = 2 };
