@@ -20,7 +20,13 @@ The JSON line also carries:
                   workload (rank 0, one thread);
   accuracy     -- relative cost difference of the sampled instance against
                   the oracle at the same K (bar: 1e-6);
-  variants     -- plain single-instance throughput and the other precision.
+  variants     -- plain single-instance throughput, the other precision, and
+                  an uneven batch of 256 point-cloud instances;
+  sinkhorn_sweep -- HBM rate of the Sinkhorn half-sweeps on a materialised
+                  16384 x 16384 FP64 cost;
+  served       -- 120 Poisson-arriving grid requests (60% 32x32, 30% 64x64,
+                  10% 128x128, eta = 1e-3, K = 10) through pins_server:
+                  solves/s and p50 / p99 latency.
 """
 import argparse
 import hashlib
@@ -83,7 +89,8 @@ def parse():
     ap.add_argument("--served", type=int, default=0, metavar="N",
                     help="only run the served measurement: N Poisson-arriving grid requests (60%% 32x32, 30%% 64x64, "
                          "10%% 128x128, eta = 1e-3, K = 10) through pins_server")
-    ap.add_argument("--rate", type=float, default=1.0, help="arrival rate of --served (requests per second)")
+    ap.add_argument("--rate", type=float, default=6.0, help="arrival rate of --served (requests per second)")
+    ap.add_argument("--no-served", action="store_true", help="skip the default served run (120 requests at 6/s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
@@ -252,6 +259,8 @@ def main():
 
     if not args.no_sweep:
         line["sinkhorn_sweep"] = sweep_roofline(P, ctx, torch, np, dev)
+    if not args.no_served:
+        line["served"] = served(P, W, 120, args.rate)
 
     if not args.no_cpu_baseline:
         import oracle
