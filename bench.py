@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-launch HIP events")
-    ap.add_argument("--lanes", type=int, default=2,
+    ap.add_argument("--lanes", type=int, default=3,
                     help="concurrent lanes of the batched call (params.streams); results do not depend on it")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the materialised-cost Sinkhorn sweep measurement (16384 x 16384 FP64 cost)")
@@ -303,7 +303,7 @@ def uneven_points(P, ctx, torch, np, dev, W, st, count=256, K=20):
                 solves_per_s=count / dt, ms=1e3 * dt)
 
 
-def served(P, W, count, rate, K=10, workers=2, max_batch=32):
+def served(P, W, count, rate, K=10, workers=3, max_batch=32):
     """Poisson arrivals through pins_server: a submitter thread sleeps until each
     request's arrival time and submits it; latency is submit -> completion as the
     server measures it; throughput = requests / (last completion - first arrival)."""
