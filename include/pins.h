@@ -98,6 +98,10 @@ typedef struct {
                              0 or 1 = one lane on the caller's stream; results do not depend on it */
     int32_t profile_mask; /* with profile: bit k set = time the launches of kernel class k
                              (PINS_K_*); 0 = every class.  Fewer timed classes, less overhead */
+    int32_t hvp;          /* Hessian-vector products of the Newton CG: 0 = the sparsified
+                             Hessian (Sparsify, CSR/CSC products; the default), 1 = matrix-free
+                             products with the full Hessian, X~ recomputed tile by tile from
+                             the potentials and the streamed cost (no Sparsify) */
 } pins_params;
 
 /* One problem instance.  For pins_solve the pointers are host pointers, for

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
                 ("ls_beta", ctypes.c_double), ("ls_c1", ctypes.c_double), ("ls_max", ctypes.c_int32),
                 ("rho_levels", ctypes.c_int32), ("rho", ctypes.c_double), ("budget", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("shift_mode", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("profile_mask", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("profile_mask", ctypes.c_int32), ("hvp", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):

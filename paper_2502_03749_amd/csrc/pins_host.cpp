@@ -197,6 +197,7 @@ void check_params(const pins_params& p) {
     if (p.precision != PINS_FP64 && p.precision != PINS_MIXED) fail(PINS_EINVAL, "unknown precision");
     if (p.shift_mode != PINS_SHIFT_IMPLICIT && p.shift_mode != PINS_SHIFT_MATERIALIZED)
         fail(PINS_EINVAL, "unknown shift_mode");
+    if (p.hvp != 0 && p.hvp != 1) fail(PINS_EINVAL, "hvp must be 0 (sparsified) or 1 (matrix-free)");
 }
 
 void check_problem_shape(const pins_problem& P) {
@@ -493,6 +494,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     }
 
     const bool f32 = p.precision == PINS_MIXED;
+    const bool mf = p.hvp == 1;  // matrix-free Hessian products (no Sparsify)
     const int K = p.max_outer;
     const int M_WARM = 1 << PH_WARM, M_FB = 1 << PH_FALLBACK;
     for (int k = 0; k < K; ++k) {
@@ -519,20 +521,21 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         for (;;) {
             run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
             run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L); });
-            run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
-            if (!wide_cg(L)) {
+            if (!mf) run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
+            if (!mf && !wide_cg(L)) {
                 run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
             } else {
-                // wide CG: iterations in chunks between readbacks of cg_on
-                run(ctx, st, PINS_K_PCG, [&] { launch_wcg_begin(L); });
+                // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
+                const int hsrc = mf ? src : -1;
+                run(ctx, st, PINS_K_PCG, [&] { launch_wcg_begin(L, hsrc); });
                 for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
                     const Ctrl* hc = readback(ctx, st, d_ctrl, count);
                     bool on = false;
                     for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
                     if (!on) break;
-                    for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG, [&] { launch_wcg_iter(L); });
+                    for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG, [&] { launch_wcg_iter(L, hsrc); });
                 }
-                run(ctx, st, PINS_K_PCG, [&] { launch_wcg_end(L); });
+                run(ctx, st, PINS_K_PCG, [&] { launch_wcg_end(L, hsrc); });
             }
             run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
             // one readback per Newton step: who is still iterating, who needs more
@@ -765,6 +768,7 @@ void pins_params_default(pins_params* p) {
     p->profile = 0;
     p->streams = 0;
     p->profile_mask = 0;
+    p->hvp = 0;
 }
 
 int pins_create(int device, pins_ctx** out) {

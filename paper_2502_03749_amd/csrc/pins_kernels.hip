@@ -1363,9 +1363,11 @@ __device__ __forceinline__ void spmv_range(const DevInst& I, int m, const int* b
 }
 
 // rhs, x = 0, D_c^-1 b_2 into p's column part; ||rhs||
-__global__ __launch_bounds__(1024) void k_wcg_begin(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+__global__ __launch_bounds__(1024) void k_wcg_begin(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                    int dense) {
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
+    if (dense && threadIdx.x == 0) ctrl[b].nnz = insts[b].m * insts[b].n;  // a product reads every entry
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
     double* __restrict__ bv = I.cgw + N;
@@ -1486,6 +1488,85 @@ __global__ __launch_bounds__(1024) void k_wcg_step(const DevInst* __restrict__ i
     __syncthreads();  // every thread has read cg_rz before it changes
     if (threadIdx.x == 0) ctrl[b].cg_rz = rz2;
     for (int i = threadIdx.x; i < m; i += 1024) p[i] = res[i] / dg[i] + be * p[i];
+}
+
+// Matrix-free products with the full Hessian (params.hvp = 1): the coupling
+// block is X~ itself, recomputed tile by tile from the potentials and the
+// streamed cost as in the Newton pass.  cols = 1: column partials
+// part[rb][j] = sum_i X~_ij u_i of the tile (u = the direction on the rows, or
+// x when `final`); cols = 0: row partials part2[cb][i] = sum_j X~_ij w_j
+// (w = D_c^-1 X~^T p on the columns).  Merged in fixed order by k_mf_merge.
+template <class Src>
+__global__ __launch_bounds__(256) void k_mf_tile(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                 int cols, int final) {
+    const BlkRef br = blk_ref(kp.toff, kp.count);
+    const int b = br.b, tl = br.l;
+    if (ctrl[b].phase != PH_NEWTON || (!final && !ctrl[b].cg_on)) return;
+    const DevInst& I = insts[b];
+    const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
+    const int m = I.m, n = I.n, N = m + n;
+    const int i0 = rb * I.R, rows = min(I.R, m - i0);
+    const double* __restrict__ p = I.cgw + 2 * N;
+    const double* __restrict__ u = final ? I.d : p;
+    __shared__ double sF[TILE_RMAX], su[TILE_RMAX], wsum[TILE_RMAX][4];
+    __shared__ double sT[64];
+    texp_table(sT);
+    if ((int)threadIdx.x < rows) {
+        sF[threadIdx.x] = I.F[i0 + threadIdx.x];
+        su[threadIdx.x] = u[i0 + threadIdx.x];
+    }
+    __syncthreads();
+    const int j = cb * TILE_C + threadIdx.x;
+    const bool valid = j < n;
+    const double kap = ctrl[b].kappa, ie = kp.inv_eta;
+    const Src src(I);
+    const double Gj = valid ? ldg(I.G + j) : 0.0;
+    if (cols) {
+        double acc = 0.0;
+        if (valid)
+            for (int r = 0; r < rows; ++r) acc += texp(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), sT) * su[r];
+        if (valid) I.part[(long)rb * n + j] = acc;
+    } else {
+        const double wj = valid ? p[m + j] : 0.0;
+        for (int r0 = 0; r0 < rows; r0 += 4) {
+            double v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int r = r0 + t;
+                v[t] = (valid && r < rows) ? texp(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), sT) * wj : 0.0;
+            }
+            wave_rows4(v, r0, wsum);
+        }
+        __syncthreads();
+        tile_rows_store(wsum, rows, i0, cb, m, I.part2);
+    }
+}
+
+// cols = 1: t_j = sum over row blocks -> p[m + j] = t_j / c_j, or q[m + j] = t_j
+// when `final`; cols = 0: q_i = sum over column blocks.
+__global__ __launch_bounds__(256) void k_mf_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, int cols,
+                                                  int final) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON || (!final && !ctrl[b].cg_on)) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, n = I.n, N = m + n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    double* __restrict__ p = I.cgw + 2 * N;
+    double* __restrict__ q = I.cgw + 3 * N;
+    if (cols) {
+        if (k >= n) return;
+        double t = 0.0;
+        for (int rb = 0; rb < I.nrb; ++rb) t += I.part[(long)rb * n + k];
+        if (final)
+            q[m + k] = t;
+        else
+            p[m + k] = t / I.rc[m + k];
+    } else {
+        if (k >= m) return;
+        double t = 0.0;
+        for (int cb = 0; cb < I.ncb; ++cb) t += I.part2[(long)cb * m + k];
+        q[k] = t;
+    }
 }
 
 // y = D_c^-1 (b_2 - S^T x) and the line-search inputs
@@ -2180,20 +2261,35 @@ static void launch_wcg_half(const LaunchCtx& L, int cols, int final) {
     }
 }
 
-void launch_wcg_begin(const LaunchCtx& L) {
-    hipLaunchKernelGGL(k_wcg_begin, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
-    launch_wcg_half(L, 0, 0);
+// one half of the product: the sparsified Hessian (src < 0) or matrix-free
+// with the full Hessian over cost source src
+static void launch_half(const LaunchCtx& L, int src, int cols, int final) {
+    if (src < 0) {
+        launch_wcg_half(L, cols, final);
+        return;
+    }
+    const dim3 g(L.total_tiles);
+#define K_(S) hipLaunchKernelGGL((k_mf_tile<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, cols, final)
+    PINS_SRC_DISPATCH(src, K_);
+#undef K_
+    hipLaunchKernelGGL(k_mf_merge, g2(((cols ? L.max_n : L.max_m) + 255) / 256, L.count), dim3(256), 0, L.stream,
+                       L.insts, L.ctrl, cols, final);
+}
+
+void launch_wcg_begin(const LaunchCtx& L, int src) {
+    hipLaunchKernelGGL(k_wcg_begin, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, src >= 0 ? 1 : 0);
+    launch_half(L, src, 0, 0);
     hipLaunchKernelGGL(k_wcg_start, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
-void launch_wcg_iter(const LaunchCtx& L) {
-    launch_wcg_half(L, 1, 0);
-    launch_wcg_half(L, 0, 0);
+void launch_wcg_iter(const LaunchCtx& L, int src) {
+    launch_half(L, src, 1, 0);
+    launch_half(L, src, 0, 0);
     hipLaunchKernelGGL(k_wcg_step, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
-void launch_wcg_end(const LaunchCtx& L) {
-    launch_wcg_half(L, 1, 1);
+void launch_wcg_end(const LaunchCtx& L, int src) {
+    launch_half(L, src, 1, 1);
     hipLaunchKernelGGL(k_wcg_finish, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 

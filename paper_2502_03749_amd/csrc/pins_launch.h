@@ -27,13 +27,15 @@ void launch_col_merge(const LaunchCtx& L, int mask);
 void launch_grad(const LaunchCtx& L, int src);
 void launch_grad_merge(const LaunchCtx& L);
 void launch_sparsify(const LaunchCtx& L, int src);
-// wide CG (batches whose largest m+n exceeds WCG_MAX_N): begin, one iteration
-// (no-op for instances that stopped), end; the host repeats launch_wcg_iter
-// until no instance has Ctrl::cg_on set
+// wide CG (batches whose largest m+n exceeds WCG_MAX_N, or matrix-free
+// products): begin, one iteration (no-op for instances that stopped), end; the
+// host repeats launch_wcg_iter until no instance has Ctrl::cg_on set.  src < 0:
+// products with the sparsified Hessian; src >= 0: matrix-free with the full
+// Hessian over that cost source
 bool wide_cg(const LaunchCtx& L);
-void launch_wcg_begin(const LaunchCtx& L);
-void launch_wcg_iter(const LaunchCtx& L);
-void launch_wcg_end(const LaunchCtx& L);
+void launch_wcg_begin(const LaunchCtx& L, int src);
+void launch_wcg_iter(const LaunchCtx& L, int src);
+void launch_wcg_end(const LaunchCtx& L, int src);
 void launch_pcg(const LaunchCtx& L);
 void launch_ls(const LaunchCtx& L, int src, bool first);
 void launch_update(const LaunchCtx& L);

@@ -72,3 +72,32 @@ def test_variants_reach_the_same_finite_K_plan(ctx):
     assert np.abs(sk["X"] - pn["X"]).sum() <= 1e-9
     assert np.abs(se["X"] - pn["X"]).sum() <= 1e-9
     assert abs(sk["cost"] - pn["cost"]) / pn["cost"] <= 1e-9
+
+
+@pytest.mark.parametrize("kind", ["dense", "grid", "points"])
+def test_matrix_free_hessian_products_parity(ctx, kind):
+    """params.hvp = 1: the Newton CG multiplies by the full Hessian, X~ recomputed
+    tile by tile (the paper's streaming variant; no Sparsify).  Same converged
+    output as the oracle (whose CG uses the sparsified Hessian)."""
+    print("case matrix-free %s" % kind, flush=True)
+    import workloads as W
+
+    if kind == "dense":
+        C, a, b = _rand(45, 38, 2031)
+        prob = dict(kind=P.COST_DENSE, C=C, a=a, b=b)
+        eta, K = 0.05, 8
+    elif kind == "grid":
+        pr = W.blob_pair(11, s=12)
+        C, a, b = oracle.cost_grid(12), pr["a"], pr["b"]
+        prob = dict(kind=P.COST_GRID, grid_s=12, a=a, b=b)
+        eta, K = 0.1, 10
+    else:
+        inst = W.points_instance(3, m=60, n=50, d=8)
+        C, a, b = oracle.cost_points(inst["x"], inst["y"]), inst["a"], inst["b"]
+        prob = dict(kind=P.COST_POINTS, x=inst["x"], y=inst["y"], a=a, b=b)
+        eta, K = 0.02, 6
+    g = gpu_solve(ctx, prob, P.params(eta=eta, max_outer=K, hvp=1))
+    g["_C"] = C
+    o = oracle.pins(C, a, b, eta=eta, K=K)
+    check_parity(g, o, a, b)
+    assert g["newton_iters"] > 0 and g["cg_iters"] > 0
