@@ -236,7 +236,7 @@ def main():
     if not args.no_variants:
         variants = {}
         other = P.FP64 if prec == P.MIXED else P.MIXED
-        prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other)
+        prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other, streams=args.lanes)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         step(prm2)
@@ -255,6 +255,13 @@ def main():
         variants["plain_single_instance_solves_per_s"] = nplain / sum(lat)
         variants["plain_single_instance_ms"] = [round(1e3 * v, 2) for v in lat]
         variants["batched_uneven_points"] = uneven_points(P, ctx, torch, np, dev, W, st)
+        # the paper's streaming variant: matrix-free products with the full Hessian
+        prm3 = P.params(eta=args.eta, max_outer=args.K, precision=prec, streams=args.lanes, hvp=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step(prm3)
+        torch.cuda.synchronize()
+        variants["batched_matrix_free_hvp_solves_per_s"] = args.pairs / (time.perf_counter() - t1)
         line["variants"] = variants
 
     if not args.no_sweep:
