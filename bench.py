@@ -10,7 +10,10 @@ T2 = 50, Armijo (0.5, 1e-4), CG relative residual 1e-6, marginal tolerance
 
 One step = one batched call of the C ABI (pins_solve_batch_device) that
 solves all 64 pairs; value = solves per second over the timed steps.  Inputs
-are resident in HBM before the timed region starts.
+are resident in HBM before the timed region starts.  The Newton CG multiplies
+by the full Hessian (matrix-free) in the first 25 outer iterations, while the
+plans are diffuse, and by the sparsified Hessian (CSR/CSC) after
+(--hvp-switch); three lanes (--lanes).
 
 The JSON line also carries:
   roofline     -- the dominant kernel class, its algorithmic work per launch
@@ -61,6 +64,8 @@ FLOPS_PER_ENTRY = {
     "csc": 7.0,
     # exponent (3) + exp + cost/entropy/marginal accumulations (6)
     "final": 10.0 + EXP_FLOPS,
+    # matrix-free Hessian products: exponent (3) + exp + product/accumulate (2) per entry and half
+    "pcg_wide": 5.0 + EXP_FLOPS,
 }
 # Algorithmic bytes per unit of the sparse kernels: CG reads each stored
 # CSR/CSC entry once per iteration: a 2-byte index (m, n <= 65536) and a
@@ -81,6 +86,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-launch HIP events")
+    ap.add_argument("--hvp-switch", type=int, default=25,
+                    help="Hessian products of the Newton CG: matrix-free (full Hessian) in the outer iterations "
+                         "k < this, sparsified (CSR) after; 0 = sparsified throughout")
     ap.add_argument("--lanes", type=int, default=3,
                     help="concurrent lanes of the batched call (params.streams); results do not depend on it")
     ap.add_argument("--no-sweep", action="store_true",
@@ -174,7 +182,8 @@ def main():
                     kwork[k] = kwork.get(k, 0.0) + v
         return kms, kwork, kcalls
 
-    base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=args.lanes)
+    hess = dict(hvp=2, hvp_switch=args.hvp_switch) if args.hvp_switch > 0 else dict(hvp=0)
+    base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=args.lanes, **hess)
     share_ms, _, _ = aggregate([step(P.params(profile=1, **base))])
     dom = max(share_ms, key=share_ms.get)
     prm = P.params(profile=0 if args.no_profile else 1, profile_mask=1 << P.KERNEL_NAMES.index(dom), **base)
@@ -225,7 +234,9 @@ def main():
                 config=dict(workload="image-histogram pairs, 28x28 grid (m=n=784), squared grid distance/max "
                                      "streamed, eta=0.1, K=250, batched (one call per step)",
                             pairs=args.pairs, m=n, n=n, eta=args.eta, K=args.K, precision=args.precision,
-                            mode="batched", lanes=args.lanes),
+                            mode="batched", lanes=args.lanes,
+                            hessian=("matrix-free full Hessian for outer iterations k < %d, sparsified (CSR) after"
+                                     % args.hvp_switch) if args.hvp_switch > 0 else "sparsified (CSR)"),
                 roofline=roofline)
 
     last = results[-1]
@@ -236,14 +247,14 @@ def main():
     if not args.no_variants:
         variants = {}
         other = P.FP64 if prec == P.MIXED else P.MIXED
-        prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other, streams=args.lanes)
+        prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other, streams=args.lanes, **hess)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         step(prm2)
         torch.cuda.synchronize()
         variants["batched_" + ("fp64" if other == P.FP64 else "mixed") + "_solves_per_s"] = \
             args.pairs / (time.perf_counter() - t1)
-        prm1 = P.params(eta=args.eta, max_outer=args.K, precision=prec)
+        prm1 = P.params(eta=args.eta, max_outer=args.K, precision=prec, **hess)
         nplain = min(4, args.pairs)
         lat = []
         for q in range(nplain):
@@ -255,13 +266,14 @@ def main():
         variants["plain_single_instance_solves_per_s"] = nplain / sum(lat)
         variants["plain_single_instance_ms"] = [round(1e3 * v, 2) for v in lat]
         variants["batched_uneven_points"] = uneven_points(P, ctx, torch, np, dev, W, st)
-        # the paper's streaming variant: matrix-free products with the full Hessian
-        prm3 = P.params(eta=args.eta, max_outer=args.K, precision=prec, streams=args.lanes, hvp=1)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        step(prm3)
-        torch.cuda.synchronize()
-        variants["batched_matrix_free_hvp_solves_per_s"] = args.pairs / (time.perf_counter() - t1)
+        # Hessian products: sparsified throughout, and matrix-free throughout
+        for key, hv in (("batched_sparsified_hvp_solves_per_s", 0), ("batched_matrix_free_hvp_solves_per_s", 1)):
+            prm3 = P.params(eta=args.eta, max_outer=args.K, precision=prec, streams=args.lanes, hvp=hv)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            step(prm3)
+            torch.cuda.synchronize()
+            variants[key] = args.pairs / (time.perf_counter() - t1)
         line["variants"] = variants
 
     if not args.no_sweep:

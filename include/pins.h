@@ -101,7 +101,9 @@ typedef struct {
     int32_t hvp;          /* Hessian-vector products of the Newton CG: 0 = the sparsified
                              Hessian (Sparsify, CSR/CSC products; the default), 1 = matrix-free
                              products with the full Hessian, X~ recomputed tile by tile from
-                             the potentials and the streamed cost (no Sparsify) */
+                             the potentials and the streamed cost (no Sparsify), 2 = matrix-free
+                             in the outer iterations k < hvp_switch, sparsified after */
+    int32_t hvp_switch;   /* hvp = 2: first outer iteration with sparsified products */
 } pins_params;
 
 /* One problem instance.  For pins_solve the pointers are host pointers, for
@@ -166,6 +168,7 @@ typedef struct {
 #define PINS_K_SHIFT 10    /* outer shift */
 #define PINS_K_FINAL 11    /* potentials and outputs */
 #define PINS_K_SETUP 12    /* cost preparation, initialisation */
+#define PINS_K_PCG_WIDE 13 /* CG with products over many blocks: large instances, matrix-free */
 
 int pins_abi_version(void);
 

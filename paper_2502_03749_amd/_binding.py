@@ -28,7 +28,7 @@ FP64, MIXED = 0, 1
 SHIFT_IMPLICIT, SHIFT_MATERIALIZED = 0, 1
 NKERN = 16
 KERNEL_NAMES = ["row_lse", "col_lse", "col_merge", "grad", "grad_merge", "fill", "csc", "pcg", "ls", "update",
-                "shift", "final", "setup"]
+                "shift", "final", "setup", "pcg_wide"]
 
 _D = ctypes.POINTER(ctypes.c_double)
 
@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
                 ("ls_beta", ctypes.c_double), ("ls_c1", ctypes.c_double), ("ls_max", ctypes.c_int32),
                 ("rho_levels", ctypes.c_int32), ("rho", ctypes.c_double), ("budget", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("shift_mode", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("profile_mask", ctypes.c_int32), ("hvp", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("profile_mask", ctypes.c_int32), ("hvp", ctypes.c_int32),
+                ("hvp_switch", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):

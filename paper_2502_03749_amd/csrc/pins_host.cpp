@@ -197,7 +197,8 @@ void check_params(const pins_params& p) {
     if (p.precision != PINS_FP64 && p.precision != PINS_MIXED) fail(PINS_EINVAL, "unknown precision");
     if (p.shift_mode != PINS_SHIFT_IMPLICIT && p.shift_mode != PINS_SHIFT_MATERIALIZED)
         fail(PINS_EINVAL, "unknown shift_mode");
-    if (p.hvp != 0 && p.hvp != 1) fail(PINS_EINVAL, "hvp must be 0 (sparsified) or 1 (matrix-free)");
+    if (p.hvp < 0 || p.hvp > 2) fail(PINS_EINVAL, "hvp must be 0 (sparsified), 1 (matrix-free) or 2 (switch)");
+    if (p.hvp_switch < 0) fail(PINS_EINVAL, "hvp_switch must be >= 0");
 }
 
 void check_problem_shape(const pins_problem& P) {
@@ -494,10 +495,12 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     }
 
     const bool f32 = p.precision == PINS_MIXED;
-    const bool mf = p.hvp == 1;  // matrix-free Hessian products (no Sparsify)
+    // matrix-free Hessian products (no Sparsify) in outer iteration k
+    auto matrix_free = [&](int k) { return p.hvp == 1 || (p.hvp == 2 && k < p.hvp_switch); };
     const int K = p.max_outer;
     const int M_WARM = 1 << PH_WARM, M_FB = 1 << PH_FALLBACK;
     for (int k = 0; k < K; ++k) {
+        const bool mf = matrix_free(k);
         kp.tol = (k == K - 1) ? p.final_tol : p.inner_tol;
         kp.last = (k == K - 1) ? 1 : 0;
         if (k > 0) run(ctx, st, PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
@@ -527,15 +530,15 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
             } else {
                 // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
                 const int hsrc = mf ? src : -1;
-                run(ctx, st, PINS_K_PCG, [&] { launch_wcg_begin(L, hsrc); });
+                run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_begin(L, hsrc); });
                 for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
                     const Ctrl* hc = readback(ctx, st, d_ctrl, count);
                     bool on = false;
                     for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
                     if (!on) break;
-                    for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG, [&] { launch_wcg_iter(L, hsrc); });
+                    for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc); });
                 }
-                run(ctx, st, PINS_K_PCG, [&] { launch_wcg_end(L, hsrc); });
+                run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_end(L, hsrc); });
             }
             run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
             // one readback per Newton step: who is still iterating, who needs more
@@ -624,6 +627,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         r.kern_work[PINS_K_GRAD] = S.work[W_GRAD];
         r.kern_work[PINS_K_FILL] = S.work[W_FILL];
         r.kern_work[PINS_K_PCG] = S.work[W_CG];
+        r.kern_work[PINS_K_PCG_WIDE] = S.work[W_CG_WIDE];
         r.kern_work[PINS_K_LS] = S.work[W_LS];
         r.kern_work[PINS_K_FINAL] = S.work[W_FINAL];
         r.group = 0;
@@ -769,6 +773,7 @@ void pins_params_default(pins_params* p) {
     p->streams = 0;
     p->profile_mask = 0;
     p->hvp = 0;
+    p->hvp_switch = 0;
 }
 
 int pins_create(int device, pins_ctx** out) {

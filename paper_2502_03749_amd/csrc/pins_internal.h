@@ -98,7 +98,7 @@ struct Ctrl {
 };
 
 // pass kinds counted in Ctrl::work
-enum WorkKind : int { W_ROW = 0, W_COL = 1, W_GRAD = 2, W_FILL = 3, W_CG = 4, W_LS = 5, W_FINAL = 6 };
+enum WorkKind : int { W_ROW = 0, W_COL = 1, W_GRAD = 2, W_FILL = 3, W_CG = 4, W_LS = 5, W_FINAL = 6, W_CG_WIDE = 7 };
 
 // Kernel-wide parameters (passed by value).
 struct KP {

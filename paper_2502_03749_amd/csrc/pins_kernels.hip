@@ -1078,10 +1078,11 @@ __device__ __forceinline__ void spmv_part(const DevInst& I, int m, const int* bi
     spmv_bin<32, IX, VT>(I, m, bins, bo[5], bo[6], rp, cp, pv, out);
 }
 
-__device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp) {
+__device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp,
+                                         int wide = 0) {
     S.last_cg = it;
     S.cg_total += it;
-    S.work[W_CG] += 2.0 * (double)S.nnz * (double)it;
+    S.work[wide ? W_CG_WIDE : W_CG] += 2.0 * (double)S.nnz * (double)it;
     S.fused = 0;
     S.gd = gd;
     S.dab = dab;
@@ -1590,7 +1591,7 @@ __global__ __launch_bounds__(1024) void k_wcg_finish(const DevInst* __restrict__
     gd = block_sum<1024>(gd, sh);
     dab = block_sum<1024>(dab, sh);
     fa = block_sum<1024>(fa, sh);
-    if (threadIdx.x == 0) ls_setup(ctrl[b], ctrl[b].cg_it, gd, dab, fa, kp);
+    if (threadIdx.x == 0) ls_setup(ctrl[b], ctrl[b].cg_it, gd, dab, fa, kp, 1);
 }
 
 // ---------------------------------------------------------------------------

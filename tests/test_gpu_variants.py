@@ -101,3 +101,24 @@ def test_matrix_free_hessian_products_parity(ctx, kind):
     o = oracle.pins(C, a, b, eta=eta, K=K)
     check_parity(g, o, a, b)
     assert g["newton_iters"] > 0 and g["cg_iters"] > 0
+
+
+def test_hybrid_hessian_schedule_parity(ctx):
+    """params.hvp = 2: matrix-free products in the first outer iterations, the
+    sparsified Hessian after; converged output as the oracle's."""
+    print("case hybrid hessian", flush=True)
+    import workloads as W
+
+    pr = W.blob_pair(13, s=14)
+    C, a, b = oracle.cost_grid(14), pr["a"], pr["b"]
+    eta, K = 0.1, 12
+    for prec in (P.FP64, P.MIXED):
+        g = gpu_solve(ctx, dict(kind=P.COST_GRID, grid_s=14, a=a, b=b),
+                      P.params(eta=eta, max_outer=K, hvp=2, hvp_switch=4, precision=prec))
+        g["_C"] = C
+        o = oracle.pins(C, a, b, eta=eta, K=K)
+        if prec == P.FP64:
+            check_parity(g, o, a, b)
+        else:
+            assert g["rc"] == 0 and g["resid"] <= 1e-10 and abs(g["cost"] - o["cost"]) / o["cost"] <= 1e-6
+        assert g["kern_work"]["pcg_wide"] > 0 and g["kern_work"]["pcg"] > 0
