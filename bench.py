@@ -67,10 +67,11 @@ FLOPS_PER_ENTRY = {
     # matrix-free Hessian products: exponent (3) + exp + product/accumulate (2) per entry and half
     "pcg_wide": 5.0 + EXP_FLOPS,
 }
-# Algorithmic bytes per unit of the sparse kernels: CG reads each stored
-# CSR/CSC entry once per iteration: a 2-byte index (m, n <= 65536) and a
-# 4-byte (mixed precision) or 8-byte (FP64) value.
-BYTES_PER_ENTRY = {"mixed": {"pcg": 6.0}, "fp64": {"pcg": 10.0}}
+# Algorithmic bytes per unit of the sparse kernels: the single-block CG reads
+# each stored CSR/CSC entry once per iteration, a 4-byte index (a byte offset
+# into the gathered vector) and a 4-byte (mixed precision) or 8-byte (FP64)
+# value.
+BYTES_PER_ENTRY = {"mixed": {"pcg": 8.0}, "fp64": {"pcg": 12.0}}
 
 
 def parse():

@@ -110,7 +110,7 @@ typedef struct {
  * the *_device entry points they are device pointers. */
 typedef struct {
     int32_t kind;      /* pins_cost_kind */
-    int32_t m, n;      /* sizes; GRID: m = n = grid_s^2 */
+    int32_t m, n;      /* sizes (>= 1, m*n < 2^31, m+n < 2^28, else PINS_EUNSUPPORTED); GRID: m = n = grid_s^2 */
     int32_t d;         /* POINTS: dimension */
     int32_t grid_s;    /* GRID: side */
     int32_t reserved;

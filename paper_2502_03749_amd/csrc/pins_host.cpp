@@ -208,6 +208,7 @@ void check_problem_shape(const pins_problem& P) {
     if (P.kind == PINS_COST_GRID && (P.grid_s < 1 || P.grid_s > 46340 || P.m != P.grid_s * P.grid_s || P.n != P.m))
         fail(PINS_EINVAL, "GRID needs m = n = grid_s^2");
     if ((double)P.m * (double)P.n > 2147483647.0) fail(PINS_EUNSUPPORTED, "m*n must be below 2^31");
+    if ((double)P.m + (double)P.n >= 268435456.0) fail(PINS_EUNSUPPORTED, "m+n must be below 2^28");
     if (P.kind == PINS_COST_DENSE && !P.C) fail(PINS_EINVAL, "DENSE needs C");
     if (P.kind == PINS_COST_POINTS && (!P.x || !P.y || P.d < 1)) fail(PINS_EINVAL, "POINTS needs x, y and d >= 1");
     if (!P.a || !P.b) fail(PINS_EINVAL, "a and b are required");
@@ -457,7 +458,10 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     L.total_rowblk = B.roff.back();
     // the CG's copy of S: 16-bit indices whenever they fit, float values in
     // mixed precision (the CG vectors and all sums stay double)
-    L.sp_fmt = ((B.max_m <= 65536 && B.max_n <= 65536) ? 1 : 0) | (p.precision == PINS_MIXED ? 2 : 0);
+    // uint16 indices (2 bytes an entry) for the wide CG, whose products stream S
+    // from memory; int32 byte offsets (no unpacking in the gather) otherwise
+    const bool u16 = B.max_mn > pins::WCG_MAX_N && B.max_m <= 65536 && B.max_n <= 65536;
+    L.sp_fmt = (u16 ? 1 : 0) | (p.precision == PINS_MIXED ? 2 : 0);
     KP& kp = L.kp;
     std::memset(&kp, 0, sizeof(kp));
     kp.eta = p.eta;

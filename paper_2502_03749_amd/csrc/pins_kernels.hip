@@ -98,9 +98,10 @@ __device__ __forceinline__ int dpp_i32(int v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
 }
 
-// sum over aligned groups of G lanes (G = 2, 4, 8, 16); every lane of the group gets it
+// sum over aligned groups of G lanes (G = 1, 2, 4, 8, 16, 32); every lane of the group gets it
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group of 1..32 lanes");
     if (G >= 2) v += dpp_f64<0xB1>(v);
     if (G >= 4) v += dpp_f64<0x4E>(v);
     if (G >= 8) v += dpp_f64<0x141>(v);
@@ -874,6 +875,14 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
     if (threadIdx.x == 0) ctrl[b].binoff[2 * NBIN] = off;
 }
 
+// Index storage of S and S^T.  uint16: the column (of S) or row (of S^T)
+// index itself.  int32: the byte offset of the vector entry the product
+// gathers, 8 (o + k) with o = m for the columns of S and o = 0 for the rows of
+// S^T, so that a product reads p at base + offset with no unpacking or scaling
+// (the host admits int32 storage only while 8 (m + n) fits in an int).
+__device__ __forceinline__ void put_ix(unsigned short* p, int slot, int k, int) { p[slot] = (unsigned short)k; }
+__device__ __forceinline__ void put_ix(int* p, int slot, int k, int o) { p[slot] = 8 * (o + k); }
+
 template <class Src, class IX, class VT>
 __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const BlkRef br = blk_ref(kp.toff, kp.count);
@@ -939,12 +948,12 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
             const int nq = sNq[r];
             if (e < 4 * nq) {
                 const int slot = quad_slot(sStart[r], nq, e);
-                static_cast<IX*>(I.col)[slot] = (IX)j;
+                put_ix(static_cast<IX*>(I.col), slot, j, m);
                 static_cast<VT*>(I.val)[slot] = v;
             }
             if (ce < 4 * cnq) {
                 const int slot = quad_slot(cstart, cnq, ce);
-                static_cast<IX*>(I.rowT)[slot] = (IX)(i0 + r);
+                put_ix(static_cast<IX*>(I.rowT), slot, i0 + r, 0);
                 static_cast<VT*>(I.valT)[slot] = v;
             }
             ++ce;
@@ -955,14 +964,14 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     if (rb == I.nrb - 1 && valid)
         for (; ce < 4 * cnq; ++ce) {
             const int slot = quad_slot(cstart, cnq, ce);
-            static_cast<IX*>(I.rowT)[slot] = (IX)0;
+            put_ix(static_cast<IX*>(I.rowT), slot, 0, 0);
             static_cast<VT*>(I.valT)[slot] = (VT)0;
         }
     if (cb == I.ncb - 1 && (int)threadIdx.x < rows) {
         const int r = threadIdx.x, nq = sNq[r];
         for (int e = sE0[r] + wc[r][0] + wc[r][1] + wc[r][2] + wc[r][3]; e < 4 * nq; ++e) {
             const int slot = quad_slot(sStart[r], nq, e);
-            static_cast<IX*>(I.col)[slot] = (IX)0;
+            put_ix(static_cast<IX*>(I.col), slot, 0, m);
             static_cast<VT*>(I.val)[slot] = (VT)0;
         }
     }
@@ -987,95 +996,150 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
 // ---------------------------------------------------------------------------
 // Off-diagonal part of M times p (S v for a row k < m, S^T u for k >= m).
 // Rows are stored in aligned, transposed quads (see quad_slot); the entry
-// order inside a row does not matter for the product.  The rows of one bin (similar quad counts)
-// are handled by groups of G lanes, each lane loading one quad (its 4 indices
-// and 4 values in one vector load each) per step, so the lanes of a wave do
-// rows of about the same length.  ptr arrays: CSR row pointers (rp, m+1) and
-// CSC column pointers (cp, n+1), in LDS or global memory; bins: the row list.
+// order inside a row does not matter for the product.  The rows of one bin
+// (similar quad counts) are handled by groups of G lanes, so the lanes of a
+// wave do rows of about the same length; a lane loads each quad (its 4
+// indices and 4 values) with one vector load each and keeps several quads in
+// flight.  ptr arrays: CSR row pointers (rp, m+1) and CSC column pointers
+// (cp, n+1), in LDS or global memory; bins: the row list.
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void load_ix4(const unsigned short* p, int q, int (&x)[4]) {
-    const u16x4 v = ldg(reinterpret_cast<const u16x4*>(p) + q);
-    x[0] = v.x;
-    x[1] = v.y;
-    x[2] = v.z;
-    x[3] = v.w;
-}
-__device__ __forceinline__ void load_ix4(const int* p, int q, int (&x)[4]) {
-    const i32x4 v = ldg(reinterpret_cast<const i32x4*>(p) + q);
-    x[0] = v.x;
-    x[1] = v.y;
-    x[2] = v.z;
-    x[3] = v.w;
-}
-__device__ __forceinline__ void load_v4(const float* p, int q, double (&w)[4]) {
-    const f32x4 v = ldg(reinterpret_cast<const f32x4*>(p) + q);
-    w[0] = v.x;
-    w[1] = v.y;
-    w[2] = v.z;
-    w[3] = v.w;
-}
-__device__ __forceinline__ void load_v4(const double* p, int q, double (&w)[4]) {
-    const f64x2 u = ldg(reinterpret_cast<const f64x2*>(p) + 2 * q);
-    const f64x2 v = ldg(reinterpret_cast<const f64x2*>(p) + 2 * q + 1);
-    w[0] = u.x;
-    w[1] = u.y;
-    w[2] = v.x;
-    w[3] = v.y;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// one quad of a row as loaded: its 4 stored indices and its 4 values, one
+// vector load each (kept packed until used, so that several quads can be in
+// flight without many registers)
+template <class IX>
+struct QuadIx;
+template <>
+struct QuadIx<unsigned short> {
+    typedef u16x4 T;
+};
+template <>
+struct QuadIx<int> {
+    typedef i32x4 T;
+};
+template <class VT>
+struct QuadVal;
+template <>
+struct QuadVal<float> {
+    typedef f32x4 T;
+};
+template <>
+struct QuadVal<double> {
+    typedef f64x4 T;
+};
+
+// The four arrays of S and S^T, read once per kernel (a per-row load of the
+// descriptor's fields would put a dependent global load in front of every row).
+template <class IX, class VT>
+struct SpArrays {
+    const IX* col;
+    const VT* val;
+    const IX* rowT;
+    const VT* valT;
+    __device__ __forceinline__ explicit SpArrays(const DevInst& I)
+        : col(static_cast<const IX*>(I.col)),
+          val(static_cast<const VT*>(I.val)),
+          rowT(static_cast<const IX*>(I.rowT)),
+          valT(static_cast<const VT*>(I.valT)) {}
+};
+
+// entry of the gathered vector named by a stored index (see put_ix): pv is the
+// vector's half for uint16 indices, the whole vector for int32 byte offsets
+template <class IX>
+__device__ __forceinline__ double gat(const double* __restrict__ pv, int x) {
+    if constexpr (sizeof(IX) == 4)
+        return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(pv) + x);
+    else
+        return pv[x];
 }
 
-template <int G, class IX, class VT>
-__device__ __forceinline__ void spmv_bin(const DevInst& I, int m, const int* bins, int lo, int hi, const int* rp,
-                                         const int* cp, const double* __restrict__ pv, double* __restrict__ out,
-                                         const double* __restrict__ rdiv = nullptr) {
+template <class IX, class XV, class WV>
+__device__ __forceinline__ double quad_dot(const XV& x, const WV& w, const double* __restrict__ pv) {
+    return ((double)w.x * gat<IX>(pv, (int)x.x) + (double)w.y * gat<IX>(pv, (int)x.y)) +
+           ((double)w.z * gat<IX>(pv, (int)x.z) + (double)w.w * gat<IX>(pv, (int)x.w));
+}
+
+// Products of the rows bins[lo..hi) of M's off-diagonal part: G lanes per
+// row, lane lg taking the row's quads lg, lg + G, ..., U quads in flight (the
+// loads of a step are issued together, also for the lane's last < U quads).
+template <int G, int U, class IX, class VT>
+__device__ __forceinline__ void spmv_bin(const SpArrays<IX, VT>& A, int m, const int* bins, int lo, int hi,
+                                         const int* rp, const int* cp, const double* __restrict__ pv,
+                                         double* __restrict__ out, const double* __restrict__ rdiv = nullptr) {
+    typedef typename QuadIx<IX>::T XV;
+    typedef typename QuadVal<VT>::T WV;
     constexpr int NG = 1024 / G;
     const int g = threadIdx.x / G, lg = threadIdx.x % G;
     for (int t = lo + g; t < hi; t += NG) {
         const int k = bins[t];
-        const IX* ix;
-        const VT* vl;
-        int q0, q1, o;
-        if (k < m) {
-            ix = static_cast<const IX*>(I.col);
-            vl = static_cast<const VT*>(I.val);
-            q0 = rp[k] >> 2;
-            q1 = rp[k + 1] >> 2;
-            o = m;
-        } else {
-            ix = static_cast<const IX*>(I.rowT);
-            vl = static_cast<const VT*>(I.valT);
-            q0 = cp[k - m] >> 2;
-            q1 = cp[k - m + 1] >> 2;
-            o = 0;
+        const bool row = k < m;
+        const XV* ix = reinterpret_cast<const XV*>(row ? A.col : A.rowT);
+        const WV* vl = reinterpret_cast<const WV*>(row ? A.val : A.valT);
+        const int* ptr = row ? rp + k : cp + (k - m);
+        const double* pvo = (sizeof(IX) == 2 && row) ? pv + m : pv;
+        const int q1 = ptr[1] >> 2;
+        int q = (ptr[0] >> 2) + lg;
+        double s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s[u] = 0.0;
+        for (; q + (U - 1) * G < q1; q += U * G) {
+            XV x[U];
+            WV w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                x[u] = ldg(ix + q + u * G);
+                w[u] = ldg(vl + q + u * G);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) s[u] += quad_dot<IX>(x[u], w[u], pvo);
         }
-        double s = 0.0;
-        for (int q = q0 + lg; q < q1; q += G) {
-            int x[4];
-            double w[4];
-            load_ix4(ix, q, x);
-            load_v4(vl, q, w);
-            s += ((w[0] * pv[o + x[0]] + w[1] * pv[o + x[1]]) + (w[2] * pv[o + x[2]] + w[3] * pv[o + x[3]]));
+        if (U > 1 && q < q1) {
+            XV x[U > 1 ? U - 1 : 1];
+            WV w[U > 1 ? U - 1 : 1];
+#pragma unroll
+            for (int u = 0; u < U - 1; ++u)
+                if (q + u * G < q1) {
+                    x[u] = ldg(ix + q + u * G);
+                    w[u] = ldg(vl + q + u * G);
+                }
+#pragma unroll
+            for (int u = 0; u < U - 1; ++u)
+                if (q + u * G < q1) s[u] += quad_dot<IX>(x[u], w[u], pvo);
         }
-        s = group_sum<G>(s);
-        if (lg == 0) out[k] = rdiv ? s / rdiv[k] : s;
+        double tot = s[0];
+#pragma unroll
+        for (int u = 1; u < U; ++u) tot += s[u];
+        const double sum = group_sum<G>(tot);
+        if (lg == 0) out[k] = rdiv ? sum / rdiv[k] : sum;
     }
 }
 
-// One half of M's off-diagonal product: bo = the NBIN + 1 bin offsets of the
-// rows of S (out[i] = (S v)_i, v = pv[m..]) or of the rows of S^T
-// (out[m + j] = (S^T u)_j, u = pv[0..m)).
+// single-block CG products: a row of up to 2^t quads gets 2^(t - CG_LANE_SHIFT)
+// lanes (at least one), each with CG_QUADS quads in flight (measured best of
+// shifts 1..3 and 2..4 quads in flight on 28x28 grid instances)
+constexpr int CG_LANE_SHIFT = 1;
+constexpr int CG_QUADS = 3;
+constexpr int cg_lanes(int quads) { return (quads >> CG_LANE_SHIFT) > 1 ? (quads >> CG_LANE_SHIFT) : 1; }
+// One half of M's off-diagonal product inside one block: bo = the NBIN + 1
+// bin offsets of the rows of S (out[i] = (S v)_i, v = pv[m..]) or of the rows
+// of S^T (out[m + j] = (S^T u)_j, u = pv[0..m)).  Bin t holds rows of up to
+// 2^t quads (the last bin: more); each row gets cg_lanes(2^t) lanes, so that
+// a lane takes a few quads of its row.
 template <class IX, class VT>
-__device__ __forceinline__ void spmv_part(const DevInst& I, int m, const int* bins, const int* bo, const int* rp,
-                                          const int* cp, const double* __restrict__ pv, double* __restrict__ out) {
-    spmv_bin<1, IX, VT>(I, m, bins, bo[0], bo[1], rp, cp, pv, out);
-    spmv_bin<2, IX, VT>(I, m, bins, bo[1], bo[2], rp, cp, pv, out);
-    spmv_bin<4, IX, VT>(I, m, bins, bo[2], bo[3], rp, cp, pv, out);
-    spmv_bin<8, IX, VT>(I, m, bins, bo[3], bo[4], rp, cp, pv, out);
-    spmv_bin<16, IX, VT>(I, m, bins, bo[4], bo[5], rp, cp, pv, out);
-    spmv_bin<32, IX, VT>(I, m, bins, bo[5], bo[6], rp, cp, pv, out);
+__device__ __forceinline__ void spmv_part(const SpArrays<IX, VT>& A, int m, const int* bins, const int* bo,
+                                          const int* rp, const int* cp, const double* __restrict__ pv,
+                                          double* __restrict__ out) {
+    spmv_bin<1, CG_QUADS, IX, VT>(A, m, bins, bo[0], bo[1], rp, cp, pv, out);
+    spmv_bin<cg_lanes(2), CG_QUADS, IX, VT>(A, m, bins, bo[1], bo[2], rp, cp, pv, out);
+    spmv_bin<cg_lanes(4), CG_QUADS, IX, VT>(A, m, bins, bo[2], bo[3], rp, cp, pv, out);
+    spmv_bin<cg_lanes(8), CG_QUADS, IX, VT>(A, m, bins, bo[3], bo[4], rp, cp, pv, out);
+    spmv_bin<cg_lanes(16), CG_QUADS, IX, VT>(A, m, bins, bo[4], bo[5], rp, cp, pv, out);
+    spmv_bin<cg_lanes(32), CG_QUADS, IX, VT>(A, m, bins, bo[5], bo[6], rp, cp, pv, out);
 }
 
 __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp,
@@ -1104,56 +1168,55 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
-    // sp: the direction p on the rows, D_c^-1 S^T p on the columns;
-    // sAp: products of the current half
+    // LDS: sp, the direction p on the rows and D_c^-1 S^T p on the columns;
+    // sAp, products of the current half; sdg, the diagonal (r, c); the
+    // pointers and the binned row list
     __shared__ double sp[1024 * EPT];
     __shared__ double sAp[1024 * EPT];
+    __shared__ double sdg[1024 * EPT];
     __shared__ double sh[32];
-    constexpr bool PTR_LDS = EPT <= 4;  // pointers and the binned row list staged in LDS when they fit
-    __shared__ int sptr[PTR_LDS ? 1024 * EPT + 2 : 1];
-    __shared__ int sbin[PTR_LDS ? 1024 * EPT : 1];
+    __shared__ int sptr[1024 * EPT + 2];
+    __shared__ int sbin[1024 * EPT];
     __shared__ int sbo[2 * NBIN + 1];
     const int tid = threadIdx.x;
-    const int* rp = I.rowptr;
-    const int* cp = I.colptr;
-    const int* bins = I.rowbin;
-    if (PTR_LDS) {
-        for (int k = tid; k <= m; k += 1024) sptr[k] = I.rowptr[k];
-        for (int k = tid; k <= n; k += 1024) sptr[m + 1 + k] = I.colptr[k];
-        for (int k = tid; k < N; k += 1024) sbin[k] = I.rowbin[k];
-        rp = sptr;
-        cp = sptr + m + 1;
-        bins = sbin;
-    }
+    const SpArrays<IX, VT> A(I);
+    for (int k = tid; k <= m; k += 1024) sptr[k] = I.rowptr[k];
+    for (int k = tid; k <= n; k += 1024) sptr[m + 1 + k] = I.colptr[k];
+    for (int k = tid; k < N; k += 1024) sbin[k] = I.rowbin[k];
+    const int* rp = sptr;
+    const int* cp = sptr + m + 1;
+    const int* bins = sbin;
     if (tid <= 2 * NBIN) sbo[tid] = ctrl[b].binoff[tid];
     const double eta = kp.eta;
-    // registers: rhs bv, diagonal dg; on rows the iterate x, residual r, direction p
-    double x[EPT], r[EPT], p[EPT], dg[EPT], bv[EPT];
+    // right-hand side eta (target - diagonal) of entry k (recomputed where needed)
+    auto rhs = [&](int k) { return eta * (((k < m) ? I.a[k] : I.b[k - m]) - sdg[k]); };
+    // registers: on the rows the iterate x, residual r, direction p
+    double x[EPT], r[EPT], p[EPT];
     double bb = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const int k = tid + 1024 * t;
-        x[t] = r[t] = p[t] = bv[t] = 0.0;
-        dg[t] = 1.0;
+        x[t] = r[t] = p[t] = 0.0;
         if (k < N) {
-            dg[t] = I.rc[k];
+            const double dk = I.rc[k];
+            sdg[k] = dk;
             const double tg = (k < m) ? I.a[k] : I.b[k - m];
-            bv[t] = eta * (tg - dg[t]);
-            bb += bv[t] * bv[t];
-            if (k >= m) sp[k] = bv[t] / dg[t];  // D_c^-1 b_2
+            const double bk = eta * (tg - dk);
+            bb += bk * bk;
+            if (k >= m) sp[k] = bk / dk;  // D_c^-1 b_2
         }
     }
     bb = block_sum<1024>(bb, sh);  // also orders the LDS writes above
     const double bn = sqrt(bb);
-    spmv_part<IX, VT>(I, m, bins, sbo, rp, cp, sp, sAp);  // S D_c^-1 b_2 on the rows
+    spmv_part<IX, VT>(A, m, bins, sbo, rp, cp, sp, sAp);  // S D_c^-1 b_2 on the rows
     __syncthreads();
     double rr = 0.0, rz = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const int k = tid + 1024 * t;
         if (k < m) {
-            r[t] = bv[t] - sAp[k];
-            p[t] = r[t] / dg[t];
+            r[t] = rhs(k) - sAp[k];
+            p[t] = r[t] / sdg[k];
             sp[k] = p[t];
             rr += r[t] * r[t];
             rz += r[t] * p[t];
@@ -1164,22 +1227,22 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     if (bn > 0.0 && sqrt(rr) > kp.cg_rtol * bn) {
         while (it < kp.cg_max) {
             __syncthreads();
-            spmv_part<IX, VT>(I, m, bins, sbo + NBIN, rp, cp, sp, sAp);  // S^T p
+            spmv_part<IX, VT>(A, m, bins, sbo + NBIN, rp, cp, sp, sAp);  // S^T p
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
-                if (k >= m && k < N) sp[k] = sAp[k] / dg[t];
+                if (k >= m && k < N) sp[k] = sAp[k] / sdg[k];
             }
             __syncthreads();
-            spmv_part<IX, VT>(I, m, bins, sbo, rp, cp, sp, sAp);  // S D_c^-1 S^T p
+            spmv_part<IX, VT>(A, m, bins, sbo, rp, cp, sp, sAp);  // S D_c^-1 S^T p
             __syncthreads();
             double pq = 0.0;
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
                 if (k < m) {
-                    const double q = dg[t] * p[t] - sAp[k];
+                    const double q = sdg[k] * p[t] - sAp[k];
                     sAp[k] = q;
                     pq += p[t] * q;
                 }
@@ -1196,7 +1259,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
                     x[t] += al * p[t];
                     r[t] -= al * sAp[k];
                     rr += r[t] * r[t];
-                    rz2 += r[t] * (r[t] / dg[t]);
+                    rz2 += r[t] * (r[t] / sdg[k]);
                 }
             }
             block_sum2<1024>(rr, rz2, sh);
@@ -1208,7 +1271,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
                 if (k < m) {
-                    p[t] = r[t] / dg[t] + be * p[t];
+                    p[t] = r[t] / sdg[k] + be * p[t];
                     sp[k] = p[t];
                 }
             }
@@ -1222,17 +1285,17 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
         if (k < m) sp[k] = x[t];
     }
     __syncthreads();
-    spmv_part<IX, VT>(I, m, bins, sbo + NBIN, rp, cp, sp, sAp);
+    spmv_part<IX, VT>(A, m, bins, sbo + NBIN, rp, cp, sp, sAp);
     __syncthreads();
     double gd = 0.0, dab = 0.0, fa = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const int k = tid + 1024 * t;
         if (k < N) {
-            if (k >= m) x[t] = (bv[t] - sAp[k]) / dg[t];
+            if (k >= m) x[t] = (rhs(k) - sAp[k]) / sdg[k];
             const double tg = (k < m) ? I.a[k] : I.b[k - m];
             I.d[k] = x[t];
-            gd += (tg - dg[t]) * x[t];
+            gd += (tg - sdg[k]) * x[t];
             dab += tg * x[t];
             fa += fabs(tg * x[t]);
         }
@@ -1241,101 +1304,6 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     dab = block_sum<1024>(dab, sh);
     fa = block_sum<1024>(fa, sh);
     if (tid == 0) ls_setup(ctrl[b], it, gd, dab, fa, kp);
-}
-
-// Same iteration with every vector in global memory (large m + n).
-template <class IX, class VT>
-__global__ __launch_bounds__(1024) void k_pcg(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
-    const int b = blockIdx.x;
-    if (ctrl[b].phase != PH_NEWTON) return;
-    const DevInst& I = insts[b];
-    const int m = I.m, n = I.n, N = m + n;
-    double* __restrict__ x = I.d;            // [x; y]
-    double* __restrict__ res = I.cgw;        // residual on the rows, rhs on the columns
-    double* __restrict__ bv = I.cgw + N;     // rhs
-    double* __restrict__ p = I.cgw + 2 * N;  // direction on the rows, D_c^-1 S^T p on the columns
-    double* __restrict__ Ap = I.cgw + 3 * N;
-    const double* __restrict__ dg = I.rc;
-    __shared__ double sh[32];
-    __shared__ int sbo[2 * NBIN + 1];
-    if (threadIdx.x <= 2 * NBIN) sbo[threadIdx.x] = ctrl[b].binoff[threadIdx.x];
-    const double eta = kp.eta;
-    double bb = 0.0;
-    for (int k = threadIdx.x; k < N; k += 1024) {
-        const double tgt = (k < m) ? I.a[k] : I.b[k - m];
-        const double rh = eta * (tgt - dg[k]);
-        bv[k] = rh;
-        x[k] = 0.0;
-        bb += rh * rh;
-        if (k >= m) p[k] = rh / dg[k];
-    }
-    bb = block_sum<1024>(bb, sh);
-    const double bn = sqrt(bb);
-    spmv_part<IX, VT>(I, m, I.rowbin, sbo, I.rowptr, I.colptr, p, Ap);
-    __syncthreads();
-    double rr = 0.0, rz = 0.0;
-    for (int k = threadIdx.x; k < m; k += 1024) {
-        const double rk = bv[k] - Ap[k];
-        res[k] = rk;
-        const double zk = rk / dg[k];
-        p[k] = zk;
-        rr += rk * rk;
-        rz += rk * zk;
-    }
-    block_sum2<1024>(rr, rz, sh);
-    int it = 0;
-    if (bn > 0.0 && sqrt(rr) > kp.cg_rtol * bn) {
-        while (it < kp.cg_max) {
-            __syncthreads();
-            spmv_part<IX, VT>(I, m, I.rowbin, sbo + NBIN, I.rowptr, I.colptr, p, Ap);
-            __syncthreads();
-            for (int k = m + threadIdx.x; k < N; k += 1024) p[k] = Ap[k] / dg[k];
-            __syncthreads();
-            spmv_part<IX, VT>(I, m, I.rowbin, sbo, I.rowptr, I.colptr, p, Ap);
-            __syncthreads();
-            double pq = 0.0;
-            for (int k = threadIdx.x; k < m; k += 1024) {
-                const double q = dg[k] * p[k] - Ap[k];
-                Ap[k] = q;
-                pq += p[k] * q;
-            }
-            pq = block_sum<1024>(pq, sh);
-            if (!(pq > 0.0)) break;
-            const double al = rz / pq;
-            double rz2 = 0.0;
-            rr = 0.0;
-            for (int k = threadIdx.x; k < m; k += 1024) {
-                x[k] += al * p[k];
-                const double rk = res[k] - al * Ap[k];
-                res[k] = rk;
-                rr += rk * rk;
-                rz2 += rk * (rk / dg[k]);
-            }
-            block_sum2<1024>(rr, rz2, sh);
-            ++it;
-            if (sqrt(rr) <= kp.cg_rtol * bn) break;
-            const double be = rz2 / rz;
-            rz = rz2;
-            for (int k = threadIdx.x; k < m; k += 1024) p[k] = res[k] / dg[k] + be * p[k];
-        }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < m; k += 1024) p[k] = x[k];
-    __syncthreads();
-    spmv_part<IX, VT>(I, m, I.rowbin, sbo + NBIN, I.rowptr, I.colptr, p, Ap);
-    __syncthreads();
-    double gd = 0.0, dab = 0.0, fa = 0.0;
-    for (int k = threadIdx.x; k < N; k += 1024) {
-        if (k >= m) x[k] = (bv[k] - Ap[k]) / dg[k];
-        const double tgt = (k < m) ? I.a[k] : I.b[k - m];
-        gd += (tgt - dg[k]) * x[k];
-        dab += tgt * x[k];
-        fa += fabs(tgt * x[k]);
-    }
-    gd = block_sum<1024>(gd, sh);
-    dab = block_sum<1024>(dab, sh);
-    fa = block_sum<1024>(fa, sh);
-    if (threadIdx.x == 0) ls_setup(ctrl[b], it, gd, dab, fa, kp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1354,10 +1322,11 @@ template <class IX, class VT>
 __device__ __forceinline__ void spmv_range(const DevInst& I, int m, const int* bins, const int* bo, int lo, int hi,
                                            const double* __restrict__ pv, double* __restrict__ out,
                                            const double* __restrict__ rdiv) {
+    const SpArrays<IX, VT> A(I);
 #define WB_(G, g)                                                                                              \
     {                                                                                                          \
         const int a_ = max(lo, bo[g]), b_ = min(hi, bo[g + 1]);                                               \
-        if (a_ < b_) spmv_bin<G, IX, VT>(I, m, bins, a_, b_, I.rowptr, I.colptr, pv, out, rdiv);              \
+        if (a_ < b_) spmv_bin<G, 2, IX, VT>(A, m, bins, a_, b_, I.rowptr, I.colptr, pv, out, rdiv);              \
     }
     WB_(1, 0) WB_(2, 1) WB_(4, 2) WB_(8, 3) WB_(16, 4) WB_(32, 5)
 #undef WB_
@@ -1930,7 +1899,6 @@ __global__ __launch_bounds__(256) void k_init_ck(const DevInst* __restrict__ ins
 // come from the same operand loads (partial over the lane's k slots, summed
 // over the 4 lanes sharing l%16).  Rounding of nearly equal points can make
 // the expansion slightly negative; it is clamped at 0.
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_points_cost(const double* __restrict__ x, const double* __restrict__ y,
                                                      int m, int n, int d, double* __restrict__ C) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -2230,6 +2198,9 @@ void launch_sparsify(const LaunchCtx& L, int src) {
     }
 }
 
+// batches with m + n <= WCG_MAX_N for every instance (the others take the
+// wide CG); every vector of an instance fits the kernel's LDS arrays
+static_assert(WCG_MAX_N <= 4 * 1024, "k_pcg_lds holds at most 4096 vector entries");
 template <class IX, class VT>
 static void launch_pcg_t(const LaunchCtx& L) {
     const int ept = (L.max_mn + 1023) / 1024;
@@ -2238,12 +2209,8 @@ static void launch_pcg_t(const LaunchCtx& L) {
         hipLaunchKernelGGL((k_pcg_lds<1, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else if (ept <= 2)
         hipLaunchKernelGGL((k_pcg_lds<2, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
-    else if (ept <= 4)
-        hipLaunchKernelGGL((k_pcg_lds<4, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
-    else if (ept <= 8)
-        hipLaunchKernelGGL((k_pcg_lds<8, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else
-        hipLaunchKernelGGL((k_pcg<IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<4, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
 template <class IX, class VT>
