@@ -87,7 +87,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-launch HIP events")
-    ap.add_argument("--hvp-switch", type=int, default=25,
+    ap.add_argument("--hvp-switch", type=int, default=15,
                     help="Hessian products of the Newton CG: matrix-free (full Hessian) in the outer iterations "
                          "k < this, sparsified (CSR) after; 0 = sparsified throughout")
     ap.add_argument("--lanes", type=int, default=3,
