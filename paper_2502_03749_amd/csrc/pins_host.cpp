@@ -105,7 +105,7 @@ InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, 
     // kept entries plus up to 3 pads per row of S or S^T, rounded to quads
     q.cap = (int)(((nnz_capacity(m, n, p.budget) + 3L * std::max(m, n)) + 3) & ~3L);
     const long tiles = (long)q.nrb * q.ncb;
-    const long nblk = std::max({tiles, (long)(m + 3) / 4, (long)(N + 255) / 256});
+    const long nblk = std::max({tiles, (long)(m + 3) / 4, (long)(N + 31) / 32});
     q.loga = cv.take(m * D);
     q.logb = cv.take(n * D);
     q.F = cv.take(m * D);

@@ -633,34 +633,40 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
     tile_level_totals(hw, nlev, I.hist);
 }
 
-// Gradient merge: r = Xt e, c = Xt^T e into rc; the last block tests
-// convergence (||a-r||_1 + ||b-c||_1 <= tol, or the Newton cap) and picks the
-// Sparsify level (densest level within the budget).
+// Gradient merge: r = Xt e, c = Xt^T e into rc.  32 entries of (r, c) per
+// block with 8 lanes each: lane s sums the partials s, s + 8, ..., and the 8
+// sums of an entry are combined in lane order; the block's part of
+// ||a - r||_1 + ||b - c||_1 goes to blk2 for k_grad_decide.
 __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
                                                     KP kp) {
     const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
-    const int nb = (N + 255) / 256;
-    if ((int)blockIdx.x >= nb) return;
-    __shared__ double sh[4];
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    double dev = 0.0;
+    if ((int)blockIdx.x * 32 >= N) return;
+    const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int k = blockIdx.x * 32 + c;
+    __shared__ double ss[8][32];
+    double s = 0.0;
     if (k < m) {
-        double s = 0.0;
-        for (int cb = 0; cb < I.ncb; ++cb) s += I.part2[(long)cb * m + k];
-        I.rc[k] = s;
-        dev = fabs(I.a[k] - s);
+        for (int cb = sl; cb < I.ncb; cb += 8) s += I.part2[(long)cb * m + k];
     } else if (k < N) {
         const int j = k - m;
-        double s = 0.0;
-        for (int rb = 0; rb < I.nrb; ++rb) s += I.part[(long)rb * n + j];
-        I.rc[k] = s;
-        dev = fabs(I.b[j] - s);
+        for (int rb = sl; rb < I.nrb; rb += 8) s += I.part[(long)rb * n + j];
     }
-    const double bs = block_sum<256>(dev, sh);
-    if (threadIdx.x == 0) I.blk2[blockIdx.x] = bs;
+    ss[sl][c] = s;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double dev = 0.0;
+        if (k < N) {
+            double t = 0.0;
+            for (int q = 0; q < 8; ++q) t += ss[q][c];
+            I.rc[k] = t;
+            dev = fabs(((k < m) ? I.a[k] : I.b[k - m]) - t);
+        }
+        for (int o = 16; o > 0; o >>= 1) dev += __shfl_xor(dev, o);  // lanes 0..31 of wave 0
+        if (threadIdx.x == 0) I.blk2[blockIdx.x] = dev;
+    }
 }
 
 // Newton control: residual, convergence, Sparsify level (one block per instance).
@@ -671,7 +677,7 @@ __global__ __launch_bounds__(256) void k_grad_decide(const DevInst* __restrict__
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n;
     __shared__ double sh[4];
-    const double res = block_sum_array<256>(I.blk2, (m + n + 255) / 256, sh);
+    const double res = block_sum_array<256>(I.blk2, (m + n + 31) / 32, sh);
     Ctrl& S = ctrl[b];
     __shared__ int s_go;
     if (threadIdx.x == 0) {
@@ -778,6 +784,26 @@ __global__ __launch_bounds__(256) void k_count(const DevInst* __restrict__ insts
     }
 }
 
+// Exclusive prefix sums in place over len counts at p[0], p[stride], ...;
+// returns the total.  Counts are loaded 16 at a time before any is stored, so
+// the loads of a chunk are in flight together.
+__device__ __forceinline__ int prefix_in_place(int* __restrict__ p, long stride, int len) {
+    constexpr int CH = 16;
+    int c = 0;
+    for (int q0 = 0; q0 < len; q0 += CH) {
+        int v[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) v[u] = (q0 + u < len) ? p[(long)(q0 + u) * stride] : 0;
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (q0 + u < len) {
+                p[(long)(q0 + u) * stride] = c;
+                c += v[u];
+            }
+    }
+    return c;
+}
+
 // Per row of M (CSR row, then CSC column): the kept count over the column
 // (row) blocks, and those per-block counts turned into exclusive prefix sums in
 // place (the fill reads them as the entry index of its first kept entry).
@@ -789,23 +815,8 @@ __global__ __launch_bounds__(256) void k_scan_totals(const DevInst* __restrict__
     const int m = I.m, n = I.n;
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= m + n) return;
-    int c = 0;
-    if (k < m) {
-        int* __restrict__ cr = I.cntr + (long)k * I.ncb;
-        for (int q = 0; q < I.ncb; ++q) {
-            const int v = cr[q];
-            cr[q] = c;
-            c += v;
-        }
-    } else {
-        int* __restrict__ cc = I.cntc + (k - m);
-        for (int q = 0; q < I.nrb; ++q) {
-            const int v = cc[(long)q * n];
-            cc[(long)q * n] = c;
-            c += v;
-        }
-    }
-    I.rowbin[k] = c;
+    I.rowbin[k] = (k < m) ? prefix_in_place(I.cntr + (long)k * I.ncb, 1, I.ncb)
+                          : prefix_in_place(I.cntc + (k - m), n, I.nrb);
 }
 
 __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
@@ -840,39 +851,69 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
         }
     }
     // rows of M grouped by quad count for the CG's product, in row order
-    // within each bin (ballot prefix per wave, wave totals in LDS); the
+    // within each bin: a counting pass (per-wave ballots, wave totals in LDS),
+    // the bin offsets, then a placing pass over 1024-row chunks in order; the
     // pointers written above are visible to the whole block after the barrier
     __syncthreads();
+    constexpr int NG2 = 2 * NBIN;
+    __shared__ int wcnt[16][NG2];
+    __shared__ int boff[NG2];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
-    int off = 0;
-    for (int g = 0; g < 2 * NBIN; ++g) {
-        const int part = g / NBIN, t = g - part * NBIN;
-        if (threadIdx.x == 0) ctrl[b].binoff[g] = off;
-        int carry = 0;
-        for (int base = part ? m : 0; base < (part ? N : m); base += 1024) {
+    auto bin_of = [&](int k) {
+        const int nq = (k < m) ? (I.rowptr[k + 1] - I.rowptr[k]) >> 2 : (I.colptr[k - m + 1] - I.colptr[k - m]) >> 2;
+        const int t = nq <= 1 ? 0 : nq <= 2 ? 1 : nq <= 4 ? 2 : nq <= 8 ? 3 : nq <= 16 ? 4 : 5;
+        return (k < m ? 0 : NBIN) + t;
+    };
+    {
+        int mine[NG2];
+#pragma unroll
+        for (int g = 0; g < NG2; ++g) mine[g] = 0;
+        for (int base = 0; base < N; base += 1024) {
             const int k = base + threadIdx.x;
-            bool f = false;
-            if (k < (part ? N : m)) {
-                const int nq = (k < m) ? (I.rowptr[k + 1] - I.rowptr[k]) >> 2 : (I.colptr[k - m + 1] - I.colptr[k - m]) >> 2;
-                const int bin = nq <= 1 ? 0 : nq <= 2 ? 1 : nq <= 4 ? 2 : nq <= 8 ? 3 : nq <= 16 ? 4 : 5;
-                f = bin == t;
-            }
-            const unsigned long long bal = __ballot(f);
-            __syncthreads();
-            if (lane == 0) ish[w] = (int)__popcll(bal);
-            __syncthreads();
-            int woff = 0, tot = 0;
-            for (int q = 0; q < 16; ++q) {
-                if (q < w) woff += ish[q];
-                tot += ish[q];
-            }
-            if (f) I.rowbin[off + carry + woff + (int)__popcll(bal & below)] = k;
-            carry += tot;
+            const int gk = k < N ? bin_of(k) : -1;
+#pragma unroll
+            for (int g = 0; g < NG2; ++g) mine[g] += (int)__popcll(__ballot(gk == g));
         }
-        off += carry;
+        if (lane == 0)
+#pragma unroll
+            for (int g = 0; g < NG2; ++g) wcnt[w][g] = mine[g];
     }
-    if (threadIdx.x == 0) ctrl[b].binoff[2 * NBIN] = off;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int g = 0; g < NG2; ++g) {
+            boff[g] = off;
+            ctrl[b].binoff[g] = off;
+            for (int q = 0; q < 16; ++q) off += wcnt[q][g];
+        }
+        ctrl[b].binoff[NG2] = off;
+    }
+    __syncthreads();
+    for (int base = 0; base < N; base += 1024) {
+        const int k = base + threadIdx.x;
+        const int gk = k < N ? bin_of(k) : -1;
+        unsigned long long myb = 0ull;
+#pragma unroll
+        for (int g = 0; g < NG2; ++g) {
+            const unsigned long long bal = __ballot(gk == g);
+            if (gk == g) myb = bal;
+            if (lane == 0) wcnt[w][g] = (int)__popcll(bal);
+        }
+        __syncthreads();
+        if (gk >= 0) {
+            int woff = 0;
+            for (int q = 0; q < w; ++q) woff += wcnt[q][gk];
+            I.rowbin[boff[gk] + woff + (int)__popcll(myb & below)] = k;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < NG2) {
+            int tot = 0;
+            for (int q = 0; q < 16; ++q) tot += wcnt[q][threadIdx.x];
+            boff[threadIdx.x] += tot;
+        }
+        __syncthreads();
+    }
 }
 
 // Index storage of S and S^T.  uint16: the column (of S) or row (of S^T)
@@ -2171,7 +2212,7 @@ void launch_grad(const LaunchCtx& L, int src) {
 }
 
 void launch_grad_merge(const LaunchCtx& L) {
-    hipLaunchKernelGGL(k_grad_merge, g2((L.max_mn + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
+    hipLaunchKernelGGL(k_grad_merge, g2((L.max_mn + 31) / 32, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
                        L.kp);
     hipLaunchKernelGGL(k_grad_decide, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
