@@ -105,7 +105,9 @@ InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, 
     // kept entries plus up to 3 pads per row of S or S^T, rounded to quads
     q.cap = (int)(((nnz_capacity(m, n, p.budget) + 3L * std::max(m, n)) + 3) & ~3L);
     const long tiles = (long)q.nrb * q.ncb;
-    const long nblk = std::max({tiles, (long)(m + 3) / 4, (long)(N + 31) / 32});
+    // per-block parts: tiles, 4-row sweep groups, 32-entry merge blocks, and
+    // (||res||^2, <res, z>) per wide-CG vector block
+    const long nblk = std::max({tiles, (long)(m + 3) / 4, (long)(N + 31) / 32, 2L * ((m + WCG_VROWS - 1) / WCG_VROWS)});
     q.loga = cv.take(m * D);
     q.logb = cv.take(n * D);
     q.F = cv.take(m * D);
@@ -535,12 +537,14 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
                 // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
                 const int hsrc = mf ? src : -1;
                 run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_begin(L, hsrc); });
+                int it = 0;  // every instance of the batch starts its CG here
                 for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
                     const Ctrl* hc = readback(ctx, st, d_ctrl, count);
                     bool on = false;
                     for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
                     if (!on) break;
-                    for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc); });
+                    for (int c = 0; c < chunk; ++c, ++it)
+                        run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc, it); });
                 }
                 run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_end(L, hsrc); });
             }

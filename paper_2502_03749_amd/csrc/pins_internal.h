@@ -25,6 +25,7 @@ constexpr int TILE_RMAX = 16;  // maximum rows per tile
 constexpr int NBIN = 6;        // CG row bins: <= 1, 2, 4, 8, 16 and more quads
 constexpr int WCG_ROWS = 128;  // wide CG: rows of one half of M per block
 constexpr int WCG_MAX_N = 4096;  // instances with m+n above this take the wide CG
+constexpr int WCG_VROWS = 1024;  // wide CG: rows per block of the vector steps
 
 enum Phase : int { PH_DONE = 0, PH_WARM = 1, PH_NEWTON = 2, PH_FALLBACK = 3 };
 enum LsState : int { LS_PENDING = 0, LS_ACCEPTED = 1, LS_FAILED = 2 };
@@ -94,7 +95,7 @@ struct Ctrl {
     double work[8];  // matrix entries visited per pass kind (W_* below); W_CG: stored entries read by CG
     int binoff[16];  // rowbin offsets: NBIN bins of rows of S, then NBIN bins of rows of S^T; [2 NBIN] = m+n
     int cg_it, cg_on;        // wide CG (many blocks per instance): iterations, still iterating
-    double cg_rz, cg_bnorm;  // wide CG: <res, z>, ||rhs||
+    double cg_rzs[2], cg_bnorm;  // wide CG: <res, z> of iteration t in cg_rzs[t & 1]; ||rhs||
 };
 
 // pass kinds counted in Ctrl::work

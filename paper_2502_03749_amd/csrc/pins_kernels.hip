@@ -1107,11 +1107,11 @@ __device__ __forceinline__ double quad_dot(const XV& x, const WV& w, const doubl
 
 // Products of the rows bins[lo..hi) of M's off-diagonal part: G lanes per
 // row, lane lg taking the row's quads lg, lg + G, ..., U quads in flight (the
-// loads of a step are issued together, also for the lane's last < U quads).
-template <int G, int U, class IX, class VT>
+// loads of a step are issued together, also for the lane's last < U quads);
+// fin(k, (M p)_k) is called once per row.
+template <int G, int U, class IX, class VT, class Fin>
 __device__ __forceinline__ void spmv_bin(const SpArrays<IX, VT>& A, int m, const int* bins, int lo, int hi,
-                                         const int* rp, const int* cp, const double* __restrict__ pv,
-                                         double* __restrict__ out, const double* __restrict__ rdiv = nullptr) {
+                                         const int* rp, const int* cp, const double* __restrict__ pv, Fin fin) {
     typedef typename QuadIx<IX>::T XV;
     typedef typename QuadVal<VT>::T WV;
     constexpr int NG = 1024 / G;
@@ -1156,7 +1156,7 @@ __device__ __forceinline__ void spmv_bin(const SpArrays<IX, VT>& A, int m, const
 #pragma unroll
         for (int u = 1; u < U; ++u) tot += s[u];
         const double sum = group_sum<G>(tot);
-        if (lg == 0) out[k] = rdiv ? sum / rdiv[k] : sum;
+        if (lg == 0) fin(k, sum);
     }
 }
 
@@ -1175,12 +1175,13 @@ template <class IX, class VT>
 __device__ __forceinline__ void spmv_part(const SpArrays<IX, VT>& A, int m, const int* bins, const int* bo,
                                           const int* rp, const int* cp, const double* __restrict__ pv,
                                           double* __restrict__ out) {
-    spmv_bin<1, CG_QUADS, IX, VT>(A, m, bins, bo[0], bo[1], rp, cp, pv, out);
-    spmv_bin<cg_lanes(2), CG_QUADS, IX, VT>(A, m, bins, bo[1], bo[2], rp, cp, pv, out);
-    spmv_bin<cg_lanes(4), CG_QUADS, IX, VT>(A, m, bins, bo[2], bo[3], rp, cp, pv, out);
-    spmv_bin<cg_lanes(8), CG_QUADS, IX, VT>(A, m, bins, bo[3], bo[4], rp, cp, pv, out);
-    spmv_bin<cg_lanes(16), CG_QUADS, IX, VT>(A, m, bins, bo[4], bo[5], rp, cp, pv, out);
-    spmv_bin<cg_lanes(32), CG_QUADS, IX, VT>(A, m, bins, bo[5], bo[6], rp, cp, pv, out);
+    auto fin = [out](int k, double v) { out[k] = v; };
+    spmv_bin<1, CG_QUADS, IX, VT>(A, m, bins, bo[0], bo[1], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(2), CG_QUADS, IX, VT>(A, m, bins, bo[1], bo[2], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(4), CG_QUADS, IX, VT>(A, m, bins, bo[2], bo[3], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(8), CG_QUADS, IX, VT>(A, m, bins, bo[3], bo[4], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(16), CG_QUADS, IX, VT>(A, m, bins, bo[4], bo[5], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(32), CG_QUADS, IX, VT>(A, m, bins, bo[5], bo[6], rp, cp, pv, fin);
 }
 
 __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp,
@@ -1350,8 +1351,9 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
 // ---------------------------------------------------------------------------
 // Wide CG for instances with m + n > WCG_MAX_N: the same Schur-complement CG,
 // with each product spread over many blocks (WCG_ROWS rows of one half of M
-// per block, over the binned row list) and the vector work in one block per
-// instance.  Kernel boundaries order the memory (no device fences); the host
+// per block, over the binned row list) and the vector steps over blocks of
+// WCG_VROWS rows, their dot products merged in fixed order from per-block
+// parts.  Kernel boundaries order the memory (no device fences); the host
 // runs iterations in chunks between readbacks, and an instance that has
 // stopped (cg_on = 0) makes every later launch return at once.
 // Vectors (global): x = I.d, res = cgw[0..m), bv = cgw[N..2N) (rhs),
@@ -1359,15 +1361,14 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
 // q = cgw[3N..4N).
 // ---------------------------------------------------------------------------
 // One half of M's product for the blocks of rows [lo, hi) of the part's list.
-template <class IX, class VT>
+template <class IX, class VT, class Fin>
 __device__ __forceinline__ void spmv_range(const DevInst& I, int m, const int* bins, const int* bo, int lo, int hi,
-                                           const double* __restrict__ pv, double* __restrict__ out,
-                                           const double* __restrict__ rdiv) {
+                                           const double* __restrict__ pv, Fin fin) {
     const SpArrays<IX, VT> A(I);
 #define WB_(G, g)                                                                                              \
     {                                                                                                          \
         const int a_ = max(lo, bo[g]), b_ = min(hi, bo[g + 1]);                                               \
-        if (a_ < b_) spmv_bin<G, 2, IX, VT>(A, m, bins, a_, b_, I.rowptr, I.colptr, pv, out, rdiv);              \
+        if (a_ < b_) spmv_bin<G, 2, IX, VT>(A, m, bins, a_, b_, I.rowptr, I.colptr, pv, fin);                    \
     }
     WB_(1, 0) WB_(2, 1) WB_(4, 2) WB_(8, 3) WB_(16, 4) WB_(32, 5)
 #undef WB_
@@ -1401,8 +1402,11 @@ __global__ __launch_bounds__(1024) void k_wcg_begin(const DevInst* __restrict__ 
     }
 }
 
-// rows: q[i] = (S p_cols)_i; columns: p[m + j] = (S^T p_rows)_j / c_j, or
-// q[m + j] = (S^T x)_j when `final` (after the iterations)
+// columns: p[m + j] = (S^T p_rows)_j / c_j, or q[m + j] = (S^T x)_j when
+// `final` (after the iterations); rows: q[i] = (S p_cols)_i for the start
+// (`final` = 2), or in the iterations q[i] = r_i p_i - (S p_cols)_i and the
+// block's part of <p, q> in blk[block] (blocks of WCG_ROWS rows of the binned
+// list, in order)
 template <class IX, class VT>
 __global__ __launch_bounds__(1024) void k_wcg_half(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
                                                    int cols, int final) {
@@ -1416,12 +1420,25 @@ __global__ __launch_bounds__(1024) void k_wcg_half(const DevInst* __restrict__ i
     if (lo >= hi) return;
     double* __restrict__ p = I.cgw + 2 * N;
     double* __restrict__ q = I.cgw + 3 * N;
-    if (!cols)
-        spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, p, q, nullptr);
-    else if (final)
-        spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, I.d, q, nullptr);
-    else
-        spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, p, p, I.rc);
+    const double* __restrict__ dg = I.rc;
+    if (cols) {
+        if (final)
+            spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, I.d, [q](int k, double v) { q[k] = v; });
+        else
+            spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, p, [p, dg](int k, double v) { p[k] = v / dg[k]; });
+    } else if (final) {
+        spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, p, [q](int k, double v) { q[k] = v; });
+    } else {
+        __shared__ double sh[32];
+        double pq = 0.0;
+        spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, p, [&](int k, double v) {
+            const double w = dg[k] * p[k] - v;
+            q[k] = w;
+            pq += p[k] * w;
+        });
+        pq = block_sum<1024>(pq, sh);
+        if (threadIdx.x == 0) I.blk[blockIdx.x] = pq;
+    }
 }
 
 // after S D_c^-1 b_2: residual, preconditioned residual, first direction
@@ -1447,58 +1464,84 @@ __global__ __launch_bounds__(1024) void k_wcg_start(const DevInst* __restrict__ 
     block_sum2<1024>(rr, rz, sh);
     if (threadIdx.x == 0) {
         Ctrl& S = ctrl[b];
-        S.cg_rz = rz;
+        S.cg_rzs[0] = rz;
         if (!(S.cg_bnorm > 0.0) || sqrt(rr) <= kp.cg_rtol * S.cg_bnorm || kp.cg_max <= 0) S.cg_on = 0;
     }
 }
 
-// one iteration's vector work: q = D_r p - S D_c^-1 S^T p, step, residual, stop test, next direction
-__global__ __launch_bounds__(1024) void k_wcg_step(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
-    const int b = blockIdx.x;
+// One iteration's vector work, over blocks of WCG_VROWS rows (the products
+// left q = D_r p - S D_c^-1 S^T p and the parts of <p, q> in blk, npq of them
+// per instance, pq_rows rows each).  t is the iteration (the host's launch
+// count; every instance of the batch starts its CG together): <res, z> of
+// iteration t is cg_rzs[t & 1], so no block reads a scalar that another block
+// of the same launch writes.  Each block sums the same partials in the same
+// order, so every block takes the same step.
+// k_wcg_alpha: step length, x and res, the parts of ||res||^2 and <res, z> in blk2.
+__global__ __launch_bounds__(256) void k_wcg_alpha(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, int t,
+                                                   int pq_rows) {
+    const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON || !ctrl[b].cg_on) return;
     const DevInst& I = insts[b];
     const int m = I.m, N = m + I.n;
-    double* __restrict__ res = I.cgw;
-    double* __restrict__ p = I.cgw + 2 * N;
-    double* __restrict__ q = I.cgw + 3 * N;
-    double* __restrict__ x = I.d;
-    const double* __restrict__ dg = I.rc;
+    const int i0 = blockIdx.x * WCG_VROWS;
+    if (i0 >= m) return;
     __shared__ double sh[32];
-    __shared__ int s_go;
-    double pq = 0.0;
-    for (int i = threadIdx.x; i < m; i += 1024) {
-        const double v = dg[i] * p[i] - q[i];
-        q[i] = v;
-        pq += p[i] * v;
-    }
-    pq = block_sum<1024>(pq, sh);
+    const double pq = block_sum_array<256>(I.blk, (m + pq_rows - 1) / pq_rows, sh);
     if (!(pq > 0.0)) {
-        if (threadIdx.x == 0) ctrl[b].cg_on = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[b].cg_on = 0;  // every block sees the same pq
         return;
     }
-    const double al = ctrl[b].cg_rz / pq;
-    double rr = 0.0, rz2 = 0.0;
-    for (int i = threadIdx.x; i < m; i += 1024) {
+    const double al = ctrl[b].cg_rzs[t & 1] / pq;
+    double* __restrict__ res = I.cgw;
+    const double* __restrict__ p = I.cgw + 2 * N;
+    const double* __restrict__ q = I.cgw + 3 * N;
+    double* __restrict__ x = I.d;
+    const double* __restrict__ dg = I.rc;
+    double rr = 0.0, rz = 0.0;
+    for (int i = i0 + threadIdx.x; i < min(m, i0 + WCG_VROWS); i += 256) {
         x[i] += al * p[i];
         const double r = res[i] - al * q[i];
         res[i] = r;
         rr += r * r;
-        rz2 += r * (r / dg[i]);
+        rz += r * (r / dg[i]);
     }
-    block_sum2<1024>(rr, rz2, sh);
+    block_sum2<256>(rr, rz, sh);
     if (threadIdx.x == 0) {
-        Ctrl& S = ctrl[b];
-        S.cg_it += 1;
-        const int go = !(sqrt(rr) <= kp.cg_rtol * S.cg_bnorm) && S.cg_it < kp.cg_max;
-        s_go = go;
-        if (!go) S.cg_on = 0;
+        I.blk2[2 * blockIdx.x] = rr;
+        I.blk2[2 * blockIdx.x + 1] = rz;
     }
-    __syncthreads();
-    if (!s_go) return;
-    const double be = rz2 / ctrl[b].cg_rz;
-    __syncthreads();  // every thread has read cg_rz before it changes
-    if (threadIdx.x == 0) ctrl[b].cg_rz = rz2;
-    for (int i = threadIdx.x; i < m; i += 1024) p[i] = res[i] / dg[i] + be * p[i];
+}
+
+// k_wcg_beta: stop test and the next direction p = D_r^-1 res + beta p.
+__global__ __launch_bounds__(256) void k_wcg_beta(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                  int t) {
+    const int b = blockIdx.y;
+    if (ctrl[b].phase != PH_NEWTON || !ctrl[b].cg_on) return;
+    const DevInst& I = insts[b];
+    const int m = I.m, N = m + I.n;
+    const int i0 = blockIdx.x * WCG_VROWS;
+    if (i0 >= m) return;
+    const int nv = (m + WCG_VROWS - 1) / WCG_VROWS;
+    double rr = 0.0, rz2 = 0.0;
+    for (int c = 0; c < nv; ++c) {
+        rr += I.blk2[2 * c];
+        rz2 += I.blk2[2 * c + 1];
+    }
+    const double rz = ctrl[b].cg_rzs[t & 1];
+    const int go = !(sqrt(rr) <= kp.cg_rtol * ctrl[b].cg_bnorm) && t + 1 < kp.cg_max;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl[b].cg_it = t + 1;
+        if (go)
+            ctrl[b].cg_rzs[(t + 1) & 1] = rz2;
+        else
+            ctrl[b].cg_on = 0;  // read by later launches only (no block of this one needs it)
+    }
+    if (!go) return;
+    const double be = rz2 / rz;
+    const double* __restrict__ res = I.cgw;
+    double* __restrict__ p = I.cgw + 2 * N;
+    const double* __restrict__ dg = I.rc;
+    for (int i = i0 + threadIdx.x; i < min(m, i0 + WCG_VROWS); i += 256) p[i] = res[i] / dg[i] + be * p[i];
 }
 
 // Matrix-free products with the full Hessian (params.hvp = 1): the coupling
@@ -1554,7 +1597,9 @@ __global__ __launch_bounds__(256) void k_mf_tile(const DevInst* __restrict__ ins
 }
 
 // cols = 1: t_j = sum over row blocks -> p[m + j] = t_j / c_j, or q[m + j] = t_j
-// when `final`; cols = 0: q_i = sum over column blocks.
+// when `final`; cols = 0: t_i = sum over column blocks -> q_i = t_i for the
+// start (`final` = 2), or in the iterations q_i = r_i p_i - t_i and the
+// block's part of <p, q> in blk[block].
 __global__ __launch_bounds__(256) void k_mf_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, int cols,
                                                   int final) {
     const int b = blockIdx.y;
@@ -1572,11 +1617,24 @@ __global__ __launch_bounds__(256) void k_mf_merge(const DevInst* __restrict__ in
             q[m + k] = t;
         else
             p[m + k] = t / I.rc[m + k];
-    } else {
+    } else if (final) {
         if (k >= m) return;
         double t = 0.0;
         for (int cb = 0; cb < I.ncb; ++cb) t += I.part2[(long)cb * m + k];
         q[k] = t;
+    } else {
+        if ((int)blockIdx.x * 256 >= m) return;  // whole block: no partial beyond this instance's rows
+        __shared__ double sh[32];
+        double pq = 0.0;
+        if (k < m) {
+            double t = 0.0;
+            for (int cb = 0; cb < I.ncb; ++cb) t += I.part2[(long)cb * m + k];
+            const double w = I.rc[k] * p[k] - t;
+            q[k] = w;
+            pq = p[k] * w;
+        }
+        pq = block_sum<256>(pq, sh);
+        if (threadIdx.x == 0) I.blk[blockIdx.x] = pq;
     }
 }
 
@@ -2287,14 +2345,17 @@ static void launch_half(const LaunchCtx& L, int src, int cols, int final) {
 
 void launch_wcg_begin(const LaunchCtx& L, int src) {
     hipLaunchKernelGGL(k_wcg_begin, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, src >= 0 ? 1 : 0);
-    launch_half(L, src, 0, 0);
+    launch_half(L, src, 0, 2);
     hipLaunchKernelGGL(k_wcg_start, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
-void launch_wcg_iter(const LaunchCtx& L, int src) {
+void launch_wcg_iter(const LaunchCtx& L, int src, int t) {
     launch_half(L, src, 1, 0);
     launch_half(L, src, 0, 0);
-    hipLaunchKernelGGL(k_wcg_step, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+    const dim3 g = g2((L.max_m + WCG_VROWS - 1) / WCG_VROWS, L.count);
+    const int pq_rows = src < 0 ? WCG_ROWS : 256;  // rows per part of <p, q> (k_wcg_half or k_mf_merge blocks)
+    hipLaunchKernelGGL(k_wcg_alpha, g, dim3(256), 0, L.stream, L.insts, L.ctrl, t, pq_rows);
+    hipLaunchKernelGGL(k_wcg_beta, g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, t);
 }
 
 void launch_wcg_end(const LaunchCtx& L, int src) {
