@@ -58,6 +58,18 @@ def test_workspace_bytes_rejects_bad_input():
         P.workspace_bytes([dict(kind=P.COST_DENSE, m=10, n=10)], P.params(eta=-1.0))
 
 
+def test_workspace_bytes_size_limits():
+    # m*n < 2^31 and m+n < 2^28 (the CG stores byte offsets of vector entries
+    # in int32); both are refused as unsupported, not as invalid
+    with pytest.raises(B.PinsError) as e:
+        P.workspace_bytes([dict(kind=P.COST_DENSE, m=2, n=(1 << 30) + 1)], P.params())
+    assert e.value.code == B.PINS_EUNSUPPORTED
+    with pytest.raises(B.PinsError) as e:
+        P.workspace_bytes([dict(kind=P.COST_DENSE, m=1, n=(1 << 28) - 1)], P.params())
+    assert e.value.code == B.PINS_EUNSUPPORTED
+    P.workspace_bytes([dict(kind=P.COST_DENSE, m=1, n=(1 << 28) - 2)], P.params(max_outer=1))
+
+
 def test_create_without_gpu_reports_device_error():
     import torch
 
