@@ -59,8 +59,10 @@ typedef enum {
 typedef enum {
     PINS_FP64 = 0, /* every step in double precision */
     PINS_MIXED = 1 /* Sinkhorn warm-up sweeps evaluate exp and accumulate the
-                      log-sum-exp in float (exponent formed in double);
-                      Newton, CG, line search, potentials and outputs stay double */
+                      log-sum-exp in float (exponent formed in double); the CG
+                      stores the kept entries of the sparsified Hessian in
+                      float; gradients, CG vectors and sums, line search,
+                      potentials and outputs stay double */
 } pins_precision;
 
 typedef enum {
