@@ -1109,12 +1109,12 @@ __device__ __forceinline__ double quad_dot(const XV& x, const WV& w, const doubl
 // row, lane lg taking the row's quads lg, lg + G, ..., U quads in flight (the
 // loads of a step are issued together, also for the lane's last < U quads);
 // fin(k, (M p)_k) is called once per row.
-template <int G, int U, class IX, class VT, class Fin>
+template <int G, int U, int NT, class IX, class VT, class Fin>
 __device__ __forceinline__ void spmv_bin(const SpArrays<IX, VT>& A, int m, const int* bins, int lo, int hi,
                                          const int* rp, const int* cp, const double* __restrict__ pv, Fin fin) {
     typedef typename QuadIx<IX>::T XV;
     typedef typename QuadVal<VT>::T WV;
-    constexpr int NG = 1024 / G;
+    constexpr int NG = NT / G;
     const int g = threadIdx.x / G, lg = threadIdx.x % G;
     for (int t = lo + g; t < hi; t += NG) {
         const int k = bins[t];
@@ -1176,12 +1176,12 @@ __device__ __forceinline__ void spmv_part(const SpArrays<IX, VT>& A, int m, cons
                                           const int* rp, const int* cp, const double* __restrict__ pv,
                                           double* __restrict__ out) {
     auto fin = [out](int k, double v) { out[k] = v; };
-    spmv_bin<1, CG_QUADS, IX, VT>(A, m, bins, bo[0], bo[1], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(2), CG_QUADS, IX, VT>(A, m, bins, bo[1], bo[2], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(4), CG_QUADS, IX, VT>(A, m, bins, bo[2], bo[3], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(8), CG_QUADS, IX, VT>(A, m, bins, bo[3], bo[4], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(16), CG_QUADS, IX, VT>(A, m, bins, bo[4], bo[5], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(32), CG_QUADS, IX, VT>(A, m, bins, bo[5], bo[6], rp, cp, pv, fin);
+    spmv_bin<1, CG_QUADS, 1024, IX, VT>(A, m, bins, bo[0], bo[1], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(2), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[1], bo[2], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(4), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[2], bo[3], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(8), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[3], bo[4], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(16), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[4], bo[5], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(32), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[5], bo[6], rp, cp, pv, fin);
 }
 
 __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp,
@@ -1368,7 +1368,7 @@ __device__ __forceinline__ void spmv_range(const DevInst& I, int m, const int* b
 #define WB_(G, g)                                                                                              \
     {                                                                                                          \
         const int a_ = max(lo, bo[g]), b_ = min(hi, bo[g + 1]);                                               \
-        if (a_ < b_) spmv_bin<G, 2, IX, VT>(A, m, bins, a_, b_, I.rowptr, I.colptr, pv, fin);                    \
+        if (a_ < b_) spmv_bin<cg_lanes(G), 3, WCG_NT, IX, VT>(A, m, bins, a_, b_, I.rowptr, I.colptr, pv, fin);  \
     }
     WB_(1, 0) WB_(2, 1) WB_(4, 2) WB_(8, 3) WB_(16, 4) WB_(32, 5)
 #undef WB_
@@ -1408,7 +1408,7 @@ __global__ __launch_bounds__(1024) void k_wcg_begin(const DevInst* __restrict__ 
 // block's part of <p, q> in blk[block] (blocks of WCG_ROWS rows of the binned
 // list, in order)
 template <class IX, class VT>
-__global__ __launch_bounds__(1024) void k_wcg_half(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+__global__ __launch_bounds__(WCG_NT) void k_wcg_half(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
                                                    int cols, int final) {
     const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON || (!final && !ctrl[b].cg_on)) return;
@@ -1436,7 +1436,7 @@ __global__ __launch_bounds__(1024) void k_wcg_half(const DevInst* __restrict__ i
             q[k] = w;
             pq += p[k] * w;
         });
-        pq = block_sum<1024>(pq, sh);
+        pq = block_sum<WCG_NT>(pq, sh);
         if (threadIdx.x == 0) I.blk[blockIdx.x] = pq;
     }
 }
@@ -2316,7 +2316,7 @@ template <class IX, class VT>
 static void launch_wcg_half_t(const LaunchCtx& L, int cols, int final) {
     const int rows = cols ? L.max_n : L.max_m;
     const dim3 g((rows + WCG_ROWS - 1) / WCG_ROWS, L.count);
-    hipLaunchKernelGGL((k_wcg_half<IX, VT>), g, dim3(1024), 0, L.stream, L.insts, L.ctrl, cols, final);
+    hipLaunchKernelGGL((k_wcg_half<IX, VT>), g, dim3(WCG_NT), 0, L.stream, L.insts, L.ctrl, cols, final);
 }
 
 static void launch_wcg_half(const LaunchCtx& L, int cols, int final) {
