@@ -880,12 +880,21 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
             for (int g = 0; g < NG2; ++g) wcnt[w][g] = mine[g];
     }
     __syncthreads();
+    __shared__ int btot[NG2];
+    if ((int)threadIdx.x < NG2) {
+        int t = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += wcnt[q][threadIdx.x];
+        btot[threadIdx.x] = t;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         int off = 0;
+#pragma unroll
         for (int g = 0; g < NG2; ++g) {
             boff[g] = off;
             ctrl[b].binoff[g] = off;
-            for (int q = 0; q < 16; ++q) off += wcnt[q][g];
+            off += btot[g];
         }
         ctrl[b].binoff[NG2] = off;
     }
@@ -903,12 +912,14 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
         __syncthreads();
         if (gk >= 0) {
             int woff = 0;
-            for (int q = 0; q < w; ++q) woff += wcnt[q][gk];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) woff += q < w ? wcnt[q][gk] : 0;
             I.rowbin[boff[gk] + woff + (int)__popcll(myb & below)] = k;
         }
         __syncthreads();
         if ((int)threadIdx.x < NG2) {
             int tot = 0;
+#pragma unroll
             for (int q = 0; q < 16; ++q) tot += wcnt[q][threadIdx.x];
             boff[threadIdx.x] += tot;
         }
