@@ -537,14 +537,12 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
                 // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
                 const int hsrc = mf ? src : -1;
                 run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_begin(L, hsrc); });
-                int it = 0;  // every instance of the batch starts its CG here
                 for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
                     const Ctrl* hc = readback(ctx, st, d_ctrl, count);
                     bool on = false;
                     for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
                     if (!on) break;
-                    for (int c = 0; c < chunk; ++c, ++it)
-                        run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc, it); });
+                    for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc); });
                 }
                 run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_end(L, hsrc); });
             }

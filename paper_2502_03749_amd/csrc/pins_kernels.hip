@@ -1413,8 +1413,8 @@ __global__ __launch_bounds__(1024) void k_wcg_begin(const DevInst* __restrict__ 
     }
 }
 
-// columns: p[m + j] = (S^T p_rows)_j / c_j, or q[m + j] = (S^T x)_j when
-// `final` (after the iterations); rows: q[i] = (S p_cols)_i for the start
+// columns: p[m + j] = (S^T p_rows)_j / c_j (and the iteration count
+// advanced), or q[m + j] = (S^T x)_j when `final` (after the iterations); rows: q[i] = (S p_cols)_i for the start
 // (`final` = 2), or in the iterations q[i] = r_i p_i - (S p_cols)_i and the
 // block's part of <p, q> in blk[block] (blocks of WCG_ROWS rows of the binned
 // list, in order)
@@ -1432,6 +1432,7 @@ __global__ __launch_bounds__(WCG_NT) void k_wcg_half(const DevInst* __restrict__
     double* __restrict__ p = I.cgw + 2 * N;
     double* __restrict__ q = I.cgw + 3 * N;
     const double* __restrict__ dg = I.rc;
+    if (cols && !final && blockIdx.x == 0 && threadIdx.x == 0) ctrl[b].cg_it += 1;  // iteration t starts: cg_it = t + 1
     if (cols) {
         if (final)
             spmv_range<IX, VT>(I, m, I.rowbin, bo, lo, hi, I.d, [q](int k, double v) { q[k] = v; });
@@ -1482,13 +1483,13 @@ __global__ __launch_bounds__(1024) void k_wcg_start(const DevInst* __restrict__ 
 
 // One iteration's vector work, over blocks of WCG_VROWS rows (the products
 // left q = D_r p - S D_c^-1 S^T p and the parts of <p, q> in blk, npq of them
-// per instance, pq_rows rows each).  t is the iteration (the host's launch
-// count; every instance of the batch starts its CG together): <res, z> of
-// iteration t is cg_rzs[t & 1], so no block reads a scalar that another block
-// of the same launch writes.  Each block sums the same partials in the same
-// order, so every block takes the same step.
+// per instance, pq_rows rows each).  In iteration t the columns half-product
+// has set cg_it = t + 1; <res, z> of iteration t is cg_rzs[t & 1], so no block
+// reads a scalar that another block of the same launch writes, and no launch of
+// an iteration takes a per-iteration argument.  Each block sums the same
+// partials in the same order, so every block takes the same step.
 // k_wcg_alpha: step length, x and res, the parts of ||res||^2 and <res, z> in blk2.
-__global__ __launch_bounds__(256) void k_wcg_alpha(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, int t,
+__global__ __launch_bounds__(256) void k_wcg_alpha(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
                                                    int pq_rows) {
     const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON || !ctrl[b].cg_on) return;
@@ -1499,9 +1500,15 @@ __global__ __launch_bounds__(256) void k_wcg_alpha(const DevInst* __restrict__ i
     __shared__ double sh[32];
     const double pq = block_sum_array<256>(I.blk, (m + pq_rows - 1) / pq_rows, sh);
     if (!(pq > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[b].cg_on = 0;  // every block sees the same pq
+        // every block sees the same pq and returns before reading cg_it; the
+        // breakdown iteration does not count
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctrl[b].cg_on = 0;
+            ctrl[b].cg_it -= 1;
+        }
         return;
     }
+    const int t = ctrl[b].cg_it - 1;
     const double al = ctrl[b].cg_rzs[t & 1] / pq;
     double* __restrict__ res = I.cgw;
     const double* __restrict__ p = I.cgw + 2 * N;
@@ -1524,8 +1531,7 @@ __global__ __launch_bounds__(256) void k_wcg_alpha(const DevInst* __restrict__ i
 }
 
 // k_wcg_beta: stop test and the next direction p = D_r^-1 res + beta p.
-__global__ __launch_bounds__(256) void k_wcg_beta(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
-                                                  int t) {
+__global__ __launch_bounds__(256) void k_wcg_beta(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON || !ctrl[b].cg_on) return;
     const DevInst& I = insts[b];
@@ -1538,10 +1544,10 @@ __global__ __launch_bounds__(256) void k_wcg_beta(const DevInst* __restrict__ in
         rr += I.blk2[2 * c];
         rz2 += I.blk2[2 * c + 1];
     }
+    const int t = ctrl[b].cg_it - 1;
     const double rz = ctrl[b].cg_rzs[t & 1];
     const int go = !(sqrt(rr) <= kp.cg_rtol * ctrl[b].cg_bnorm) && t + 1 < kp.cg_max;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctrl[b].cg_it = t + 1;
         if (go)
             ctrl[b].cg_rzs[(t + 1) & 1] = rz2;
         else
@@ -1607,8 +1613,8 @@ __global__ __launch_bounds__(256) void k_mf_tile(const DevInst* __restrict__ ins
     }
 }
 
-// cols = 1: t_j = sum over row blocks -> p[m + j] = t_j / c_j, or q[m + j] = t_j
-// when `final`; cols = 0: t_i = sum over column blocks -> q_i = t_i for the
+// cols = 1: t_j = sum over row blocks -> p[m + j] = t_j / c_j (and the
+// iteration count advanced), or q[m + j] = t_j when `final`; cols = 0: t_i = sum over column blocks -> q_i = t_i for the
 // start (`final` = 2), or in the iterations q_i = r_i p_i - t_i and the
 // block's part of <p, q> in blk[block].
 __global__ __launch_bounds__(256) void k_mf_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, int cols,
@@ -1621,6 +1627,7 @@ __global__ __launch_bounds__(256) void k_mf_merge(const DevInst* __restrict__ in
     double* __restrict__ p = I.cgw + 2 * N;
     double* __restrict__ q = I.cgw + 3 * N;
     if (cols) {
+        if (!final && k == 0) ctrl[b].cg_it += 1;  // iteration t starts: cg_it = t + 1
         if (k >= n) return;
         double t = 0.0;
         for (int rb = 0; rb < I.nrb; ++rb) t += I.part[(long)rb * n + k];
@@ -2360,13 +2367,13 @@ void launch_wcg_begin(const LaunchCtx& L, int src) {
     hipLaunchKernelGGL(k_wcg_start, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
-void launch_wcg_iter(const LaunchCtx& L, int src, int t) {
+void launch_wcg_iter(const LaunchCtx& L, int src) {
     launch_half(L, src, 1, 0);
     launch_half(L, src, 0, 0);
     const dim3 g = g2((L.max_m + WCG_VROWS - 1) / WCG_VROWS, L.count);
     const int pq_rows = src < 0 ? WCG_ROWS : 256;  // rows per part of <p, q> (k_wcg_half or k_mf_merge blocks)
-    hipLaunchKernelGGL(k_wcg_alpha, g, dim3(256), 0, L.stream, L.insts, L.ctrl, t, pq_rows);
-    hipLaunchKernelGGL(k_wcg_beta, g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, t);
+    hipLaunchKernelGGL(k_wcg_alpha, g, dim3(256), 0, L.stream, L.insts, L.ctrl, pq_rows);
+    hipLaunchKernelGGL(k_wcg_beta, g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
 void launch_wcg_end(const LaunchCtx& L, int src) {

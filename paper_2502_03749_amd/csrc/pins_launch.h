@@ -34,7 +34,7 @@ void launch_sparsify(const LaunchCtx& L, int src);
 // Hessian over that cost source
 bool wide_cg(const LaunchCtx& L);
 void launch_wcg_begin(const LaunchCtx& L, int src);
-void launch_wcg_iter(const LaunchCtx& L, int src, int t);  // t: the iteration (0, 1, ...)
+void launch_wcg_iter(const LaunchCtx& L, int src);  // one iteration; no per-iteration argument
 void launch_wcg_end(const LaunchCtx& L, int src);
 void launch_pcg(const LaunchCtx& L);
 void launch_ls(const LaunchCtx& L, int src, bool first);
