@@ -550,11 +550,12 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
             // one readback per Newton step: who is still iterating, who needs more
             // Armijo trials, who will take the Sinkhorn fallback
             const Ctrl* h = readback(ctx, st, d_ctrl, count);
-            bool any = false, pending = false, failed = false;
+            bool any = false, pending = false, failed = false, unapplied = false;
             for (int q = 0; q < count; ++q) {
                 any |= h[q].phase == PH_NEWTON;
                 pending |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_PENDING;
                 failed |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_FAILED;
+                unapplied |= h[q].phase == PH_NEWTON && h[q].ls_state != LS_APPLIED;
             }
             if (!any) break;
             for (int hh = 1; pending && hh < p.ls_max; hh += LS_T) {
@@ -566,7 +567,9 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
                     failed |= h2[q].phase == PH_NEWTON && h2[q].ls_state == LS_FAILED;
                 }
             }
-            run(ctx, st, PINS_K_UPDATE, [&] { launch_update(L); });
+            // the update (and the step's bookkeeping) of every instance whose full
+            // step the fused first trial has not already applied
+            if (unapplied) run(ctx, st, PINS_K_UPDATE, [&] { launch_update(L); });
             if (failed) {
                 run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, false, M_FB); });
                 run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, false, M_FB); });

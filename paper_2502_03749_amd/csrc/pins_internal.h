@@ -29,7 +29,8 @@ constexpr int WCG_MAX_N = 4096;  // instances with m+n above this take the wide 
 constexpr int WCG_VROWS = 1024;  // wide CG: rows per block of the vector steps
 
 enum Phase : int { PH_DONE = 0, PH_WARM = 1, PH_NEWTON = 2, PH_FALLBACK = 3 };
-enum LsState : int { LS_PENDING = 0, LS_ACCEPTED = 1, LS_FAILED = 2 };
+// LS_APPLIED: the full step accepted by the fused first trial and already applied
+enum LsState : int { LS_PENDING = 0, LS_ACCEPTED = 1, LS_FAILED = 2, LS_APPLIED = 3 };
 enum SrcKind : int { SRC_DENSE = 0, SRC_GRID = 1 };
 
 // Per-instance descriptor (device memory, read-only in kernels).

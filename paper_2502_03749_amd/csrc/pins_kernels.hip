@@ -1769,17 +1769,36 @@ __global__ __launch_bounds__(256) void k_ls_first_merge(const DevInst* __restric
     const DevInst& I = insts[b];
     __shared__ double sh[4];
     const double tot = block_sum_array<256>(I.blk, I.nrb * I.ncb, sh);
+    __shared__ int s_acc;
     if (threadIdx.x == 0) {
         Ctrl& S = ctrl[b];
         const double inc = S.dab - kp.eta * tot;
-        if (inc >= kp.ls_c1 * S.gd) {
-            S.alpha = 1.0;
-            S.ls_state = LS_ACCEPTED;
-            S.fused = 1;
-        } else {
+        s_acc = inc >= kp.ls_c1 * S.gd;
+        if (!s_acc) {
             S.ls_h = 1;
             if (S.ls_h >= kp.ls_max) S.ls_state = LS_FAILED;
         }
+    }
+    __syncthreads();
+    if (!s_acc) return;
+    // full step accepted: apply it here (what k_update does for an accepted
+    // step; F + 1.0 * d rounds as F + d there), with the next gradient already
+    // formed by the fused trial, so the host can skip k_update
+    const int m = I.m, N = m + I.n;
+    for (int k = threadIdx.x; k < N; k += 256) {
+        if (k < m)
+            I.F[k] += I.d[k];
+        else
+            I.G[k - m] += I.d[k];
+    }
+    if (threadIdx.x == 0) {
+        Ctrl& S = ctrl[b];
+        S.alpha = 1.0;
+        S.fused = 1;
+        S.ls_state = LS_APPLIED;
+        S.t += 1;
+        S.newton_total += 1;
+        S.grad_ready = 1;
     }
 }
 
@@ -1894,7 +1913,7 @@ __global__ __launch_bounds__(256) void k_ls_merge(const DevInst* __restrict__ in
 // one Sinkhorn iteration instead (phase FALLBACK).  One block per instance.
 __global__ __launch_bounds__(1024) void k_update(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
     const int b = blockIdx.x;
-    if (ctrl[b].phase != PH_NEWTON) return;
+    if (ctrl[b].phase != PH_NEWTON || ctrl[b].ls_state == LS_APPLIED) return;
     const DevInst& I = insts[b];
     const int m = I.m, N = I.m + I.n;
     const int st = ctrl[b].ls_state;
