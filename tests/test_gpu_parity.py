@@ -265,12 +265,12 @@ def test_caps_report_not_converged(ctx):
     assert np.isfinite(r["alpha"]).all() and np.isfinite(r["cost"])
 
 
-@pytest.mark.parametrize("case", ["lds8", "global"])
+@pytest.mark.parametrize("case", ["square", "tall"])
 def test_large_instances_parity(ctx, case):
-    """Sizes that use the largest register/LDS CG variant (m+n <= 8192) and the
-    global-memory CG (m+n > 8192)."""
+    """Dense instances above the one-block CG's limit (m + n > 4096): the wide
+    CG over many blocks, with 16-bit indices (m, n <= 65536)."""
     print("case large %s" % case, flush=True)
-    m, n = (4100, 4000) if case == "lds8" else (6000, 2300)
+    m, n = (4100, 4000) if case == "square" else (6000, 2300)
     C, a, b = _rand(m, n, 4242 + m)
     eta, K = 0.05, 1
     prm = P.params(eta=eta, max_outer=K)
@@ -282,8 +282,9 @@ def test_large_instances_parity(ctx, case):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_int32_index_storage_parity(ctx, precision):
-    """m > 65535 makes the CG's copy of S use 32-bit indices (16-bit otherwise),
-    with double (FP64) or float (mixed) values; parity in both precisions."""
+    """m > 65535 makes the wide CG's copy of S store 32-bit byte offsets
+    (16-bit indices otherwise), with double (FP64) or float (mixed) values;
+    parity in both precisions."""
     print("case tall 70000x3 %s" % precision, flush=True)
     m, n = 70000, 3
     C, a, b = _rand(m, n, 515)
