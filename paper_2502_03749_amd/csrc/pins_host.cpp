@@ -529,7 +529,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         // Newton steps; a readback after each
         for (;;) {
             run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
-            run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L); });
+            run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, false); });
             if (!mf) run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
             if (!mf && !wide_cg(L)) {
                 run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
@@ -547,6 +547,11 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
                 run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_end(L, hsrc); });
             }
             run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
+            // instances whose full step the fused first trial applied: the next
+            // gradient is formed, so merge it and take the convergence decision
+            // now (a subproblem that converged in one step then needs no further
+            // round of launches)
+            run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, true); });
             // one readback per Newton step: who is still iterating, who needs more
             // Armijo trials, who will take the Sinkhorn fallback
             const Ctrl* h = readback(ctx, st, d_ctrl, count);

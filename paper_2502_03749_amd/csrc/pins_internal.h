@@ -97,6 +97,7 @@ struct Ctrl {
     double work[8];  // matrix entries visited per pass kind (W_* below); W_CG: stored entries read by CG
     int binoff[16];  // rowbin offsets: NBIN bins of rows of S, then NBIN bins of rows of S^T; [2 NBIN] = m+n
     int cg_it, cg_on;        // wide CG (many blocks per instance): iterations, still iterating
+    int decided, pad3;       // 1: the next round's gradient already merged and decided (after the fused trial)
     double cg_rzs[2], cg_bnorm;  // wide CG: <res, z> of iteration t in cg_rzs[t & 1]; ||rhs||
 };
 

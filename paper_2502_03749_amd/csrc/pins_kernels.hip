@@ -636,11 +636,13 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
 // Gradient merge: r = Xt e, c = Xt^T e into rc.  32 entries of (r, c) per
 // block with 8 lanes each: lane s sums the partials s, s + 8, ..., and the 8
 // sums of an entry are combined in lane order; the block's part of
-// ||a - r||_1 + ||b - c||_1 goes to blk2 for k_grad_decide.
+// ||a - r||_1 + ||b - c||_1 goes to blk2 for k_grad_decide.  `early`: right
+// after a full step applied by the fused first trial (whose partials are the
+// next gradient's), for those instances only; a later round then skips them.
 __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
-                                                    KP kp) {
+                                                    KP kp, int early) {
     const int b = blockIdx.y;
-    if (ctrl[b].phase != PH_NEWTON) return;
+    if (ctrl[b].phase != PH_NEWTON || (early ? ctrl[b].ls_state != LS_APPLIED : ctrl[b].decided)) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
     if ((int)blockIdx.x * 32 >= N) return;
@@ -671,9 +673,18 @@ __global__ __launch_bounds__(256) void k_grad_merge(const DevInst* __restrict__ 
 
 // Newton control: residual, convergence, Sparsify level (one block per instance).
 __global__ __launch_bounds__(256) void k_grad_decide(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
-                                                     KP kp) {
+                                                     KP kp, int early) {
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
+    if (early && ctrl[b].ls_state != LS_APPLIED) return;
+    if (!early && ctrl[b].decided) {  // decided right after the previous step (early)
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ctrl[b].decided = 0;
+            ctrl[b].grad_ready = 0;
+        }
+        return;
+    }
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n;
     __shared__ double sh[4];
@@ -723,7 +734,13 @@ __global__ __launch_bounds__(256) void k_grad_decide(const DevInst* __restrict__
     }
     __syncthreads();
     if ((int)threadIdx.x < NLEV) I.hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) S.grad_ready = 0;
+    if (threadIdx.x == 0) {
+        // early and continuing: the next round skips this instance's Newton
+        // pass, merge and decision (the gradient is the fused trial's)
+        const int keep = early && S.phase == PH_NEWTON;
+        S.grad_ready = keep;
+        S.decided = keep;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2306,10 +2323,10 @@ void launch_grad(const LaunchCtx& L, int src) {
 #undef K_
 }
 
-void launch_grad_merge(const LaunchCtx& L) {
+void launch_grad_merge(const LaunchCtx& L, bool early) {
     hipLaunchKernelGGL(k_grad_merge, g2((L.max_mn + 31) / 32, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
-                       L.kp);
-    hipLaunchKernelGGL(k_grad_decide, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp);
+                       L.kp, early ? 1 : 0);
+    hipLaunchKernelGGL(k_grad_decide, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, early ? 1 : 0);
 }
 
 template <class IX, class VT>

@@ -25,7 +25,7 @@ void launch_row_lse(const LaunchCtx& L, int src, bool f32, int mask);
 void launch_col_lse(const LaunchCtx& L, int src, bool f32, int mask);
 void launch_col_merge(const LaunchCtx& L, int mask);
 void launch_grad(const LaunchCtx& L, int src);
-void launch_grad_merge(const LaunchCtx& L);
+void launch_grad_merge(const LaunchCtx& L, bool early);  // early: only instances whose fused full step was just applied
 void launch_sparsify(const LaunchCtx& L, int src);
 // wide CG (batches whose largest m+n exceeds WCG_MAX_N, or matrix-free
 // products): begin, one iteration (no-op for instances that stopped), end; the
