@@ -505,25 +505,46 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     auto matrix_free = [&](int k) { return p.hvp == 1 || (p.hvp == 2 && k < p.hvp_switch); };
     const int K = p.max_outer;
     const int M_WARM = 1 << PH_WARM, M_FB = 1 << PH_FALLBACK;
+    bool quick_warm = false;  // every warm-up of the last outer iteration took one iteration
     for (int k = 0; k < K; ++k) {
         const bool mf = matrix_free(k);
         kp.tol = (k == K - 1) ? p.final_tol : p.inner_tol;
         kp.last = (k == K - 1) ? 1 : 0;
         if (k > 0) run(ctx, st, PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
         // warm-up: chunks of W Sinkhorn iterations, then a readback
-        if (p.max_sinkhorn > 0) {
-            int W = 1;
+        // warm-up sweeps of the instances in the warm-up phase: chunks of W
+        // iterations, a readback after each, until none is left; returns the
+        // number of chunks
+        auto warm_loop = [&](int W) {
+            int chunks = 0;
             for (;;) {
                 for (int w = 0; w < W; ++w) {
                     run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
                     run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
                     run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
                 }
+                ++chunks;
                 const Ctrl* h = readback(ctx, st, d_ctrl, count);
                 bool any = false;
                 for (int q = 0; q < count; ++q) any |= h[q].phase == PH_WARM;
-                if (!any) break;
+                if (!any) return chunks;
                 W = std::min(2 * W, 8);
+            }
+        };
+        // After the shift, when every warm-up of the previous outer iteration
+        // took a single iteration, one iteration is launched and the first Newton
+        // round follows without a readback: the Newton kernels act only on the
+        // instances that iteration moved to the Newton phase, and any still in the
+        // warm-up finish it after the round's readback and join the next round.
+        bool warm_unread = false;
+        if (p.max_sinkhorn > 0) {
+            if (quick_warm) {
+                run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
+                run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
+                run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
+                warm_unread = true;
+            } else {
+                quick_warm = warm_loop(1) == 1;
             }
         }
         // Newton steps; a readback after each
@@ -555,14 +576,19 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
             // one readback per Newton step: who is still iterating, who needs more
             // Armijo trials, who will take the Sinkhorn fallback
             const Ctrl* h = readback(ctx, st, d_ctrl, count);
-            bool any = false, pending = false, failed = false, unapplied = false;
+            bool any = false, pending = false, failed = false, unapplied = false, warm = false;
             for (int q = 0; q < count; ++q) {
                 any |= h[q].phase == PH_NEWTON;
                 pending |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_PENDING;
                 failed |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_FAILED;
                 unapplied |= h[q].phase == PH_NEWTON && h[q].ls_state != LS_APPLIED;
+                warm |= h[q].phase == PH_WARM;
             }
-            if (!any) break;
+            if (warm_unread) {
+                warm_unread = false;
+                quick_warm = !warm;
+            }
+            if (!any && !warm) break;
             for (int hh = 1; pending && hh < p.ls_max; hh += LS_T) {
                 run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, false); });
                 const Ctrl* h2 = readback(ctx, st, d_ctrl, count);
@@ -580,6 +606,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
                 run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, false, M_FB); });
                 run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_FB); });
             }
+            if (warm) warm_loop(2);  // the instances the single warm-up iteration left
         }
     }
     bool want_x = false;
