@@ -61,7 +61,8 @@ typedef enum {
     PINS_MIXED = 1 /* Sinkhorn warm-up sweeps evaluate exp and accumulate the
                       log-sum-exp in float (exponent formed in double); the CG
                       stores the kept entries of the sparsified Hessian in
-                      float; gradients, CG vectors and sums, line search,
+                      float, and matrix-free products evaluate X~ with a float
+                      exp; gradients, CG vectors and sums, line search,
                       potentials and outputs stay double */
 } pins_precision;
 

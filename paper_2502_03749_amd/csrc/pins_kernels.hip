@@ -1584,7 +1584,7 @@ __global__ __launch_bounds__(256) void k_wcg_beta(const DevInst* __restrict__ in
 // part[rb][j] = sum_i X~_ij u_i of the tile (u = the direction on the rows, or
 // x when `final`); cols = 0: row partials part2[cb][i] = sum_j X~_ij w_j
 // (w = D_c^-1 X~^T p on the columns).  Merged in fixed order by k_mf_merge.
-template <class Src>
+template <class Src, class T>
 __global__ __launch_bounds__(256) void k_mf_tile(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
                                                  int cols, int final) {
     const BlkRef br = blk_ref(kp.toff, kp.count);
@@ -1612,7 +1612,7 @@ __global__ __launch_bounds__(256) void k_mf_tile(const DevInst* __restrict__ ins
     if (cols) {
         double acc = 0.0;
         if (valid)
-            for (int r = 0; r < rows; ++r) acc += texp(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), sT) * su[r];
+            for (int r = 0; r < rows; ++r) acc += (double)ex<T>(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), sT) * su[r];
         if (valid) I.part[(long)rb * n + j] = acc;
     } else {
         const double wj = valid ? p[m + j] : 0.0;
@@ -1621,7 +1621,7 @@ __global__ __launch_bounds__(256) void k_mf_tile(const DevInst* __restrict__ ins
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int r = r0 + t;
-                v[t] = (valid && r < rows) ? texp(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), sT) * wj : 0.0;
+                v[t] = (valid && r < rows) ? (double)ex<T>(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), sT) * wj : 0.0;
             }
             wave_rows4(v, r0, wsum);
         }
@@ -2390,8 +2390,12 @@ static void launch_half(const LaunchCtx& L, int src, int cols, int final) {
         return;
     }
     const dim3 g(L.total_tiles);
-#define K_(S) hipLaunchKernelGGL((k_mf_tile<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, cols, final)
-    PINS_SRC_DISPATCH(src, K_);
+#define K_(S, T) hipLaunchKernelGGL((k_mf_tile<S, T>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, cols, final)
+    if (L.sp_fmt & 2) {
+        PINS_SRC_DISPATCH(src, K_, float);  // mixed precision: float exp (exponent formed in double)
+    } else {
+        PINS_SRC_DISPATCH(src, K_, double);
+    }
 #undef K_
     hipLaunchKernelGGL(k_mf_merge, g2(((cols ? L.max_n : L.max_m) + 255) / 256, L.count), dim3(256), 0, L.stream,
                        L.insts, L.ctrl, cols, final);
