@@ -23,8 +23,10 @@ The JSON line also carries:
                   workload (rank 0, one thread);
   accuracy     -- relative cost difference of the sampled instance against
                   the oracle at the same K (bar: 1e-6);
-  variants     -- plain single-instance throughput, the other precision, and
-                  an uneven batch of 256 point-cloud instances;
+  variants     -- plain single-instance throughput, the other precision, an
+                  uneven batch of 256 point-cloud instances, and the batch
+                  with the sparsified Hessian throughout and with matrix-free
+                  products throughout;
   sinkhorn_sweep -- HBM rate of the Sinkhorn half-sweeps on a materialised
                   16384 x 16384 FP64 cost;
   served       -- 120 Poisson-arriving grid requests (60% 32x32, 30% 64x64,
