@@ -282,3 +282,24 @@ def test_degenerate_sizes(oracle_mod):
     r = oracle_mod.pins(np.array([[0.7]]), np.array([1.0]), np.array([1.0]), eta=0.1, K=2)
     assert r["X"][0, 0] == pytest.approx(1.0, abs=1e-15)
     assert r["cost"] == pytest.approx(0.7)
+
+
+def test_oracle_reproduces_its_fixtures(oracle_mod):
+    """tests/golden/oracle_fixtures.json (written by make_oracle_fixtures.py from
+    the pinned oracle): the oracle still computes the same outputs."""
+    import json
+    import os
+    import sys
+
+    gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, gdir)
+    import make_oracle_fixtures as G
+
+    ref = json.load(open(os.path.join(gdir, "oracle_fixtures.json")))
+    for name, C, a, b, eta, K in G.cases():
+        r = oracle_mod.pins(C, a, b, eta=eta, K=K, want_plan=False)
+        f = ref[name]
+        assert r["status"] == 0 and f["eta"] == eta and f["K"] == K, name
+        assert abs(r["cost"] - f["cost"]) <= 1e-12 * abs(f["cost"]), name
+        assert np.abs(r["alpha"] - np.array(f["alpha"])).max() <= 1e-11, name
+        assert np.abs(r["beta"] - np.array(f["beta"])).max() <= 1e-11, name
