@@ -1057,11 +1057,13 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
 // iterations CG on M with diag(M) needs, at the same cost per iteration (one
 // product with S^T, one with S).  With y eliminated exactly the residual of
 // M's system is (reduced residual, 0), so the stop ||res||_2 <= cg_rtol *
-// ||b||_2 (or cg_max iterations) is the rule for M's system itself.  One block
-// of 1024 threads per instance; each thread owns the vector entries
-// k = tid + 1024 t (registers in the LDS variant); the products are done by
-// lane groups over the binned rows, gathering from LDS.  Afterwards the
-// line-search inputs <grad P, d>, <a,dF>+<b,dG> and the resolution test.
+// ||b||_2 (or cg_max iterations) is the rule for M's system itself.  For
+// m + n <= WCG_MAX_N one block of 1024 threads per instance; each thread owns
+// the vector entries k = tid + 1024 t (the row iterate, residual and direction
+// in registers, the rest in LDS); the products are done by lane groups over the
+// binned rows, gathering from LDS.  Larger instances take the wide CG below.
+// Afterwards the line-search inputs <grad P, d>, <a,dF>+<b,dG> and the
+// resolution test.
 // ---------------------------------------------------------------------------
 // Off-diagonal part of M times p (S v for a row k < m, S^T u for k >= m).
 // Rows are stored in aligned, transposed quads (see quad_slot); the entry
@@ -1070,7 +1072,8 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
 // wave do rows of about the same length; a lane loads each quad (its 4
 // indices and 4 values) with one vector load each and keeps several quads in
 // flight.  ptr arrays: CSR row pointers (rp, m+1) and CSC column pointers
-// (cp, n+1), in LDS or global memory; bins: the row list.
+// (cp, n+1), in LDS (one-block CG) or global memory (wide CG); bins: the row
+// list.
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
