@@ -29,6 +29,8 @@ The JSON line also carries:
                   products throughout;
   sinkhorn_sweep -- HBM rate of the Sinkhorn half-sweeps on a materialised
                   16384 x 16384 FP64 cost;
+  sinkhorn_sweep_streamed -- the same sweeps over a streamed 128 x 128 grid
+                  cost: entries per second and compute-unit cycles per entry;
   served       -- 120 Poisson-arriving grid requests (60% 32x32, 30% 64x64,
                   10% 128x128, eta = 1e-3, K = 10) through pins_server:
                   solves/s and p50 / p99 latency.
@@ -100,7 +102,7 @@ def parse():
                     help="concurrent lanes of the batched call (params.streams); results do not depend on it")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the materialised-cost Sinkhorn sweep measurement (16384 x 16384 FP64 cost)")
-    ap.add_argument("--sweep-only", action="store_true", help="only run the materialised-cost sweep measurement")
+    ap.add_argument("--sweep-only", action="store_true", help="only run the sweep measurements (materialised and streamed cost)")
     ap.add_argument("--served", type=int, default=0, metavar="N",
                     help="only run the served measurement: N Poisson-arriving grid requests (60%% 32x32, 30%% 64x64, "
                          "10%% 128x128, eta = 1e-3, K = 10) through pins_server")
@@ -169,7 +171,8 @@ def main():
         return
     ctx = P.Context(0)
     if args.sweep_only:
-        print(json.dumps(dict(sinkhorn_sweep=sweep_roofline(P, ctx, torch, np, dev))), flush=True)
+        print(json.dumps(dict(sinkhorn_sweep=sweep_roofline(P, ctx, torch, np, dev),
+                              sinkhorn_sweep_streamed=streamed_sweep(P, ctx, torch, np, dev, W))), flush=True)
         ctx.close()
         return
     stream = torch.cuda.current_stream()
@@ -294,6 +297,7 @@ def main():
 
     if not args.no_sweep:
         line["sinkhorn_sweep"] = sweep_roofline(P, ctx, torch, np, dev)
+        line["sinkhorn_sweep_streamed"] = streamed_sweep(P, ctx, torch, np, dev, W)
     if not args.no_served:
         line["served"] = served(P, W, 120, args.rate)
 
@@ -511,6 +515,38 @@ def sweep_roofline(P, ctx, torch, np, dev, side=16384, sweeps=7):
     torch.cuda.empty_cache()
     return dict(workload="dense %dx%d FP64 cost (%.2f GB), %d warm-up iterations" % (m, n, 8.0 * m * n / 1e9, sweeps),
                 bytes_per_half_sweep=bytes_per_sweep, peak_GBs=PEAK_HBM_GBS, **res)
+
+
+def streamed_sweep(P, ctx, torch, np, dev, W, side=128, sweeps=7):
+    """Sinkhorn half-sweeps over a streamed grid cost (never stored): an
+    s x s pixel grid pair (Gaussian mixtures, m = n = s^2), `sweeps` warm-up
+    iterations, no Newton steps, K = 1, timed per launch by the library's
+    events.  Nothing but the potentials moves through HBM, so the rate is the
+    ALU's: entries per second (one exp each, float in mixed precision after an
+    exponent formed in double, the table-driven double exp in FP64) and the
+    compute-unit cycles one entry takes (256 CUs at 2.4 GHz)."""
+    pr = W.grid_pair("gmm", 0, s=side)
+    m = n = side * side
+    t = lambda v: torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev)
+    prob = dict(kind=P.COST_GRID, m=m, n=n, grid_s=side, a=t(pr["a"]), b=t(pr["b"]))
+    out = dict(alpha=torch.empty(m, dtype=torch.float64, device=dev), beta=torch.empty(n, dtype=torch.float64, device=dev))
+    res = {}
+    for name, prec in (("mixed", P.MIXED), ("fp64", P.FP64)):
+        prm = P.params(eta=1e-3, max_outer=1, max_sinkhorn=sweeps, max_newton=0, warm_tol=0.0, precision=prec,
+                       profile=1)
+        _, r = ctx.solve_device(prob, prm, out, stream=torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        ent = {}
+        for k in ("row_lse", "col_lse"):
+            calls = r["kern_calls"][k]
+            if calls:
+                us = 1e3 * r["kern_ms"][k] / calls
+                eps = m * n / (us * 1e-6)
+                ent[k] = dict(avg_launch_us=round(us, 2), entries_per_s=float("%.4g" % eps),
+                              cu_cycles_per_entry=round(256 * 2.4e9 / eps, 3), launches=calls)
+        res[name] = ent
+    return dict(workload="%dx%d grid pair (m = n = %d), streamed cost, %d warm-up iterations" % (side, side, m, sweeps),
+                **res)
 
 
 def _traffic(kernel):
