@@ -202,6 +202,41 @@ int pins_solve(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pi
 int pins_solve_device(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res,
                       void* stream);
 
+/* ---- Checkpoint / resume of the outer loop ----
+ * Under the implicit shift the k-th EPPA subproblem, eq. (eppa-sub), has the
+ * exponent (F_i + G_j - (k+1) C_ij) / eta: the shifted cost C - eta log X^k
+ * of Alg. 2 is carried by k and the accumulated row and column shifts A, B,
+ * and the subproblem's dual iterate by (F, G).  After k completed outer
+ * iterations the tuple (k, F, G, A, B) therefore fixes everything that
+ * follows: it is a complete resume point.  All arrays are HOST arrays owned
+ * by the caller. */
+typedef struct {
+    int32_t m, n;        /* sizes of the problem the state belongs to */
+    int32_t outer_done;  /* k: outer iterations completed */
+    int32_t flags;       /* bit1 of pins_result.flags so far (an earlier subproblem hit T2) */
+    double* F;           /* m: row dual iterate of the last subproblem */
+    double* G;           /* n: column dual iterate */
+    double* A;           /* m: accumulated row shift */
+    double* B;           /* n: accumulated column shift */
+} pins_state;
+
+/* pins_solve (HOST pointers, synchronous) over a range of outer iterations:
+ * start after from->outer_done iterations (from = NULL: from the start, as
+ * pins_solve), run up to `stop` completed iterations (0 = p->max_outer = K)
+ * and, when save is non-NULL, write the state reached into save (its F, G, A,
+ * B must point to m, n, m, n doubles; the call sets m, n, outer_done and
+ * flags).  The subproblem tolerance follows the absolute iteration index
+ * (final_tol only for iteration K-1), so a solve split at any stop and resumed
+ * from the saved state gives bitwise the iterates and outputs of the unbroken
+ * solve.  The outputs in *res describe the plan after `stop` iterations
+ * (eps = eta/stop, outer_iters = stop); the iteration counters and kern_*
+ * cover this call only.  Needs the implicit shift (else PINS_EUNSUPPORTED).
+ * PINS_EINVAL when stop > K, when from does not match the problem's m and n,
+ * when from->outer_done is not in [1, stop) or from has a NULL or non-finite
+ * array, or when save has a NULL array; nothing is written then. */
+int pins_solve_resume(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, const pins_state* from,
+                      int32_t stop, pins_state* save, pins_result* res);
+
 /* Solve `count` independent problems in one batch (DEVICE pointers): every
  * kernel launch covers all instances still active, each instance keeps its
  * own iteration control, and each result equals the one its problem gets

@@ -71,6 +71,11 @@ class Result(ctypes.Structure):
         return out
 
 
+class State(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("outer_done", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("F", _D), ("G", _D), ("A", _D), ("B", _D)]
+
+
 class PinsError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("pins error %d: %s" % (code, msg))
@@ -102,6 +107,8 @@ def lib():
         L.pins_solve.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(Result)]
         L.pins_solve_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(Result),
                                         vp]
+        L.pins_solve_resume.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(State),
+                                        ctypes.c_int32, ctypes.POINTER(State), ctypes.POINTER(Result)]
         L.pins_solve_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
                                               ctypes.POINTER(Result), vp]
         L.pins_server_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
@@ -165,27 +172,37 @@ class Context:
     # -------------------------------------------------------------- host API
     def solve(self, kind, a, b, prm: Params, C=None, x=None, y=None, grid_s=0, cost_scale=0.0, want_plan=False):
         """pins_solve with numpy host arrays.  Returns dict(alpha, beta, X, **scalars)."""
-        a = np.ascontiguousarray(a, np.float64)
-        b = np.ascontiguousarray(b, np.float64)
-        keep = [a, b]
-        P = Problem(kind=kind, m=a.size, n=b.size, d=0, grid_s=grid_s, cost_scale=cost_scale,
-                    a=a.ctypes.data, b=b.ctypes.data)
-        if C is not None:
-            C = np.ascontiguousarray(C, np.float64)
-            keep.append(C)
-            P.C = C.ctypes.data
-        if x is not None:
-            x = np.ascontiguousarray(x, np.float64)
-            y = np.ascontiguousarray(y, np.float64)
-            keep += [x, y]
-            P.x, P.y, P.d = x.ctypes.data, y.ctypes.data, x.shape[1]
-        alpha = np.empty(a.size)
-        beta = np.empty(b.size)
-        X = np.empty((a.size, b.size)) if want_plan else None
-        R = Result(alpha=alpha.ctypes.data, beta=beta.ctypes.data, X=X.ctypes.data if X is not None else None)
+        P, keep = _host_problem(kind, a, b, C, x, y, grid_s, cost_scale)
+        R, outs = _host_result(P.m, P.n, want_plan)
         rc = self._check(lib().pins_solve(self.h, ctypes.byref(P), ctypes.byref(prm), ctypes.byref(R)))
         out = R.scalars()
-        out.update(alpha=alpha, beta=beta, X=X, rc=rc)
+        out.update(outs, rc=rc)
+        return out
+
+    def solve_resume(self, kind, a, b, prm: Params, state=None, stop=0, C=None, x=None, y=None, grid_s=0,
+                     cost_scale=0.0, want_plan=False):
+        """pins_solve_resume with numpy host arrays.
+
+        state: None (start) or a dict(outer_done, flags, F, G, A, B) returned by an earlier call;
+        stop: outer iterations completed when the call returns (0 = max_outer).
+        Returns dict(alpha, beta, X, state, **scalars), state being the resume point reached.
+        """
+        P, keep = _host_problem(kind, a, b, C, x, y, grid_s, cost_scale)
+        R, outs = _host_result(P.m, P.n, want_plan)
+        m, n = P.m, P.n
+        save = {k: np.empty(m if k in ("F", "A") else n) for k in ("F", "G", "A", "B")}
+        S_out = State(**{k: v.ctypes.data_as(_D) for k, v in save.items()})
+        S_in = None
+        if state is not None:
+            arr = {k: np.ascontiguousarray(state[k], np.float64) for k in ("F", "G", "A", "B")}
+            keep.append(arr)
+            S_in = State(m=arr["F"].size, n=arr["G"].size, outer_done=state["outer_done"],
+                         flags=state.get("flags", 0), **{k: v.ctypes.data_as(_D) for k, v in arr.items()})
+        rc = self._check(lib().pins_solve_resume(self.h, ctypes.byref(P), ctypes.byref(prm),
+                                                 ctypes.byref(S_in) if S_in is not None else None, int(stop),
+                                                 ctypes.byref(S_out), ctypes.byref(R)))
+        out = R.scalars()
+        out.update(outs, rc=rc, state=dict(save, outer_done=S_out.outer_done, flags=S_out.flags))
         return out
 
     # ------------------------------------------------------------ device API
@@ -279,6 +296,33 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _host_problem(kind, a, b, C, x, y, grid_s, cost_scale):
+    """A Problem over numpy host arrays, and the arrays it points into."""
+    a = np.ascontiguousarray(a, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    keep = [a, b]
+    P = Problem(kind=kind, m=a.size, n=b.size, d=0, grid_s=grid_s, cost_scale=cost_scale,
+                a=a.ctypes.data, b=b.ctypes.data)
+    if C is not None:
+        C = np.ascontiguousarray(C, np.float64)
+        keep.append(C)
+        P.C = C.ctypes.data
+    if x is not None:
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.ascontiguousarray(y, np.float64)
+        keep += [x, y]
+        P.x, P.y, P.d = x.ctypes.data, y.ctypes.data, x.shape[1]
+    return P, keep
+
+
+def _host_result(m, n, want_plan):
+    """A Result with host output arrays alpha (m), beta (n) and optionally X (m x n)."""
+    outs = dict(alpha=np.empty(m), beta=np.empty(n), X=np.empty((m, n)) if want_plan else None)
+    R = Result(alpha=outs["alpha"].ctypes.data, beta=outs["beta"].ctypes.data,
+               X=outs["X"].ctypes.data if want_plan else None)
+    return R, outs
 
 
 def _ptr(t):

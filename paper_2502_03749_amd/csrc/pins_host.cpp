@@ -295,8 +295,17 @@ const Ctrl* readback(Lane* c, hipStream_t st, const Ctrl* d_ctrl, int count) {
     return h;
 }
 
+// A range of outer iterations for pins_solve_resume: start after
+// from->outer_done completed iterations (from = nullptr: at the start), stop
+// after `stop`, copy the state reached to *save when non-null.
+struct ResumeIO {
+    const pins_state* from;
+    int stop;
+    pins_state* save;
+};
+
 int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_params& p, pins_result* res,
-               hipStream_t st, bool host_api) {
+               hipStream_t st, bool host_api, const ResumeIO* rio = nullptr) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
     if (count < 1) fail(PINS_EINVAL, "count must be >= 1");
@@ -499,6 +508,27 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         for (int q = 0; q < count; ++q)
             if (h[q].nonfinite) fail(PINS_EINVAL, "C has non-finite entries (instance " + std::to_string(q) + ")");
     }
+    // resume: the saved (F, G, A, B), kappa = k (k + 1 after the coming shift)
+    // and the earlier-subproblem flag replace what the initialisation wrote
+    int k_begin = 0, k_end = p.max_outer;
+    if (rio) {
+        k_end = rio->stop;
+        if (rio->from) {
+            const pins_state& S = *rio->from;
+            const InstPlan& Lp = B.plans[0];
+            const size_t D = sizeof(double);
+            k_begin = S.outer_done;
+            const double kap = (double)S.outer_done;
+            const int fl = S.flags & 2;
+            HIPCHK(hipMemcpyAsync(Dp(Lp.F), S.F, D * Lp.m, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(Dp(Lp.G), S.G, D * Lp.n, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(Dp(Lp.Ah), S.A, D * Lp.m, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(Dp(Lp.Bh), S.B, D * Lp.n, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(&d_ctrl[0].kappa, &kap, sizeof(double), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(&d_ctrl[0].flags, &fl, sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+    }
 
     const bool f32 = p.precision == PINS_MIXED;
     // matrix-free Hessian products (no Sparsify) in outer iteration k
@@ -506,7 +536,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     const int K = p.max_outer;
     const int M_WARM = 1 << PH_WARM, M_FB = 1 << PH_FALLBACK;
     bool quick_warm = false;  // every warm-up of the last outer iteration took one iteration
-    for (int k = 0; k < K; ++k) {
+    for (int k = k_begin; k < k_end; ++k) {
         const bool mf = matrix_free(k);
         kp.tol = (k == K - 1) ? p.final_tol : p.inner_tol;
         kp.last = (k == K - 1) ? 1 : 0;
@@ -611,8 +641,22 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     }
     bool want_x = false;
     for (int q = 0; q < count; ++q) want_x |= hI[q].X != nullptr;
-    run(ctx, st, PINS_K_FINAL, [&] { launch_final(L, base_src, (double)K, want_x); });
+    run(ctx, st, PINS_K_FINAL, [&] { launch_final(L, base_src, (double)k_end, want_x); });
     const Ctrl* h = readback(ctx, st, d_ctrl, count);
+    if (rio && rio->save) {
+        pins_state& S = *rio->save;
+        const InstPlan& Lp = B.plans[0];
+        const size_t D = sizeof(double);
+        HIPCHK(hipMemcpyAsync(S.F, Dp(Lp.F), D * Lp.m, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(S.G, Dp(Lp.G), D * Lp.n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(S.A, Dp(Lp.Ah), D * Lp.m, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(S.B, Dp(Lp.Bh), D * Lp.n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        S.m = Lp.m;
+        S.n = Lp.n;
+        S.outer_done = k_end;
+        S.flags = h[0].flags & 2;
+    }
 
     // outputs
     if (host_api) {
@@ -643,7 +687,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         pins_result& r = res[q];
         const Ctrl& S = h[q];
         r.cost = S.cost;
-        r.eps = p.eta / (double)K;
+        r.eps = p.eta / (double)k_end;
         r.resid = S.resid;
         r.dual = S.dual;
         r.gap = S.cost - S.dual;
@@ -651,7 +695,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         r.cost_scale = need_max ? S.scale : hI[q].bscale;
         r.time_ms = wall;
         r.flags = S.flags | (S.nonfinite ? 4 : 0);
-        r.outer_iters = K;
+        r.outer_iters = k_end;
         r.sinkhorn_iters = S.sink_total;
         r.newton_iters = S.newton_total;
         r.cg_iters = S.cg_total;
@@ -867,6 +911,33 @@ int pins_solve_device(pins_ctx* ctx, const pins_problem* prob, const pins_params
     return guarded(ctx, [&] {
         if (!prob || !p || !res) fail(PINS_EINVAL, "null argument");
         return solve_entry(ctx, prob, 1, *p, res, (hipStream_t)stream, false);
+    });
+}
+
+int pins_solve_resume(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, const pins_state* from,
+                      int32_t stop, pins_state* save, pins_result* res) {
+    return guarded(ctx, [&] {
+        if (!prob || !p || !res) fail(PINS_EINVAL, "null argument");
+        check_params(*p);
+        check_problem_shape(*prob);
+        if (p->shift_mode != PINS_SHIFT_IMPLICIT)
+            fail(PINS_EUNSUPPORTED, "resume needs the implicit shift (shift_mode 0)");
+        const int K = p->max_outer;
+        if (stop < 0 || stop > K) fail(PINS_EINVAL, "stop must be in [0, max_outer]");
+        const ResumeIO io{from, stop > 0 ? stop : K, save};
+        if (from) {
+            const pins_state& S = *from;
+            if (S.m != prob->m || S.n != prob->n) fail(PINS_EINVAL, "state sizes do not match the problem");
+            if (S.outer_done < 1 || S.outer_done >= io.stop)
+                fail(PINS_EINVAL, "state outer_done must be in [1, stop)");
+            if (!S.F || !S.G || !S.A || !S.B) fail(PINS_EINVAL, "state arrays are required");
+            for (int i = 0; i < S.m; ++i)
+                if (!std::isfinite(S.F[i]) || !std::isfinite(S.A[i])) fail(PINS_EINVAL, "state has non-finite entries");
+            for (int j = 0; j < S.n; ++j)
+                if (!std::isfinite(S.G[j]) || !std::isfinite(S.B[j])) fail(PINS_EINVAL, "state has non-finite entries");
+        }
+        if (save && (!save->F || !save->G || !save->A || !save->B)) fail(PINS_EINVAL, "save arrays are required");
+        return solve_impl(lane(ctx, 0), prob, 1, *p, res, nullptr, true, &io);
     });
 }
 

@@ -26,12 +26,13 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pins.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(pins_params), sizeof(pins_problem),'
-                   ' sizeof(pins_result), offsetof(pins_result, kern_ms), offsetof(pins_problem, a));return 0;}\n')
+                   ' sizeof(pins_result), offsetof(pins_result, kern_ms), offsetof(pins_problem, a));'
+                   'printf("%zu %zu\\n", sizeof(pins_state), offsetof(pins_state, B));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert got == [ctypes.sizeof(B.Params), ctypes.sizeof(B.Problem), ctypes.sizeof(B.Result),
-                   B.Result.kern_ms.offset, B.Problem.a.offset]
+                   B.Result.kern_ms.offset, B.Problem.a.offset, ctypes.sizeof(B.State), B.State.B.offset]
 
 
 def test_default_params_are_the_papers():
@@ -91,3 +92,13 @@ def test_server_without_gpu_reports_device_error():
     prm = P.params(eta=0.1)
     assert P.lib().pins_server_create(0, 2, 8, 0, ctypes.byref(prm), ctypes.byref(h)) == P._binding.PINS_EDEVICE
     assert P.lib().pins_server_create(0, 0, 8, 0, ctypes.byref(prm), ctypes.byref(h)) == P._binding.PINS_EINVAL
+
+
+def test_entry_points_reject_a_null_context():
+    """Every solve entry point returns PINS_EINVAL for a NULL context, with no GPU."""
+    prm = P.params(eta=0.1)
+    L = P.lib()
+    assert L.pins_solve(None, None, ctypes.byref(prm), None) == B.PINS_EINVAL
+    assert L.pins_solve_device(None, None, ctypes.byref(prm), None, None) == B.PINS_EINVAL
+    assert L.pins_solve_batch_device(None, None, 1, ctypes.byref(prm), None, None) == B.PINS_EINVAL
+    assert L.pins_solve_resume(None, None, ctypes.byref(prm), None, 0, None, None) == B.PINS_EINVAL
