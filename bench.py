@@ -13,9 +13,12 @@ solves all 64 pairs; value = solves per second over the timed steps.  Inputs
 are resident in HBM before the timed region starts.  The Newton CG multiplies
 by the full Hessian (matrix-free) in the first 15 outer iterations, while the
 plans are diffuse, and by the sparsified Hessian (CSR/CSC) after
-(--hvp-switch); three lanes (--lanes).
+(--hvp-switch).  The number of concurrent lanes is picked on the batch by the
+library's autotuner before the warm-up (--lanes fixes it instead).
 
 The JSON line also carries:
+  autotune     -- each lane count's time for one batched call (ms) and the
+                  count chosen;
   roofline     -- the dominant kernel class, its algorithmic work per launch
                   over its average launch time (HIP events on the solver's
                   stream, recorded by the library in the timed region);
@@ -98,8 +101,9 @@ def parse():
     ap.add_argument("--hvp-switch", type=int, default=15,
                     help="Hessian products of the Newton CG: matrix-free (full Hessian) in the outer iterations "
                          "k < this, sparsified (CSR) after; 0 = sparsified throughout")
-    ap.add_argument("--lanes", type=int, default=3,
-                    help="concurrent lanes of the batched call (params.streams); results do not depend on it")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="concurrent lanes of the batched call (params.streams); results do not depend on it. "
+                         "0 = the library's autotuner (pins_tune_batch_device) picks it on this batch, untimed")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the materialised-cost Sinkhorn sweep measurement (16384 x 16384 FP64 cost)")
     ap.add_argument("--sweep-only", action="store_true", help="only run the sweep measurements (materialised and streamed cost)")
@@ -202,7 +206,14 @@ def main():
         return kms, kwork, kcalls
 
     hess = dict(hvp=2, hvp_switch=args.hvp_switch) if args.hvp_switch > 0 else dict(hvp=0)
-    base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=args.lanes, **hess)
+    lanes, autotune = args.lanes, None
+    if lanes <= 0:
+        best, ms = ctx.tune_batch_device(probs, P.params(eta=args.eta, max_outer=args.K, precision=prec, **hess),
+                                         outs, max_lanes=4, reps=2, stream=st)
+        lanes = best
+        autotune = dict(lanes=best, ms_by_lanes=[round(v, 1) for v in ms], reps=2,
+                        searched="params.streams = 1..4 (launch schedule only; results do not depend on it)")
+    base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=lanes, **hess)
     share_ms, _, _ = aggregate([step(P.params(profile=1, **base))])
     dom = max(share_ms, key=share_ms.get)
     prm = P.params(profile=0 if args.no_profile else 1, profile_mask=1 << P.KERNEL_NAMES.index(dom), **base)
@@ -253,10 +264,10 @@ def main():
                 config=dict(workload="image-histogram pairs, 28x28 grid (m=n=784), squared grid distance/max "
                                      "streamed, eta=0.1, K=250, batched (one call per step)",
                             pairs=args.pairs, m=n, n=n, eta=args.eta, K=args.K, precision=args.precision,
-                            mode="batched", lanes=args.lanes,
+                            mode="batched", lanes=lanes,
                             hessian=("matrix-free full Hessian for outer iterations k < %d, sparsified (CSR) after"
                                      % args.hvp_switch) if args.hvp_switch > 0 else "sparsified (CSR)"),
-                roofline=roofline)
+                roofline=roofline, autotune=autotune)
 
     last = results[-1]
     line["iterations"] = dict(sinkhorn=[r["sinkhorn_iters"] for r in last][:4],
@@ -266,7 +277,7 @@ def main():
     if not args.no_variants:
         variants = {}
         other = P.FP64 if prec == P.MIXED else P.MIXED
-        prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other, streams=args.lanes, **hess)
+        prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other, streams=lanes, **hess)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         step(prm2)
@@ -287,7 +298,7 @@ def main():
         variants["batched_uneven_points"] = uneven_points(P, ctx, torch, np, dev, W, st)
         # Hessian products: sparsified throughout, and matrix-free throughout
         for key, hv in (("batched_sparsified_hvp_solves_per_s", 0), ("batched_matrix_free_hvp_solves_per_s", 1)):
-            prm3 = P.params(eta=args.eta, max_outer=args.K, precision=prec, streams=args.lanes, hvp=hv)
+            prm3 = P.params(eta=args.eta, max_outer=args.K, precision=prec, streams=lanes, hvp=hv)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             step(prm3)

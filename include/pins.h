@@ -245,6 +245,20 @@ int pins_solve_resume(pins_ctx* ctx, const pins_problem* prob, const pins_params
 int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
                             pins_result* res, void* stream);
 
+/* Autotuner over the batch schedule.  The number of concurrent lanes
+ * (params.streams) is the launch-schedule choice of pins_solve_batch_device
+ * that leaves every result bitwise unchanged, and its best value depends on
+ * the batch (how many instances, how uneven, how their Newton phases
+ * overlap).  For each lane count g = 1 .. max_lanes (at most 4) the batch is
+ * solved once untimed (workspace set-up) and then `reps` times, timed with the
+ * host clock (each solve returns when it has finished); ms[g-1] (when ms is
+ * non-NULL) receives the fastest of the reps and *best the fastest g.  The
+ * outputs in res (DEVICE arrays, as for pins_solve_batch_device) are those of
+ * the last solve.  Returns the batch's worst status; PINS_EINVAL for
+ * max_lanes outside [1, 4], reps < 1 or a NULL best. */
+int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
+                           int max_lanes, int reps, pins_result* res, void* stream, int32_t* best, double* ms);
+
 /* ---- Serving (continuous admission of requests onto concurrent batches) ----
  * A server owns `workers` (1..4) solver threads on HIP device `device`, each
  * with its own context and HIP stream.  A worker that becomes free takes every

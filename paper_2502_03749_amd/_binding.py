@@ -109,6 +109,9 @@ def lib():
                                         vp]
         L.pins_solve_resume.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(State),
                                         ctypes.c_int32, ctypes.POINTER(State), ctypes.POINTER(Result)]
+        L.pins_tune_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
+                                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(Result), vp,
+                                             ctypes.POINTER(ctypes.c_int32), _D]
         L.pins_solve_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
                                               ctypes.POINTER(Result), vp]
         L.pins_server_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
@@ -213,6 +216,15 @@ class Context:
         raw device pointers as ints); outs: list of dicts with alpha, beta and optional X (device).
         Returns (rc, [scalars per instance]).
         """
+        P, R = self._batch_args(problems, outs)
+        cnt = len(problems)
+        rc = self._check(lib().pins_solve_batch_device(self.h, P, cnt, ctypes.byref(prm), R,
+                                                       ctypes.c_void_p(stream or 0)))
+        return rc, [R[q].scalars() for q in range(cnt)]
+
+    @staticmethod
+    def _batch_args(problems, outs):
+        """Problem and Result arrays over device tensors (or raw device pointers)."""
         cnt = len(problems)
         P = (Problem * cnt)()
         R = (Result * cnt)()
@@ -230,9 +242,19 @@ class Context:
             R[q].beta = _ptr(outs[q]["beta"])
             if outs[q].get("X") is not None:
                 R[q].X = _ptr(outs[q]["X"])
-        rc = self._check(lib().pins_solve_batch_device(self.h, P, cnt, ctypes.byref(prm), R,
-                                                       ctypes.c_void_p(stream or 0)))
-        return rc, [R[q].scalars() for q in range(cnt)]
+        return P, R
+
+    def tune_batch_device(self, problems, prm: Params, outs, max_lanes=4, reps=2, stream=None):
+        """pins_tune_batch_device: the fastest lane count (params.streams) for this batch.
+
+        Same arguments as solve_batch_device.  Returns (best, [ms with 1 .. max_lanes lanes]).
+        """
+        P, R = self._batch_args(problems, outs)
+        best = ctypes.c_int32(0)
+        ms = (ctypes.c_double * max_lanes)()
+        self._check(lib().pins_tune_batch_device(self.h, P, len(problems), ctypes.byref(prm), max_lanes, reps, R,
+                                                 ctypes.c_void_p(stream or 0), ctypes.byref(best), ms))
+        return best.value, list(ms)
 
     def solve_device(self, problem, prm: Params, out, stream=None):
         cnt_rc, res = self.solve_batch_device([problem], prm, [out], stream)

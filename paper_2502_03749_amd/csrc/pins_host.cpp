@@ -949,4 +949,37 @@ int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count,
     });
 }
 
+int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
+                           int max_lanes, int reps, pins_result* res, void* stream, int32_t* best, double* ms) {
+    return guarded(ctx, [&] {
+        if (!probs || !p || !res || !best) fail(PINS_EINVAL, "null argument");
+        if (max_lanes < 1 || max_lanes > 4) fail(PINS_EINVAL, "max_lanes must be in [1, 4]");
+        if (reps < 1) fail(PINS_EINVAL, "reps must be >= 1");
+        using clk = std::chrono::steady_clock;
+        pins_params q = *p;
+        int rc = PINS_OK, best_g = 1;
+        double best_ms = 0.0;
+        for (int g = 1; g <= max_lanes; ++g) {
+            q.streams = g;
+            rc = solve_entry(ctx, probs, count, q, res, (hipStream_t)stream, false);
+            if (rc < 0) return rc;
+            double t = 0.0;
+            for (int r = 0; r < reps; ++r) {
+                const auto t0 = clk::now();
+                rc = solve_entry(ctx, probs, count, q, res, (hipStream_t)stream, false);
+                if (rc < 0) return rc;
+                const double e = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+                t = (r == 0) ? e : std::min(t, e);
+            }
+            if (ms) ms[g - 1] = t;
+            if (g == 1 || t < best_ms) {
+                best_ms = t;
+                best_g = g;
+            }
+        }
+        *best = best_g;
+        return rc;
+    });
+}
+
 }  // extern "C"
