@@ -535,7 +535,9 @@ def streamed_sweep(P, ctx, torch, np, dev, W, side=128, sweeps=7):
     events.  Nothing but the potentials moves through HBM, so the rate is the
     ALU's: entries per second (one exp each, float in mixed precision after an
     exponent formed in double, the table-driven double exp in FP64) and the
-    compute-unit cycles one entry takes (256 CUs at 2.4 GHz)."""
+    compute-unit cycles one entry takes (256 CUs at 2.4 GHz).  The measured
+    issue rate of the float exponential is reported beside it, with the mixed
+    sweeps' fraction of it."""
     pr = W.grid_pair("gmm", 0, s=side)
     m = n = side * side
     t = lambda v: torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev)
@@ -556,6 +558,14 @@ def streamed_sweep(P, ctx, torch, np, dev, W, side=128, sweeps=7):
                 ent[k] = dict(avg_launch_us=round(us, 2), entries_per_s=float("%.4g" % eps),
                               cu_cycles_per_entry=round(256 * 2.4e9 / eps, 3), launches=calls)
         res[name] = ent
+    # the ceiling: the measured issue rate of the float exponential (one per entry in mixed precision)
+    rate, kms = P.probe_exp_rate(0)
+    res["exp_probe"] = dict(exps_per_s=float("%.4g" % rate), per_cu_cycle=round(rate / (256 * 2.4e9), 2),
+                            kernel_ms=round(kms, 3),
+                            what="v_exp_f32 issue rate (pins_probe_exp_rate): 8 independent chains per thread, "
+                                 "one multiply per exponential")
+    for e in res["mixed"].values():
+        e["frac_of_exp_rate"] = round(e["entries_per_s"] / rate, 3)
     return dict(workload="%dx%d grid pair (m = n = %d), streamed cost, %d warm-up iterations" % (side, side, m, sweeps),
                 **res)
 

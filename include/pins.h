@@ -260,6 +260,17 @@ int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count,
 int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
                            int max_lanes, int reps, pins_result* res, void* stream, int32_t* best, double* ms);
 
+/* ---- Measurement support ----
+ * Issue rate of the hardware float exponential on HIP device `device`, the
+ * ALU ceiling of a streamed warm-up sweep (one exponential per cost entry,
+ * no cost bytes moved).  Launches `blocks` blocks of 256 threads, each thread
+ * running 8 independent chains of `iters` exponentials (one multiply each),
+ * timed with HIP events on the null stream; *exps_per_s receives the rate and
+ * *ms (when non-NULL) the kernel time.  Allocates and frees its own small
+ * buffer.  PINS_EINVAL for blocks or iters outside [1, 2^20] or a NULL
+ * exps_per_s; PINS_EDEVICE / PINS_ENOMEM on runtime failure. */
+int pins_probe_exp_rate(int device, int blocks, int iters, double* exps_per_s, double* ms);
+
 /* ---- Serving (continuous admission of requests onto concurrent batches) ----
  * A server owns `workers` (1..4) solver threads on HIP device `device`, each
  * with its own context and HIP stream.  A worker that becomes free takes every

@@ -112,6 +112,7 @@ def lib():
         L.pins_tune_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
                                              ctypes.c_int, ctypes.c_int, ctypes.POINTER(Result), vp,
                                              ctypes.POINTER(ctypes.c_int32), _D]
+        L.pins_probe_exp_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D]
         L.pins_solve_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
                                               ctypes.POINTER(Result), vp]
         L.pins_server_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
@@ -359,6 +360,15 @@ def _ptr(t):
             raise TypeError("device arrays must be float64")
         return t.data_ptr()
     raise TypeError("unsupported array type %r" % type(t))
+
+
+def probe_exp_rate(device: int = 0, blocks: int = 8192, iters: int = 4096):
+    """pins_probe_exp_rate: (float exponentials per second, kernel ms)."""
+    rate, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().pins_probe_exp_rate(device, blocks, iters, ctypes.byref(rate), ctypes.byref(ms))
+    if rc != PINS_OK:
+        raise PinsError(rc, "pins_probe_exp_rate failed")
+    return rate.value, ms.value
 
 
 def workspace_bytes(problems, prm: Params) -> int:

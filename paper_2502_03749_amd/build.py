@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpins.so")
-SOURCES = ["pins_kernels.hip", "pins_host.cpp", "pins_server.cpp"]
+SOURCES = ["pins_kernels.hip", "pins_host.cpp", "pins_server.cpp", "pins_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

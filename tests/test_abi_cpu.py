@@ -105,3 +105,16 @@ def test_entry_points_reject_a_null_context():
     best = ctypes.c_int32(0)
     assert L.pins_tune_batch_device(None, None, 1, ctypes.byref(prm), 4, 1, None, None, ctypes.byref(best),
                                     None) == B.PINS_EINVAL
+
+
+def test_exp_probe_argument_checks():
+    """pins_probe_exp_rate rejects bad sizes before touching a device; without a GPU it reports a device error."""
+    import torch
+
+    rate = ctypes.c_double(0.0)
+    L = P.lib()
+    assert L.pins_probe_exp_rate(0, 0, 16, ctypes.byref(rate), None) == B.PINS_EINVAL
+    assert L.pins_probe_exp_rate(0, 8, 0, ctypes.byref(rate), None) == B.PINS_EINVAL
+    assert L.pins_probe_exp_rate(0, 8, 16, None, None) == B.PINS_EINVAL
+    if not torch.cuda.is_available():
+        assert L.pins_probe_exp_rate(0, 8, 16, ctypes.byref(rate), None) == B.PINS_EDEVICE

@@ -1,4 +1,4 @@
-"""The batch autotuner (pins_tune_batch_device) through the C ABI.
+"""The batch autotuner (pins_tune_batch_device) and the exponential probe through the C ABI.
 
 The lane count it searches is a launch-schedule choice only: the batch solved
 with any count must give bitwise the single-lane results, and the tuner's own
@@ -75,3 +75,13 @@ def test_tuner_rejects_bad_arguments(ctx):
         with pytest.raises(P.PinsError) as e:
             ctx.tune_batch_device(probs[:2], prm, outs[:2], **kw)
         assert e.value.code == P._binding.PINS_EINVAL
+
+
+def test_exp_probe_rate_is_plausible():
+    """The exponential probe runs and gives a rate between 1 and 64 float exponentials per
+    compute-unit cycle (256 CUs at 2.4 GHz); 64 (4 SIMDs x 16 lanes) is the full VALU rate."""
+    print("case exp probe", flush=True)
+    rate, ms = P.probe_exp_rate(0, blocks=2048, iters=1024)
+    assert ms > 0.0
+    per_cu_cycle = rate / (256 * 2.4e9)
+    assert 1.0 <= per_cu_cycle <= 64.0, per_cu_cycle
