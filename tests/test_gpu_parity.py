@@ -300,20 +300,23 @@ def test_int32_index_storage_parity(ctx, precision):
         assert g["rc"] == 0 and rel <= 1e-6 and g["resid"] <= 1e-10
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_full_size_batch_sampled_parity(ctx, precision):
+@pytest.mark.parametrize("precision,hvp_switch", [("mixed", 15), ("fp64", 15), ("mixed", 0)])
+def test_full_size_batch_sampled_parity(ctx, precision, hvp_switch):
     """The benchmarked configuration itself: 64 pairs of 28x28 histograms, grid
-    cost, eta = 0.1, K = 250, one batched call.  Every instance converges
-    (status OK, marginal residual <= 1e-10, gauge); two sampled pairs match the
-    oracle at the same K (mixed <= 1e-6, FP64 <= 1e-9 relative cost)."""
+    cost, eta = 0.1, K = 250, one batched call over three lanes, with the timed
+    Hessian schedule (matrix-free products for the first 15 outer iterations,
+    sparsified after) and with sparsified products throughout.  Every instance
+    converges (status OK, marginal residual <= 1e-10, gauge); two sampled pairs
+    match the oracle at the same K (mixed <= 1e-6, FP64 <= 1e-9 relative cost)."""
     s, K, eta = 28, 250, 0.1
     n = s * s
-    print("case full-size batch 64 x %dx%d %s" % (n, n, precision), flush=True)
+    print("case full-size batch 64 x %dx%d %s switch %d" % (n, n, precision, hvp_switch), flush=True)
     pairs = [W.blob_pair(i, s=s) for i in range(64)]
     probs = [dict(kind=P.COST_GRID, m=n, n=n, grid_s=s, a=_t(p["a"]), b=_t(p["b"])) for p in pairs]
     outs = [dict(alpha=torch.empty(n, dtype=torch.float64, device=DEV),
                  beta=torch.empty(n, dtype=torch.float64, device=DEV)) for _ in pairs]
-    prm = P.params(eta=eta, max_outer=K, precision=P.MIXED if precision == "mixed" else P.FP64)
+    hess = dict(hvp=2, hvp_switch=hvp_switch) if hvp_switch > 0 else dict(hvp=0)
+    prm = P.params(eta=eta, max_outer=K, precision=P.MIXED if precision == "mixed" else P.FP64, streams=3, **hess)
     rc, rs = ctx.solve_batch_device(probs, prm, outs, stream=torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert rc == 0
