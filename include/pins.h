@@ -253,7 +253,9 @@ int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count,
  * overlap).  For each lane count g = 1 .. max_lanes (at most 4) the batch is
  * solved once untimed (workspace set-up) and then `reps` times, timed with the
  * host clock (each solve returns when it has finished); ms[g-1] (when ms is
- * non-NULL) receives the fastest of the reps and *best the fastest g.  The
+ * non-NULL) receives the fastest of the reps and *best the fastest g.  Counts
+ * above `count` are not tried (a batch runs on at most `count` lanes) and get
+ * ms[g-1] = 0.  The
  * outputs in res (DEVICE arrays, as for pins_solve_batch_device) are those of
  * the last solve.  Returns the batch's worst status; PINS_EINVAL for
  * max_lanes outside [1, 4], reps < 1 or a NULL best. */

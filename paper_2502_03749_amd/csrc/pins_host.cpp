@@ -956,10 +956,15 @@ int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, 
         if (max_lanes < 1 || max_lanes > 4) fail(PINS_EINVAL, "max_lanes must be in [1, 4]");
         if (reps < 1) fail(PINS_EINVAL, "reps must be >= 1");
         using clk = std::chrono::steady_clock;
+        if (count < 1) fail(PINS_EINVAL, "count must be >= 1");
         pins_params q = *p;
         int rc = PINS_OK, best_g = 1;
         double best_ms = 0.0;
-        for (int g = 1; g <= max_lanes; ++g) {
+        // a batch runs on at most `count` lanes: larger counts are not tried
+        const int gmax = std::min(max_lanes, count);
+        if (ms)
+            for (int g = gmax; g < max_lanes; ++g) ms[g] = 0.0;
+        for (int g = 1; g <= gmax; ++g) {
             q.streams = g;
             rc = solve_entry(ctx, probs, count, q, res, (hipStream_t)stream, false);
             if (rc < 0) return rc;

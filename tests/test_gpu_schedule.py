@@ -67,6 +67,14 @@ def test_tuner_picks_a_lane_count_and_keeps_results(ctx):
         assert r1["cost"] == r2["cost"] and r1["resid"] == r2["resid"]
 
 
+def test_tuner_tries_no_more_lanes_than_instances(ctx):
+    print("case tuner 2 instances", flush=True)
+    probs, outs = _batch()
+    best, ms = ctx.tune_batch_device(probs[:2], P.params(eta=0.03, max_outer=2), outs[:2], max_lanes=4, reps=1)
+    torch.cuda.synchronize()
+    assert best in (1, 2) and ms[0] > 0 and ms[1] > 0 and ms[2] == 0.0 and ms[3] == 0.0
+
+
 def test_tuner_rejects_bad_arguments(ctx):
     print("case tuner bad arguments", flush=True)
     probs, outs = _batch()
