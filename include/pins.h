@@ -231,8 +231,8 @@ typedef struct {
  * solve.  The outputs in *res describe the plan after `stop` iterations
  * (eps = eta/stop, outer_iters = stop); the iteration counters and kern_*
  * cover this call only.  Before iteration K-1 has run, a subproblem that hit
- * T2 shows as flags bit1, never as PINS_NOT_CONVERGED.  Needs the implicit shift (else PINS_EUNSUPPORTED).
- * PINS_EINVAL when stop > K, when from does not match the problem's m and n,
+ * T2 shows as flags bit1, never as PINS_NOT_CONVERGED.  Needs the implicit
+ * shift (else PINS_EUNSUPPORTED).  PINS_EINVAL when stop > K, when from does not match the problem's m and n,
  * when from->outer_done is not in [1, stop) or from has a NULL or non-finite
  * array, or when save has a NULL array; nothing is written then. */
 int pins_solve_resume(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, const pins_state* from,
