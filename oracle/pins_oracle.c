@@ -319,8 +319,10 @@ int oracle_pins_trace(int m, int n, const double* C, const double* a, const doub
             }
             if (t == p->T2) break;
 
-            /* Sparsify(Hessian, rho): first threshold level whose kept count fits the budget */
-            lev = p->rho_levels - 1;
+            /* Sparsify(Hessian, rho): first threshold level whose kept count fits
+             * the budget; when none does, no entry is kept (lev = rho_levels,
+             * threshold +inf) and the Newton system is its diagonal */
+            lev = p->rho_levels;
             for (l = 0; l < p->rho_levels; ++l) {
                 double rl = p->rho * pow(10.0, (double)l);
                 nnz = 0;
@@ -335,7 +337,7 @@ int oracle_pins_trace(int m, int n, const double* C, const double* a, const doub
                 }
             }
             {
-                double rl = p->rho * pow(10.0, (double)lev);
+                double rl = (lev < p->rho_levels) ? p->rho * pow(10.0, (double)lev) : INFINITY;
                 nnz = 0;
                 rp[0] = 0;
                 for (i = 0; i < m; ++i) {

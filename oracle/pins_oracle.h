@@ -33,7 +33,7 @@ typedef struct {
     int ls_max;        /* number of trial step sizes 1, beta, beta^2, ... */
     double rho;        /* Sparsify: keep Xt_ij >= rho*10^l*min(a_i,b_j), for the */
     double budget;     /* smallest level l in [0, rho_levels) with nnz <= budget*(m+n-1) */
-    int rho_levels;    /* (the densest retained set that fits the budget) */
+    int rho_levels;    /* (the densest retained set that fits the budget); no level fitting: nothing kept */
 } oracle_params;
 
 typedef struct {
