@@ -57,13 +57,16 @@ typedef enum {
 } pins_cost_kind;
 
 typedef enum {
-    PINS_FP64 = 0, /* every step in double precision */
-    PINS_MIXED = 1 /* Sinkhorn warm-up sweeps evaluate exp and accumulate the
-                      log-sum-exp in float (exponent formed in double); the CG
-                      stores the kept entries of the sparsified Hessian in
-                      float, and matrix-free products evaluate X~ with a float
-                      exp; gradients, CG vectors and sums, line search,
-                      potentials and outputs stay double */
+    PINS_FP64 = 0,      /* every step in double precision */
+    PINS_MIXED = 1,     /* Sinkhorn warm-up sweeps evaluate exp and accumulate the
+                           log-sum-exp in float (exponent formed in double);
+                           everything else -- the Newton passes and gradients,
+                           the sparsified Hessian and its CG, line search,
+                           potentials and outputs -- in double */
+    PINS_MIXED_FAST = 2 /* PINS_MIXED, and in addition the CG stores the kept
+                           entries of the sparsified Hessian in float and
+                           matrix-free products evaluate X~ with a float exp
+                           (CG vectors and sums stay double) */
 } pins_precision;
 
 typedef enum {
@@ -92,7 +95,9 @@ typedef struct {
     int32_t ls_max;       /* number of trial steps 1, beta, ..., beta^(ls_max-1) */
     int32_t rho_levels;   /* Sparsify levels tried: thresholds rho * 10^l, l < rho_levels */
     double rho;           /* Sparsify keeps Xt_ij >= rho*10^l*min(a_i,b_j) for the smallest */
-    double budget;        /* level l whose count is <= budget*(m+n-1) */
+    double budget;        /* level l whose count is <= budget*(m+n-1); when no level is
+                             within that budget no entry is kept (the Newton system is its
+                             diagonal) */
     int32_t precision;    /* pins_precision */
     int32_t shift_mode;   /* pins_shift_mode */
     int32_t profile;      /* nonzero: time every kernel launch with HIP events (pins_result.kern_*) */
@@ -289,8 +294,9 @@ int pins_server_create(int device, int workers, int max_batch, size_t hbm_budget
                        pins_server** out);
 /* Queue one problem given by HOST pointers (copied before the call returns);
  * *ticket identifies it.  PINS_EINVAL for an invalid problem (shape, kind,
- * marginals not positive, finite and summing to 1 within 1e-10) or a stopping
- * server; the dense cost's finiteness is checked when its batch runs. */
+ * marginals not positive, finite and summing to 1 within 1e-10, a dense cost
+ * or point coordinates with a non-finite entry) or a stopping server, so that
+ * no admitted request can fail the batch it joins. */
 int pins_server_submit(pins_server* s, const pins_problem* prob, int64_t* ticket);
 /* Block until the ticket's solve has finished; fill *res (scalars; alpha and
  * beta copied to res->alpha / res->beta when non-NULL, HOST arrays of m and n

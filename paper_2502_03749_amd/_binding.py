@@ -24,7 +24,7 @@ PINS_ENUMERIC = -4
 PINS_EUNSUPPORTED = -5
 
 COST_DENSE, COST_POINTS, COST_GRID = 0, 1, 2
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_FAST = 0, 1, 2
 SHIFT_IMPLICIT, SHIFT_MATERIALIZED = 0, 1
 NKERN = 16
 KERNEL_NAMES = ["row_lse", "col_lse", "col_merge", "grad", "grad_merge", "fill", "csc", "pcg", "ls", "update",

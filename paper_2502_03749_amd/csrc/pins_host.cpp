@@ -158,6 +158,15 @@ struct Batch {
 
 constexpr int SCRATCH_BLK = 512;
 
+// The CG an instance takes and how its S is stored (DevInst::cgfmt), from its
+// sizes alone: the wide CG above WCG_MAX_N rows and columns together, with
+// uint16 indices (2 bytes an entry; the wide products stream S from memory)
+// when every index fits; else int32 byte offsets (no unpacking in the gather).
+int cg_format(int m, int n) {
+    if (m + n <= WCG_MAX_N) return 0;
+    return 1 | ((m <= 65536 && n <= 65536) ? 2 : 0);
+}
+
 Batch plan_batch(const pins_problem* probs, int count, const pins_params& p, bool host_api, const pins_result* res) {
     Batch B;
     Carver cv;
@@ -196,7 +205,8 @@ void check_params(const pins_params& p) {
     if (p.rho_levels < 1 || p.rho_levels > NLEV) fail(PINS_EINVAL, "rho_levels must be in [1, 16]");
     if (!(p.rho > 0.0) || !std::isfinite(p.rho) || !(p.budget > 0.0) || !std::isfinite(p.budget))
         fail(PINS_EINVAL, "rho and budget must be positive and finite");
-    if (p.precision != PINS_FP64 && p.precision != PINS_MIXED) fail(PINS_EINVAL, "unknown precision");
+    if (p.precision != PINS_FP64 && p.precision != PINS_MIXED && p.precision != PINS_MIXED_FAST)
+        fail(PINS_EINVAL, "unknown precision");
     if (p.shift_mode != PINS_SHIFT_IMPLICIT && p.shift_mode != PINS_SHIFT_MATERIALIZED)
         fail(PINS_EINVAL, "unknown shift_mode");
     if (p.hvp < 0 || p.hvp > 2) fail(PINS_EINVAL, "hvp must be 0 (sparsified), 1 (matrix-free) or 2 (switch)");
@@ -324,23 +334,14 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     ctx->profile_mask = p.profile_mask;
     ctx->ev_used = 0;
 
-    // marginals are validated on the host (device arrays are copied back first)
-    {
-        std::vector<double> hb;
+    // host marginals are validated here, before any copy; device marginals by
+    // the set-up kernel on the solve's stream (ordered after the caller's work
+    // on it), read back with the set-up's control blocks
+    if (host_api)
         for (int q = 0; q < count; ++q) {
-            const pins_problem& P = probs[q];
-            if (host_api) {
-                check_marginal(P.a, P.m, "a");
-                check_marginal(P.b, P.n, "b");
-            } else {
-                hb.resize(std::max(P.m, P.n));
-                HIPCHK(hipMemcpy(hb.data(), P.a, sizeof(double) * P.m, hipMemcpyDeviceToHost));
-                check_marginal(hb.data(), P.m, "a");
-                HIPCHK(hipMemcpy(hb.data(), P.b, sizeof(double) * P.n, hipMemcpyDeviceToHost));
-                check_marginal(hb.data(), P.n, "b");
-            }
+            check_marginal(probs[q].a, probs[q].m, "a");
+            check_marginal(probs[q].b, probs[q].n, "b");
         }
-    }
 
     const Batch B = plan_batch(probs, count, p, host_api, res);
     char* ws = workspace(ctx, B.total);
@@ -387,6 +388,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         I.nrb = L.nrb;
         I.ncb = L.ncb;
         I.nnz_cap = L.cap;
+        I.cgfmt = cg_format(L.m, L.n);
         I.ldc = L.n;
         I.a = da;
         I.b = db;
@@ -429,7 +431,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         I.val = Dp(L.val);
         I.colptr = Ip(L.colptr);
         I.rowT = Ip(L.rowT);
-        I.valT = Dp(L.valT);  // reinterpreted by the kernels per LaunchCtx::sp_fmt
+        I.valT = Dp(L.valT);  // reinterpreted by the kernels per cgfmt and LaunchCtx::sp_f32
         I.rowbin = Ip(L.rowbin);
         if (host_api) {
             I.alpha = Dp(L.alpha);
@@ -451,7 +453,8 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         std::memcpy(ho, B.toff.data(), sizeof(int) * (count + 1));
         std::memcpy(ho + count + 1, B.roff.data(), sizeof(int) * (count + 1));
         HIPCHK(hipMemcpyAsync(ws + B.offs, ho, sizeof(int) * 2 * (count + 1), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemsetAsync(d_ctrl, 0, sizeof(Ctrl) * count, st));
+        launch_zero(st, d_ctrl, sizeof(Ctrl) * count);
+        HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));  // the pinned staging area is reused by readback()
     }
 
@@ -467,12 +470,22 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     L.max_tiles = B.max_tiles;
     L.total_tiles = B.toff.back();
     L.total_rowblk = B.roff.back();
-    // the CG's copy of S: 16-bit indices whenever they fit, float values in
-    // mixed precision (the CG vectors and all sums stay double)
-    // uint16 indices (2 bytes an entry) for the wide CG, whose products stream S
-    // from memory; int32 byte offsets (no unpacking in the gather) otherwise
-    const bool u16 = B.max_mn > pins::WCG_MAX_N && B.max_m <= 65536 && B.max_n <= 65536;
-    L.sp_fmt = (u16 ? 1 : 0) | (p.precision == PINS_MIXED ? 2 : 0);
+    // the CG's copy of S: float values in the fast-mixed precision only (the
+    // CG vectors and all sums stay double); the CG kinds present in the batch
+    L.sp_f32 = p.precision == PINS_MIXED_FAST ? 1 : 0;
+    L.any_small = L.any_wide16 = L.any_wide32 = false;
+    L.max_mn_small = 0;
+    for (int q = 0; q < count; ++q) {
+        const int f = hI[q].cgfmt;
+        if (!(f & 1)) {
+            L.any_small = true;
+            L.max_mn_small = std::max(L.max_mn_small, hI[q].m + hI[q].n);
+        } else if (f & 2) {
+            L.any_wide16 = true;
+        } else {
+            L.any_wide32 = true;
+        }
+    }
     KP& kp = L.kp;
     std::memset(&kp, 0, sizeof(kp));
     kp.eta = p.eta;
@@ -505,8 +518,15 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     setup.end();
     {
         const Ctrl* h = readback(ctx, st, d_ctrl, count);
-        for (int q = 0; q < count; ++q)
-            if (h[q].nonfinite) fail(PINS_EINVAL, "C has non-finite entries (instance " + std::to_string(q) + ")");
+        for (int q = 0; q < count; ++q) {
+            const std::string at = " (instance " + std::to_string(q) + ")";
+            const int mb = h[q].margbad;
+            if (mb & 1) fail(PINS_EINVAL, "a must be positive and finite" + at);
+            if (mb & 2) fail(PINS_EINVAL, "a must sum to 1 (|sum-1| <= 1e-10)" + at);
+            if (mb & 4) fail(PINS_EINVAL, "b must be positive and finite" + at);
+            if (mb & 8) fail(PINS_EINVAL, "b must sum to 1 (|sum-1| <= 1e-10)" + at);
+            if (h[q].nonfinite) fail(PINS_EINVAL, "C has non-finite entries" + at);
+        }
     }
     // resume: the saved (F, G, A, B), kappa = k (k + 1 after the coming shift)
     // and the earlier-subproblem flag replace what the initialisation wrote
@@ -530,7 +550,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         }
     }
 
-    const bool f32 = p.precision == PINS_MIXED;
+    const bool f32 = p.precision != PINS_FP64;  // float warm-up sweeps
     // matrix-free Hessian products (no Sparsify) in outer iteration k
     auto matrix_free = [&](int k) { return p.hvp == 1 || (p.hvp == 2 && k < p.hvp_switch); };
     const int K = p.max_outer;
@@ -582,9 +602,11 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
             run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
             run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, false); });
             if (!mf) run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
-            if (!mf && !wide_cg(L)) {
-                run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
-            } else {
+            // sparsified products: the one-block CG for the instances with m + n <=
+            // WCG_MAX_N and the wide CG for the others (the choice is each
+            // instance's own); matrix-free products: the wide CG for every instance
+            if (!mf && L.any_small) run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
+            if (mf || L.any_wide16 || L.any_wide32) {
                 // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
                 const int hsrc = mf ? src : -1;
                 run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_begin(L, hsrc); });

@@ -19,6 +19,7 @@
 namespace pins {
 
 constexpr int NLEV = 16;     // maximum number of Sparsify levels
+constexpr int LEV_NONE = 1 << 20;  // Sparsify level meaning "keep no entry" (no level fits the budget)
 constexpr int LS_T = 8;      // trial step sizes per line-search pass (after the first)
 constexpr int TILE_C = 256;  // columns per tile (one per thread)
 constexpr int TILE_RMAX = 16;  // maximum rows per tile
@@ -40,7 +41,10 @@ struct DevInst {
     int R;        // rows per tile of the tile kernels (<= TILE_RMAX)
     int nrb, ncb; // row blocks (ceil(m/R)), column blocks (ceil(n/TILE_C))
     int nnz_cap;  // capacity of the CSR/CSC arrays
-    int pad0;
+    int cgfmt;    // CG of this instance: bit 0 set = the wide CG (m + n > WCG_MAX_N), else the
+                  // one-block CG; bit 1 set = uint16 indices in S and S^T (wide CG with m, n <= 65536),
+                  // else int32 byte offsets.  A function of (m, n) only, so an instance takes the
+                  // same CG and storage alone and in any batch
     long ldc;                 // leading dimension of csrc / cbase
     const double* csrc;       // exponent cost source: C (implicit) or C^k (materialised)
     double cscale;            // scale applied to csrc entries
@@ -68,10 +72,11 @@ struct DevInst {
     // S (CSR) and S^T (CSC).  Every row of S and of S^T starts at a multiple
     // of 4 entries and is padded to one with (index 0, value 0), so the CG
     // reads them in aligned quads; within a row of nq quads the quads are
-    // stored transposed (component u of quad q holds the row's entry u*nq + q).  Index arrays hold uint16 when every index
-    // of the batch is < 65536, else int32; value arrays hold float in mixed
-    // precision, else double (the launch chooses; the buffers are sized for
-    // int32/double).  nnz_cap (a multiple of 4) includes the padding.
+    // stored transposed (component u of quad q holds the row's entry u*nq + q).
+    // nnz_cap (a multiple of 4) includes the padding.
+    // Index arrays hold uint16 or int32 per instance (cgfmt bit 1); value arrays
+    // hold float in the fast-mixed precision, else double (the buffers are sized
+    // for int32/double).
     int* rowptr;    // m+1
     void* col;      // nnz_cap column indices of S
     void* val;      // nnz_cap values of S
@@ -97,7 +102,9 @@ struct Ctrl {
     double work[8];  // matrix entries visited per pass kind (W_* below); W_CG: stored entries read by CG
     int binoff[16];  // rowbin offsets: NBIN bins of rows of S, then NBIN bins of rows of S^T; [2 NBIN] = m+n
     int cg_it, cg_on;        // wide CG (many blocks per instance): iterations, still iterating
-    int decided, pad3;       // 1: the next round's gradient already merged and decided (after the fused trial)
+    int decided;             // 1: the next round's gradient already merged and decided (after the fused trial)
+    int margbad;             // set up: bit 0 a has an entry <= 0 or non-finite, bit 1 |sum a - 1| > 1e-10,
+                             // bits 2, 3 the same for b
     double cg_rzs[2], cg_bnorm;  // wide CG: <res, z> of iteration t in cg_rzs[t & 1]; ||rhs||
 };
 

@@ -716,7 +716,9 @@ __global__ __launch_bounds__(256) void k_grad_decide(const DevInst* __restrict__
         __syncthreads();
         if (threadIdx.x == 0) {
             const double lim = kp.budget * (double)(m + n - 1);
-            int lev = nlev - 1;
+            // no level within the budget: keep no entry (the Newton system is
+            // then its diagonal), never a kept set the CSR/CSC arrays cannot hold
+            int lev = LEV_NONE;
             long cum = 0;
             // count kept at level l = sum_{l' >= l} tot[l']; smallest l within the budget
             long kept[NLEV];
@@ -952,7 +954,7 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
 __device__ __forceinline__ void put_ix(unsigned short* p, int slot, int k, int) { p[slot] = (unsigned short)k; }
 __device__ __forceinline__ void put_ix(int* p, int slot, int k, int o) { p[slot] = 8 * (o + k); }
 
-template <class Src, class IX, class VT>
+template <class Src, class VT>
 __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const BlkRef br = blk_ref(kp.toff, kp.count);
     const int b = br.b, tl = br.l;
@@ -979,6 +981,13 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     const bool valid = j < n;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double lev = (double)ctrl[b].level, kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
+    const bool u16 = (I.cgfmt & 2) != 0;  // index storage of this instance (uniform over the block)
+    auto put = [&](void* arr, int slot, int k, int o) {
+        if (u16)
+            put_ix(static_cast<unsigned short*>(arr), slot, k, o);
+        else
+            put_ix(static_cast<int*>(arr), slot, k, o);
+    };
     const Src src(I);
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
     int ce = 0, cstart = 0, cnq = 0;  // entry index within column j, its start and quad count
@@ -1017,12 +1026,12 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
             const int nq = sNq[r];
             if (e < 4 * nq) {
                 const int slot = quad_slot(sStart[r], nq, e);
-                put_ix(static_cast<IX*>(I.col), slot, j, m);
+                put(I.col, slot, j, m);
                 static_cast<VT*>(I.val)[slot] = v;
             }
             if (ce < 4 * cnq) {
                 const int slot = quad_slot(cstart, cnq, ce);
-                put_ix(static_cast<IX*>(I.rowT), slot, i0 + r, 0);
+                put(I.rowT, slot, i0 + r, 0);
                 static_cast<VT*>(I.valT)[slot] = v;
             }
             ++ce;
@@ -1033,14 +1042,14 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     if (rb == I.nrb - 1 && valid)
         for (; ce < 4 * cnq; ++ce) {
             const int slot = quad_slot(cstart, cnq, ce);
-            put_ix(static_cast<IX*>(I.rowT), slot, 0, 0);
+            put(I.rowT, slot, 0, 0);
             static_cast<VT*>(I.valT)[slot] = (VT)0;
         }
     if (cb == I.ncb - 1 && (int)threadIdx.x < rows) {
         const int r = threadIdx.x, nq = sNq[r];
         for (int e = sE0[r] + wc[r][0] + wc[r][1] + wc[r][2] + wc[r][3]; e < 4 * nq; ++e) {
             const int slot = quad_slot(sStart[r], nq, e);
-            put_ix(static_cast<IX*>(I.col), slot, 0, m);
+            put(I.col, slot, 0, m);
             static_cast<VT*>(I.val)[slot] = (VT)0;
         }
     }
@@ -1238,7 +1247,7 @@ __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab,
 template <int EPT, class IX, class VT>
 __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.x;
-    if (ctrl[b].phase != PH_NEWTON) return;
+    if (ctrl[b].phase != PH_NEWTON || (insts[b].cgfmt & 1)) return;  // wide instances take the wide CG
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
     // LDS: sp, the direction p on the rows and D_c^-1 S^T p on the columns;
@@ -1406,10 +1415,18 @@ __device__ __forceinline__ void spmv_range(const DevInst& I, int m, const int* b
 }
 
 // rhs, x = 0, D_c^-1 b_2 into p's column part; ||rhs||
+// Instances that take part: every one with matrix-free products (dense = 1),
+// else those whose cgfmt selects the wide CG.
+__device__ __forceinline__ bool wcg_member(const DevInst& I, int dense) { return dense || (I.cgfmt & 1); }
+
 __global__ __launch_bounds__(1024) void k_wcg_begin(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
                                                     int dense) {
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
+    if (!wcg_member(insts[b], dense)) {
+        if (threadIdx.x == 0) ctrl[b].cg_on = 0;
+        return;
+    }
     if (dense && threadIdx.x == 0) ctrl[b].nnz = insts[b].m * insts[b].n;  // a product reads every entry
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
@@ -1444,6 +1461,9 @@ __global__ __launch_bounds__(WCG_NT) void k_wcg_half(const DevInst* __restrict__
     const int b = blockIdx.y;
     if (ctrl[b].phase != PH_NEWTON || (!final && !ctrl[b].cg_on)) return;
     const DevInst& I = insts[b];
+    // wide instances whose index storage is this launch's
+    constexpr int ix16 = sizeof(IX) == 2 ? 2 : 0;
+    if (!(I.cgfmt & 1) || (I.cgfmt & 2) != ix16) return;
     const int m = I.m, N = m + I.n;
     const int* bo = ctrl[b].binoff + (cols ? NBIN : 0);
     const int lo = bo[0] + blockIdx.x * WCG_ROWS;
@@ -1474,9 +1494,10 @@ __global__ __launch_bounds__(WCG_NT) void k_wcg_half(const DevInst* __restrict__
 }
 
 // after S D_c^-1 b_2: residual, preconditioned residual, first direction
-__global__ __launch_bounds__(1024) void k_wcg_start(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+__global__ __launch_bounds__(1024) void k_wcg_start(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                    int dense) {
     const int b = blockIdx.x;
-    if (ctrl[b].phase != PH_NEWTON) return;
+    if (ctrl[b].phase != PH_NEWTON || !wcg_member(insts[b], dense)) return;
     const DevInst& I = insts[b];
     const int m = I.m, N = m + I.n;
     double* __restrict__ res = I.cgw;
@@ -1677,9 +1698,10 @@ __global__ __launch_bounds__(256) void k_mf_merge(const DevInst* __restrict__ in
 }
 
 // y = D_c^-1 (b_2 - S^T x) and the line-search inputs
-__global__ __launch_bounds__(1024) void k_wcg_finish(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+__global__ __launch_bounds__(1024) void k_wcg_finish(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
+                                                     int dense) {
     const int b = blockIdx.x;
-    if (ctrl[b].phase != PH_NEWTON) return;
+    if (ctrl[b].phase != PH_NEWTON || !wcg_member(insts[b], dense)) return;
     const DevInst& I = insts[b];
     const int m = I.m, N = m + I.n;
     const double* __restrict__ bv = I.cgw + N;
@@ -2005,7 +2027,10 @@ __global__ __launch_bounds__(256) void k_shift_dense(const DevInst* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// setup: log marginals, initial duals (f = g = 0), X^0 = a b^T.
+// setup: log marginals, initial duals (f = g = 0), X^0 = a b^T; the marginals
+// checked against eq. (ot)'s domain (every entry positive and finite, each
+// sum 1 within 1e-10) into Ctrl::margbad, read back by the host before any
+// iteration runs.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_init(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.x;
@@ -2013,23 +2038,42 @@ __global__ __launch_bounds__(1024) void k_init(const DevInst* __restrict__ insts
     const int m = I.m, N = I.m + I.n;
     const double eta = kp.eta;
     const bool mat = kp.shift_mode != 0;
+    __shared__ double sh[32];
+    __shared__ int sbad;
+    if (threadIdx.x == 0) sbad = 0;
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+    int bad = 0;
     for (int k = threadIdx.x; k < N; k += 1024) {
         if (k < m) {
-            const double la = log(I.a[k]);
+            const double av = I.a[k];
+            if (!(av > 0.0) || !isfinite(av)) bad |= 1;
+            sa += av;
+            const double la = log(av);
             I.loga[k] = la;
             I.Ah[k] = eta * la;
             I.F[k] = mat ? -eta : eta * la - eta;
         } else {
-            const double lb = log(I.b[k - m]);
+            const double bv = I.b[k - m];
+            if (!(bv > 0.0) || !isfinite(bv)) bad |= 4;
+            sb += bv;
+            const double lb = log(bv);
             I.logb[k - m] = lb;
             I.Bh[k - m] = eta * lb;
             I.G[k - m] = mat ? 0.0 : eta * lb;
         }
     }
+    if (bad) atomicOr(&sbad, bad);
     for (int t = threadIdx.x; t < NLEV; t += 1024) I.hist[t] = 0;
+    sa = block_sum<1024>(sa, sh);  // its barriers also order the LDS flag
+    sb = block_sum<1024>(sb, sh);
     if (threadIdx.x == 0) {
         Ctrl& S = ctrl[b];
-        S.phase = S.nonfinite ? PH_DONE : (kp.T1 > 0 ? PH_WARM : PH_NEWTON);
+        int mb = sbad;
+        if (!(fabs(sa - 1.0) <= 1e-10)) mb |= 2;
+        if (!(fabs(sb - 1.0) <= 1e-10)) mb |= 8;
+        S.margbad = mb;
+        S.phase = (S.nonfinite || mb) ? PH_DONE : (kp.T1 > 0 ? PH_WARM : PH_NEWTON);
         S.kappa = 1.0;
     }
 }
@@ -2332,9 +2376,9 @@ void launch_grad_merge(const LaunchCtx& L, bool early) {
     hipLaunchKernelGGL(k_grad_decide, dim3(L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, early ? 1 : 0);
 }
 
-template <class IX, class VT>
+template <class VT>
 static void launch_fill_t(const LaunchCtx& L, int src, dim3 g) {
-#define K_(S) hipLaunchKernelGGL((k_fill<S, IX, VT>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
+#define K_(S) hipLaunchKernelGGL((k_fill<S, VT>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp)
     PINS_SRC_DISPATCH(src, K_);
 #undef K_
 }
@@ -2346,20 +2390,20 @@ void launch_sparsify(const LaunchCtx& L, int src) {
 #undef K_
     hipLaunchKernelGGL(k_scan_totals, g2((L.max_mn + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl);
     hipLaunchKernelGGL(k_scan, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl);
-    switch (L.sp_fmt) {
-        case 0: launch_fill_t<int, double>(L, src, g); break;
-        case 1: launch_fill_t<unsigned short, double>(L, src, g); break;
-        case 2: launch_fill_t<int, float>(L, src, g); break;
-        default: launch_fill_t<unsigned short, float>(L, src, g); break;
-    }
+    if (L.sp_f32)
+        launch_fill_t<float>(L, src, g);
+    else
+        launch_fill_t<double>(L, src, g);
 }
 
-// batches with m + n <= WCG_MAX_N for every instance (the others take the
-// wide CG); every vector of an instance fits the kernel's LDS arrays
+// instances with m + n <= WCG_MAX_N (the others take the wide CG); every
+// vector of such an instance fits the kernel's LDS arrays.  The entries a
+// thread owns beyond an instance's m + n add zeros to its sums, so the
+// instance's arithmetic does not depend on the batch's largest m + n.
 static_assert(WCG_MAX_N <= 4 * 1024, "k_pcg_lds holds at most 4096 vector entries");
 template <class IX, class VT>
 static void launch_pcg_t(const LaunchCtx& L) {
-    const int ept = (L.max_mn + 1023) / 1024;
+    const int ept = (L.max_mn_small + 1023) / 1024;
     const dim3 g(L.count), blk(1024);
     if (ept <= 1)
         hipLaunchKernelGGL((k_pcg_lds<1, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
@@ -2376,12 +2420,20 @@ static void launch_wcg_half_t(const LaunchCtx& L, int cols, int final) {
     hipLaunchKernelGGL((k_wcg_half<IX, VT>), g, dim3(WCG_NT), 0, L.stream, L.insts, L.ctrl, cols, final);
 }
 
+// one launch per index storage present among the wide instances (each skips
+// the instances stored the other way)
 static void launch_wcg_half(const LaunchCtx& L, int cols, int final) {
-    switch (L.sp_fmt) {
-        case 0: launch_wcg_half_t<int, double>(L, cols, final); break;
-        case 1: launch_wcg_half_t<unsigned short, double>(L, cols, final); break;
-        case 2: launch_wcg_half_t<int, float>(L, cols, final); break;
-        default: launch_wcg_half_t<unsigned short, float>(L, cols, final); break;
+    if (L.any_wide16) {
+        if (L.sp_f32)
+            launch_wcg_half_t<unsigned short, float>(L, cols, final);
+        else
+            launch_wcg_half_t<unsigned short, double>(L, cols, final);
+    }
+    if (L.any_wide32) {
+        if (L.sp_f32)
+            launch_wcg_half_t<int, float>(L, cols, final);
+        else
+            launch_wcg_half_t<int, double>(L, cols, final);
     }
 }
 
@@ -2394,8 +2446,8 @@ static void launch_half(const LaunchCtx& L, int src, int cols, int final) {
     }
     const dim3 g(L.total_tiles);
 #define K_(S, T) hipLaunchKernelGGL((k_mf_tile<S, T>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, cols, final)
-    if (L.sp_fmt & 2) {
-        PINS_SRC_DISPATCH(src, K_, float);  // mixed precision: float exp (exponent formed in double)
+    if (L.sp_f32) {
+        PINS_SRC_DISPATCH(src, K_, float);  // fast-mixed precision: float exp (exponent formed in double)
     } else {
         PINS_SRC_DISPATCH(src, K_, double);
     }
@@ -2407,7 +2459,7 @@ static void launch_half(const LaunchCtx& L, int src, int cols, int final) {
 void launch_wcg_begin(const LaunchCtx& L, int src) {
     hipLaunchKernelGGL(k_wcg_begin, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, src >= 0 ? 1 : 0);
     launch_half(L, src, 0, 2);
-    hipLaunchKernelGGL(k_wcg_start, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+    hipLaunchKernelGGL(k_wcg_start, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, src >= 0 ? 1 : 0);
 }
 
 void launch_wcg_iter(const LaunchCtx& L, int src) {
@@ -2421,18 +2473,15 @@ void launch_wcg_iter(const LaunchCtx& L, int src) {
 
 void launch_wcg_end(const LaunchCtx& L, int src) {
     launch_half(L, src, 1, 1);
-    hipLaunchKernelGGL(k_wcg_finish, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp);
+    hipLaunchKernelGGL(k_wcg_finish, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, src >= 0 ? 1 : 0);
 }
 
-bool wide_cg(const LaunchCtx& L) { return L.max_mn > WCG_MAX_N; }
-
+// the one-block instances always store int32 byte offsets
 void launch_pcg(const LaunchCtx& L) {
-    switch (L.sp_fmt) {
-        case 0: launch_pcg_t<int, double>(L); break;
-        case 1: launch_pcg_t<unsigned short, double>(L); break;
-        case 2: launch_pcg_t<int, float>(L); break;
-        default: launch_pcg_t<unsigned short, float>(L); break;
-    }
+    if (L.sp_f32)
+        launch_pcg_t<int, float>(L);
+    else
+        launch_pcg_t<int, double>(L);
 }
 
 void launch_ls(const LaunchCtx& L, int src, bool first) {
@@ -2486,6 +2535,20 @@ void launch_cost_max(const LaunchCtx& L, double* scratch, int nblk, int exponent
     hipLaunchKernelGGL(k_cost_max, dim3(nblk, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl, scratch);
     hipLaunchKernelGGL(k_set_scale, dim3((L.count + 63) / 64), dim3(64), 0, L.stream, L.insts_mut, L.ctrl, L.count,
                        exponent_uses_base);
+}
+
+// zero fill of `words` 8-byte words (control blocks at set-up; a kernel
+// rather than a memset node, so the clear is an ordinary launch on the stream)
+__global__ __launch_bounds__(256) void k_zero(unsigned long long* __restrict__ p, long words) {
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k < words) p[k] = 0ull;
+}
+
+void launch_zero(hipStream_t st, void* p, size_t bytes) {
+    const long words = (long)(bytes / 8);
+    if (words > 0)
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
+                           (unsigned long long*)p, words);
 }
 
 void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x) {

@@ -18,7 +18,12 @@ struct LaunchCtx {
     int max_m, max_n, max_mn;  // maxima over the batch (max_mn = max m+n)
     int max_tiles;             // max nrb*ncb
     int total_tiles, total_rowblk;  // sums over the batch (flat grids of the tile and row kernels)
-    int sp_fmt;                // storage of S: bit 0 uint16 indices, bit 1 float values
+    int sp_f32;                // values of S stored in float (fast-mixed precision), else double
+    // CG kinds present in the batch (per instance by DevInst::cgfmt): the
+    // one-block CG, the wide CG with uint16 / int32 indices; the largest m+n
+    // among the one-block instances
+    bool any_small, any_wide16, any_wide32;
+    int max_mn_small;
 };
 
 void launch_row_lse(const LaunchCtx& L, int src, bool f32, int mask);
@@ -27,16 +32,16 @@ void launch_col_merge(const LaunchCtx& L, int mask);
 void launch_grad(const LaunchCtx& L, int src);
 void launch_grad_merge(const LaunchCtx& L, bool early);  // early: only instances whose fused full step was just applied
 void launch_sparsify(const LaunchCtx& L, int src);
-// wide CG (batches whose largest m+n exceeds WCG_MAX_N, or matrix-free
-// products): begin, one iteration (no-op for instances that stopped), end; the
-// host repeats launch_wcg_iter until no instance has Ctrl::cg_on set.  src < 0:
-// products with the sparsified Hessian; src >= 0: matrix-free with the full
-// Hessian over that cost source
-bool wide_cg(const LaunchCtx& L);
+// wide CG (instances with m+n above WCG_MAX_N, or every instance with
+// matrix-free products): begin, one iteration (no-op for instances that
+// stopped), end; the host repeats launch_wcg_iter until no instance has
+// Ctrl::cg_on set.  src < 0: products with the sparsified Hessian, for the
+// instances whose cgfmt selects the wide CG; src >= 0: matrix-free with the full
+// Hessian over that cost source, for every instance
 void launch_wcg_begin(const LaunchCtx& L, int src);
 void launch_wcg_iter(const LaunchCtx& L, int src);  // one iteration; no per-iteration argument
 void launch_wcg_end(const LaunchCtx& L, int src);
-void launch_pcg(const LaunchCtx& L);
+void launch_pcg(const LaunchCtx& L);  // the one-block CG of the instances with m+n <= WCG_MAX_N
 void launch_ls(const LaunchCtx& L, int src, bool first);
 void launch_update(const LaunchCtx& L);
 void launch_shift(const LaunchCtx& L, int base_src);
@@ -44,5 +49,6 @@ void launch_init(const LaunchCtx& L, int base_src);
 void launch_points_cost(hipStream_t st, const double* x, const double* y, int m, int n, int d, double* C);
 void launch_cost_max(const LaunchCtx& L, double* scratch, int nblk, int exponent_uses_base);
 void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x);
+void launch_zero(hipStream_t st, void* p, size_t bytes);  // bytes: a multiple of 8
 
 }  // namespace pins

@@ -51,6 +51,12 @@ bool marginal_ok(const double* v, int len) {
     return std::fabs(s - 1.0) <= 1e-10;
 }
 
+bool all_finite(const double* v, size_t len) {
+    for (size_t i = 0; i < len; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
 }  // namespace
 
 struct pins_server {
@@ -104,7 +110,8 @@ void worker_loop(pins_server* S) {
     pins_ctx* ctx = nullptr;
     const int crc = pins_create(S->device, &ctx);
     hipStream_t st = nullptr;
-    const bool ok = crc == PINS_OK && hipStreamCreate(&st) == hipSuccess;
+    // non-blocking: no implicit synchronisation with other workers' work through the null stream
+    const bool ok = crc == PINS_OK && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
     Staging stage;
     pins_params p = S->params;
     p.streams = 0;  // this worker is one lane
@@ -243,6 +250,11 @@ int pins_server_submit(pins_server* S, const pins_problem* prob, int64_t* ticket
     if (prob->kind == PINS_COST_DENSE && !prob->C) return PINS_EINVAL;
     if (prob->kind == PINS_COST_POINTS && (!prob->x || !prob->y || prob->d < 1)) return PINS_EINVAL;
     if (!marginal_ok(prob->a, prob->m) || !marginal_ok(prob->b, prob->n)) return PINS_EINVAL;
+    // a non-finite cost would fail the batch it joins: rejected here
+    if (prob->kind == PINS_COST_DENSE && !all_finite(prob->C, (size_t)prob->m * prob->n)) return PINS_EINVAL;
+    if (prob->kind == PINS_COST_POINTS && (!all_finite(prob->x, (size_t)prob->m * prob->d) ||
+                                           !all_finite(prob->y, (size_t)prob->n * prob->d)))
+        return PINS_EINVAL;
     auto r = std::make_unique<Request>();
     r->prob = *prob;
     r->a.assign(prob->a, prob->a + prob->m);
