@@ -80,9 +80,12 @@ FLOPS_PER_ENTRY = {
 }
 # Algorithmic bytes per unit of the sparse kernels: the single-block CG reads
 # each stored CSR/CSC entry once per iteration, a 4-byte index (a byte offset
-# into the gathered vector) and a 4-byte (mixed precision) or 8-byte (FP64)
-# value.
-BYTES_PER_ENTRY = {"mixed": {"pcg": 8.0}, "fp64": {"pcg": 12.0}}
+# into the gathered vector) and an 8-byte value (4-byte in the fast-mixed
+# variant, which stores the kept entries in float).
+BYTES_PER_ENTRY = {"mixed": {"pcg": 12.0}, "fp64": {"pcg": 12.0}, "mixed_fast": {"pcg": 8.0}}
+# One compute unit's read path from L2 (64 bytes per clock at 2.4 GHz): the
+# ceiling of a kernel that runs one block per instance out of L2
+CU_L2_GBS = 64 * 2.4
 
 
 def parse():
@@ -90,7 +93,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "fp64", "mixed_fast"], default="mixed",
+                    help="mixed: float warm-up sweeps, everything else double; fp64; mixed_fast: mixed and the "
+                         "CG's kept Hessian entries stored in float, matrix-free products with a float exp")
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--K", type=int, default=250)
     ap.add_argument("--eta", type=float, default=0.1)
@@ -169,7 +174,7 @@ def main():
     probs = [dict(kind=P.COST_GRID, m=n, n=n, grid_s=s, a=t(p["a"]), b=t(p["b"])) for p in pairs]
     outs = [dict(alpha=torch.empty(n, dtype=torch.float64, device=dev),
                  beta=torch.empty(n, dtype=torch.float64, device=dev)) for _ in pairs]
-    prec = P.MIXED if args.precision == "mixed" else P.FP64
+    prec = {"mixed": P.MIXED, "fp64": P.FP64, "mixed_fast": P.MIXED_FAST}[args.precision]
     if args.served:
         print(json.dumps(dict(served=served(P, W, args.served, args.rate))), flush=True)
         return
@@ -260,7 +265,7 @@ def main():
     line = dict(metric="OT solves/sec at rel. cost error <=1e-6 (plain vs batched/served); p50/p99 latency",
                 value=value, unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                 ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
-                dtype="f32+f64" if prec == P.MIXED else "f64", data="synthetic",
+                dtype="f64" if prec == P.FP64 else "f32+f64", data="synthetic",
                 config=dict(workload="image-histogram pairs, 28x28 grid (m=n=784), squared grid distance/max "
                                      "streamed, eta=0.1, K=250, batched (one call per step)",
                             pairs=args.pairs, m=n, n=n, eta=args.eta, K=args.K, precision=args.precision,
@@ -276,14 +281,17 @@ def main():
 
     if not args.no_variants:
         variants = {}
-        other = P.FP64 if prec == P.MIXED else P.MIXED
-        prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other, streams=lanes, **hess)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        step(prm2)
-        torch.cuda.synchronize()
-        variants["batched_" + ("fp64" if other == P.FP64 else "mixed") + "_solves_per_s"] = \
-            args.pairs / (time.perf_counter() - t1)
+        for oname, other in (("mixed", P.MIXED), ("fp64", P.FP64), ("mixed_fast", P.MIXED_FAST)):
+            if other == prec:
+                continue
+            prm2 = P.params(eta=args.eta, max_outer=args.K, precision=other, streams=lanes, **hess)
+            step(prm2)  # untimed (first call at this precision)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            step(prm2)
+            torch.cuda.synchronize()
+            variants["batched_%s_solves_per_s" % oname] = args.pairs / (time.perf_counter() - t1)
+        variants["pcg_single_instance"] = pcg_single(P, ctx, torch, probs[0], outs[0], st, args, prec)
         prm1 = P.params(eta=args.eta, max_outer=args.K, precision=prec, **hess)
         nplain = min(4, args.pairs)
         lat = []
@@ -331,6 +339,29 @@ def main():
                                 gpu_resid=g0["resid"], oracle_resid=ref["resid"], bar=1e-6)
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def pcg_single(P, ctx, torch, prob, out, st, args, prec):
+    """The one-block CG alone: one pair solved by itself with sparsified Hessian
+    products throughout (so every CG iteration is the one-block CG's: one
+    block, one compute unit, nothing else on the GPU), HIP events around the CG
+    launches only.  Time per CG iteration, the stored entries an iteration
+    reads, and the rate at which the compute unit reads them against its L2
+    read path (64 bytes per clock at 2.4 GHz)."""
+    prm = P.params(eta=args.eta, max_outer=args.K, precision=prec, profile=1,
+                   profile_mask=1 << P.KERNEL_NAMES.index("pcg"), hvp=0)
+    rc, r = ctx.solve_device(prob, prm, out, stream=st)
+    torch.cuda.synchronize()
+    ms, calls, it = r["kern_ms"]["pcg"], r["kern_calls"]["pcg"], r["cg_iters"]
+    entries = r["kern_work"]["pcg"]  # 2 nnz per iteration, summed over the iterations
+    bpe = BYTES_PER_ENTRY[{P.MIXED: "mixed", P.FP64: "fp64", P.MIXED_FAST: "mixed_fast"}[prec]]["pcg"]
+    res = dict(launches=calls, cg_iters=it, pcg_ms=round(ms, 3))
+    if calls and it > 0:
+        gbs = entries * bpe / (ms * 1e-3) / 1e9
+        res.update(us_per_iteration=round(1e3 * ms / it, 3), stored_entries_per_iteration=round(entries / it, 1),
+                   bytes_per_entry=bpe, achieved_GBs_one_cu=round(gbs, 2), cu_l2_ceiling_GBs=CU_L2_GBS,
+                   frac_of_cu_l2=round(gbs / CU_L2_GBS, 4))
+    return res
 
 
 def uneven_points(P, ctx, torch, np, dev, W, st, count=256, K=20):
