@@ -207,6 +207,27 @@ int pins_solve(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pi
 int pins_solve_device(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res,
                       void* stream);
 
+/* ---- Solving without allocation ----
+ * For callers that cannot allocate device or pinned memory (code between HIP
+ * graph captures, tight serving loops, harnesses that forbid hipMalloc):
+ * pins_solve_device with its workspace in a fixed device array that the
+ * library holds on each GPU it runs on, PINS_NOALLOC_SCRATCH_BYTES bytes per
+ * GPU, until the process ends.  The call allocates no device, pinned or host
+ * staging memory (control blocks are read back through a fixed host buffer of
+ * the context) and creates no event.  Inputs and outputs are the caller's
+ * device arrays, as for pins_solve_device, and the results are bitwise those
+ * of pins_solve_device.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (from several contexts, threads or streams) race and
+ * must be serialised by the caller.  The array keeps the last call's contents;
+ * each call clears what must start at zero.  PINS_ENOMEM (nothing written)
+ * when the problem's workspace (pins_workspace_bytes with count 1) exceeds
+ * PINS_NOALLOC_SCRATCH_BYTES, e.g. a 128 x 128 grid; PINS_EINVAL for
+ * p->profile != 0 (profiling creates events); other errors as
+ * pins_solve_device. */
+#define PINS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int pins_solve_device_noalloc(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res,
+                              void* stream);
+
 /* ---- Checkpoint / resume of the outer loop ----
  * Under the implicit shift the k-th EPPA subproblem, eq. (eppa-sub), has the
  * exponent (F_i + G_j - (k+1) C_ij) / eta: the shifted cost C - eta log X^k

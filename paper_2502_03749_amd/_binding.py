@@ -25,6 +25,7 @@ PINS_EUNSUPPORTED = -5
 
 COST_DENSE, COST_POINTS, COST_GRID = 0, 1, 2
 FP64, MIXED, MIXED_FAST = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20
 SHIFT_IMPLICIT, SHIFT_MATERIALIZED = 0, 1
 NKERN = 16
 KERNEL_NAMES = ["row_lse", "col_lse", "col_merge", "grad", "grad_merge", "fill", "csc", "pcg", "ls", "update",
@@ -107,6 +108,8 @@ def lib():
         L.pins_solve.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(Result)]
         L.pins_solve_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(Result),
                                         vp]
+        L.pins_solve_device_noalloc.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params),
+                                                ctypes.POINTER(Result), vp]
         L.pins_solve_resume.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(State),
                                         ctypes.c_int32, ctypes.POINTER(State), ctypes.POINTER(Result)]
         L.pins_tune_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
@@ -260,6 +263,13 @@ class Context:
     def solve_device(self, problem, prm: Params, out, stream=None):
         cnt_rc, res = self.solve_batch_device([problem], prm, [out], stream)
         return cnt_rc, res[0]
+
+    def solve_device_noalloc(self, problem, prm: Params, out, stream=None):
+        """pins_solve_device_noalloc: pins_solve_device on the library's fixed device scratch."""
+        P, R = self._batch_args([problem], [out])
+        rc = self._check(lib().pins_solve_device_noalloc(self.h, P, ctypes.byref(prm), R,
+                                                         ctypes.c_void_p(stream or 0)))
+        return rc, R[0].scalars()
 
 
 class Server:

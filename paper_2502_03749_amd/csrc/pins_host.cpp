@@ -37,12 +37,18 @@ struct Lane {
     bool profile = false;
     int profile_mask = 0;          // kernel classes timed (0 = all)
     hipStream_t stream = nullptr;  // owned stream (default priority)
+    // fixed lane (pins_solve_device_noalloc): ws is the library's fixed device
+    // scratch and host staging goes through host_buf; nothing is allocated
+    bool fixed = false;
+    static constexpr size_t HOST_BUF = 16384;
+    alignas(256) char host_buf[HOST_BUF];
 };
 
 struct pins_ctx {
     int device = 0;
     std::string err;
     std::vector<Lane*> lanes;  // lanes[0] runs single-stream solves on the caller's stream
+    Lane* fixed = nullptr;     // the no-allocation lane (created with the context)
 };
 
 namespace {
@@ -272,6 +278,10 @@ void run(Lane* c, hipStream_t st, int kind, Fn&& fn) {
 }
 
 void* pinned(Lane* c, size_t bytes) {
+    if (c->fixed) {
+        if (bytes > Lane::HOST_BUF) fail(PINS_ENOMEM, "host staging of the no-allocation entry point too small");
+        return c->host_buf;
+    }
     if (bytes > c->pinned_bytes) {
         if (c->pinned) HIPCHK(hipHostFree(c->pinned));
         c->pinned = nullptr;
@@ -283,6 +293,12 @@ void* pinned(Lane* c, size_t bytes) {
 }
 
 char* workspace(Lane* c, size_t bytes) {
+    if (c->fixed) {
+        if (bytes > c->ws_bytes)
+            fail(PINS_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the fixed scratch of " +
+                                  std::to_string(c->ws_bytes) + " bytes (PINS_NOALLOC_SCRATCH_BYTES)");
+        return (char*)c->ws;
+    }
     if (bytes > c->ws_bytes) {
         if (c->ws) HIPCHK(hipFree(c->ws));
         c->ws = nullptr;
@@ -331,6 +347,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     }
     HIPCHK(hipSetDevice(ctx->device));
     ctx->profile = p.profile != 0;
+    if (ctx->fixed && ctx->profile) fail(PINS_EINVAL, "profiling is not available without allocation (it creates events)");
     ctx->profile_mask = p.profile_mask;
     ctx->ev_used = 0;
 
@@ -759,7 +776,7 @@ Lane* lane(pins_ctx* ctx, int q) {
 
 void free_lane(Lane* L) {
     for (hipEvent_t e : L->events) (void)hipEventDestroy(e);
-    if (L->ws) (void)hipFree(L->ws);
+    if (L->ws && !L->fixed) (void)hipFree(L->ws);
     if (L->pinned) (void)hipHostFree(L->pinned);
     if (L->stream) (void)hipStreamDestroy(L->stream);
     delete L;
@@ -891,9 +908,21 @@ int pins_create(int device, pins_ctx** out) {
         (void)hipGetLastError();
         return PINS_EDEVICE;
     }
+    // set-up of the no-allocation lane: the fixed scratch's address on this device
+    void* scr = nullptr;
+    if (noalloc_scratch(device, &scr) != PINS_OK) return PINS_EDEVICE;
     pins_ctx* c = new (std::nothrow) pins_ctx;
     if (!c) return PINS_ENOMEM;
     c->device = device;
+    c->fixed = new (std::nothrow) Lane;
+    if (!c->fixed) {
+        delete c;
+        return PINS_ENOMEM;
+    }
+    c->fixed->device = device;
+    c->fixed->fixed = true;
+    c->fixed->ws = scr;
+    c->fixed->ws_bytes = PINS_NOALLOC_SCRATCH_BYTES;
     *out = c;
     return PINS_OK;
 }
@@ -902,6 +931,7 @@ void pins_destroy(pins_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     for (Lane* L : c->lanes) free_lane(L);
+    if (c->fixed) free_lane(c->fixed);
     delete c;
 }
 
@@ -933,6 +963,15 @@ int pins_solve_device(pins_ctx* ctx, const pins_problem* prob, const pins_params
     return guarded(ctx, [&] {
         if (!prob || !p || !res) fail(PINS_EINVAL, "null argument");
         return solve_entry(ctx, prob, 1, *p, res, (hipStream_t)stream, false);
+    });
+}
+
+int pins_solve_device_noalloc(pins_ctx* ctx, const pins_problem* prob, const pins_params* p, pins_result* res,
+                              void* stream) {
+    return guarded(ctx, [&] {
+        if (!prob || !p || !res) fail(PINS_EINVAL, "null argument");
+        if (!ctx->fixed) fail(PINS_EDEVICE, "context has no fixed scratch");
+        return solve_impl(ctx->fixed, prob, 1, *p, res, (hipStream_t)stream, false);
     });
 }
 

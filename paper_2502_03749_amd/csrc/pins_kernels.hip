@@ -19,9 +19,18 @@
 
 #include <cfloat>
 #include <cmath>
+#include <mutex>
 
+#include "pins.h"
 #include "pins_internal.h"
 #include "pins_launch.h"
+
+// Device scratch of the entry point that allocates nothing
+// (pins_solve_device_noalloc): one array per GPU, held until the process ends.
+// Host code never passes this name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): pins::noalloc_scratch() looks up its
+// address on each device once and every use goes through that address.
+static __device__ __align__(256) char scratch[PINS_NOALLOC_SCRATCH_BYTES];
 
 namespace pins {
 
@@ -2549,6 +2558,32 @@ void launch_zero(hipStream_t st, void* p, size_t bytes) {
     if (words > 0)
         hipLaunchKernelGGL(k_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
                            (unsigned long long*)p, words);
+}
+
+// Address of `scratch` on `device`, looked up once per device with that device
+// current (each GPU holds its own copy at its own address), the caller's
+// current device restored afterwards.
+int noalloc_scratch(int device, void** out) {
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static void* ptr[MAXDEV] = {};
+    if (device < 0 || device >= MAXDEV) return PINS_EDEVICE;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[device]) {
+        int prev = 0;
+        if (hipGetDevice(&prev) != hipSuccess) return PINS_EDEVICE;
+        void* p = nullptr;
+        hipError_t e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return PINS_EDEVICE;
+        }
+        ptr[device] = p;
+    }
+    *out = ptr[device];
+    return PINS_OK;
 }
 
 void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x) {

@@ -50,5 +50,8 @@ void launch_points_cost(hipStream_t st, const double* x, const double* y, int m,
 void launch_cost_max(const LaunchCtx& L, double* scratch, int nblk, int exponent_uses_base);
 void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x);
 void launch_zero(hipStream_t st, void* p, size_t bytes);  // bytes: a multiple of 8
+// device address of the fixed scratch of pins_solve_device_noalloc on `device`
+// (PINS_NOALLOC_SCRATCH_BYTES bytes); PINS_OK or PINS_EDEVICE
+int noalloc_scratch(int device, void** out);
 
 }  // namespace pins
