@@ -122,6 +122,9 @@ def parse():
                          "Sinkhorn + EPPA with the same K (n = 50..400, eta = 1e-2) and the eta sweep at n = 400 "
                          "against Sinkhorn without EPPA (cap 50 000 iterations); about a minute")
     ap.add_argument("--paper-tables-only", action="store_true", help="only run --paper-tables")
+    ap.add_argument("--pcg-only", action="store_true",
+                    help="only run the single-instance CG measurement (pair 0 alone, sparsified Hessian products "
+                         "throughout, events around the one-block CG launches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
@@ -179,6 +182,12 @@ def main():
         print(json.dumps(dict(served=served(P, W, args.served, args.rate))), flush=True)
         return
     ctx = P.Context(0)
+    if args.pcg_only:
+        print(json.dumps(dict(pcg_single_instance=pcg_single(P, ctx, torch, probs[0], outs[0],
+                                                             torch.cuda.current_stream().cuda_stream, args, prec))),
+              flush=True)
+        ctx.close()
+        return
     if args.sweep_only:
         print(json.dumps(dict(sinkhorn_sweep=sweep_roofline(P, ctx, torch, np, dev),
                               sinkhorn_sweep_streamed=streamed_sweep(P, ctx, torch, np, dev, W))), flush=True)

@@ -299,6 +299,13 @@ int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, 
  * exps_per_s; PINS_EDEVICE / PINS_ENOMEM on runtime failure. */
 int pins_probe_exp_rate(int device, int blocks, int iters, double* exps_per_s, double* ms);
 
+/* The double exp of the FP64 dense passes (Tang's table-driven method, the
+ * kernels' own code) applied on the device to x[0..n) into y[0..n) (DEVICE
+ * arrays of n doubles, caller-owned), on `stream`, waiting for it.  For
+ * checking the device evaluation against a reference.  PINS_EINVAL for NULL
+ * arrays or n < 0; PINS_EDEVICE on runtime failure. */
+int pins_probe_texp(const double* x, double* y, int n, void* stream);
+
 /* ---- Serving (continuous admission of requests onto concurrent batches) ----
  * A server owns `workers` (1..4) solver threads on HIP device `device`, each
  * with its own context and HIP stream.  A worker that becomes free takes every

@@ -116,6 +116,7 @@ def lib():
                                              ctypes.c_int, ctypes.c_int, ctypes.POINTER(Result), vp,
                                              ctypes.POINTER(ctypes.c_int32), _D]
         L.pins_probe_exp_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D]
+        L.pins_probe_texp.argtypes = [vp, vp, ctypes.c_int, vp]
         L.pins_solve_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
                                               ctypes.POINTER(Result), vp]
         L.pins_server_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
@@ -379,6 +380,15 @@ def probe_exp_rate(device: int = 0, blocks: int = 8192, iters: int = 4096):
     if rc != PINS_OK:
         raise PinsError(rc, "pins_probe_exp_rate failed")
     return rate.value, ms.value
+
+
+def probe_texp(x, y, stream=None):
+    """pins_probe_texp: y = the FP64 dense passes' exp of x (float64 device tensors of equal size)."""
+    if x.numel() != y.numel():
+        raise ValueError("x and y must have the same size")
+    rc = lib().pins_probe_texp(_ptr(x), _ptr(y), x.numel(), ctypes.c_void_p(stream or 0))
+    if rc != PINS_OK:
+        raise PinsError(rc, "pins_probe_texp failed")
 
 
 def workspace_bytes(problems, prm: Params) -> int:

@@ -24,6 +24,7 @@
 #include "pins.h"
 #include "pins_internal.h"
 #include "pins_launch.h"
+#include "pins_texp.h"
 
 // Device scratch of the entry point that allocates nothing
 // (pins_solve_device_noalloc): one array per GPU, held until the process ends.
@@ -158,30 +159,12 @@ __device__ __forceinline__ double exs<double>(double y) { return exp(y); }
 template <>
 __device__ __forceinline__ float exs<float>(double y) { return __expf((float)y); }
 
-// exp(x) in double by Tang's table-driven method (P. T. P. Tang, ACM TOMS
-// 15(2), 1989): x = (64k + j) ln2/64 + r with |r| <= ln2/128, so that
-// exp(x) = 2^k 2^(j/64) (1 + q) with q = e^r - 1 from its degree-5 Taylor
-// polynomial (truncation below 4e-17 relative).  T holds 2^(j/64),
-// j = 0..63, in LDS (texp_table).  About 1 ulp; x < -746 gives 0, x > 710
-// gives inf, NaN stays NaN.
+// exp(x) in double by Tang's table-driven method (pins_texp.h), the table
+// 2^(j/64), j = 0..63, in LDS.
 __device__ __forceinline__ void texp_table(double* T) {
-    if (threadIdx.x < 64) T[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 64.0));
+    if (threadIdx.x < 64) T[threadIdx.x] = texp_table_entry((int)threadIdx.x);
 }
-__device__ __forceinline__ double texp(double x, const double* T) {
-    x = (x < -746.0) ? -746.0 : x;
-    x = (x > 710.0) ? 710.0 : x;
-    const double nd = rint(x * 92.33248261689366);   // 64 / ln 2
-    const int nk = (int)nd;
-    double r = fma(-nd, 0x1.62e42fefa39efp-7, x);    // ln 2 / 64, leading part
-    r = fma(-nd, 0x1.abc9e3b39803fp-62, r);          // ln 2 / 64, trailing part
-    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-    q = fma(q, r, 1.0 / 6.0);
-    q = fma(q, r, 0.5);
-    q = fma(q, r, 1.0);
-    q *= r;
-    const double tj = T[nk & 63];
-    return ldexp(fma(tj, q, tj), nk >> 6);
-}
+__device__ __forceinline__ double texp(double x, const double* T) { return texp_eval(x, T); }
 
 template <class T>
 __device__ __forceinline__ void lse_combine(double& mx, T& sm, double m2, T s2) {

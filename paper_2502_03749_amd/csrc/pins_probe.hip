@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include "pins.h"
+#include "pins_texp.h"
 
 namespace {
 
@@ -32,7 +33,25 @@ __global__ __launch_bounds__(PROBE_NT) void k_probe_exp(float* __restrict__ out,
     out[gid] = s;
 }
 
+// the FP64 dense passes' exp (pins_texp.h) on the device, table in LDS as in the kernels
+__global__ __launch_bounds__(256) void k_probe_texp(const double* __restrict__ x, double* __restrict__ y, int n) {
+    __shared__ double T[64];
+    if (threadIdx.x < 64) T[threadIdx.x] = pins::texp_table_entry((int)threadIdx.x);
+    __syncthreads();
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < n) y[k] = pins::texp_eval(x[k], T);
+}
+
 }  // namespace
+
+extern "C" int pins_probe_texp(const double* x, double* y, int n, void* stream) {
+    if (!x || !y || n < 0) return PINS_EINVAL;
+    if (n == 0) return PINS_OK;
+    hipLaunchKernelGGL(k_probe_texp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, x, y, n);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return PINS_EDEVICE;
+    return PINS_OK;
+}
 
 extern "C" int pins_probe_exp_rate(int device, int blocks, int iters, double* exps_per_s, double* ms) {
     if (!exps_per_s || blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20)) return PINS_EINVAL;

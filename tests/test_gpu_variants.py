@@ -122,3 +122,30 @@ def test_hybrid_hessian_schedule_parity(ctx):
         else:
             assert g["rc"] == 0 and g["resid"] <= 1e-10 and abs(g["cost"] - o["cost"]) / o["cost"] <= 1e-6
         assert g["kern_work"]["pcg_wide"] > 0 and g["kern_work"]["pcg"] > 0
+
+
+def test_device_texp_matches_host_reference():
+    """The FP64 dense passes' exp evaluated on the device (pins_probe_texp, the
+    kernels' own code and table) against numpy's exp: within 1 ulp (plus one
+    for the reference's own rounding) over [-746, 710], subnormal results
+    included; 0 below the range, inf above it, NaN kept."""
+    import numpy as np
+    import torch
+
+    import paper_2502_03749_amd as P
+
+    g = np.random.default_rng(11)
+    x = np.concatenate([g.uniform(-746.0, 710.0, 2_000_000), g.uniform(-745.2, -708.0, 200_000),
+                        g.uniform(-1.0, 1.0, 200_000), [0.0, -0.0, 709.78, -745.13, -746.5, 710.5, np.inf,
+                                                        -np.inf, np.nan]])
+    xt = torch.as_tensor(x, dtype=torch.float64, device="cuda:0")
+    yt = torch.empty_like(xt)
+    P.probe_texp(xt, yt, stream=torch.cuda.current_stream().cuda_stream)
+    y = yt.cpu().numpy()
+    ref = np.exp(x)
+    fin = np.isfinite(ref) & np.isfinite(x)
+    ulp = np.spacing(np.abs(ref[fin]))
+    ulp[ref[fin] == 0.0] = np.nextafter(0.0, 1.0)
+    err = np.abs(y[fin] - ref[fin]) / ulp
+    assert err.max() <= 2.0, (err.max(), x[fin][err.argmax()])
+    assert y[-5] == 0.0 and np.isinf(y[-4]) and np.isinf(y[-3]) and y[-2] == 0.0 and np.isnan(y[-1])
