@@ -259,17 +259,25 @@ def main():
                             traffic=_traffic(dom), avg_launch_us=1e3 * avg_ms, launches=calls,
                             entries_per_launch=kwork[dom] / calls, flops_per_entry=fpe)
         elif dom in BYTES_PER_ENTRY[args.precision] and kwork.get(dom, 0) > 0:
+            # the one-block CG: one block (one compute unit) per instance of the
+            # lane, its stored entries read from L2 every iteration; the ceiling
+            # is the L2 read path of the compute units one launch occupies
             bytes_per_launch = kwork[dom] * BYTES_PER_ENTRY[args.precision][dom] / calls
             achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-            roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
-                            frac=achieved / PEAK_HBM_GBS, traffic=_traffic(dom), avg_launch_us=1e3 * avg_ms,
-                            launches=calls, bytes_per_launch=bytes_per_launch)
+            cus = args.pairs / lanes
+            peak = CU_L2_GBS * cus
+            roofline = dict(kernel=dom, bound="l2", achieved=achieved, peak=peak, unit="GB/s",
+                            frac=achieved / peak, traffic=_traffic(dom), avg_launch_us=1e3 * avg_ms,
+                            launches=calls, bytes_per_launch=bytes_per_launch,
+                            peak_is="%.1f compute units (one per instance of a lane) x 64 B/clock x 2.4 GHz" % cus)
         else:
             roofline = dict(kernel=dom, bound="latency", achieved=None, peak=None, unit=None, frac=None,
                             traffic=None, avg_launch_us=1e3 * avg_ms, launches=calls)
         roofline["kernel_ms_share"] = {k: round(v / sum(share_ms.values()), 4) for k, v in
                                        sorted(share_ms.items(), key=lambda kv: -kv[1]) if v > 0}
         roofline["kernel_ms_share_from"] = "one untimed step with every launch timed"
+        # the lanes run concurrently: per lane, the dominant class's kernel time per step
+        roofline["kernel_ms_per_step_per_lane"] = kms[dom] / args.steps / lanes
 
     line = dict(metric="OT solves/sec at rel. cost error <=1e-6 (plain vs batched/served); p50/p99 latency",
                 value=value, unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PINS_ABI_VERSION 1
+#define PINS_ABI_VERSION 2
 
 typedef struct pins_ctx pins_ctx;
 
@@ -112,6 +112,14 @@ typedef struct {
                              the potentials and the streamed cost (no Sparsify), 2 = matrix-free
                              in the outer iterations k < hvp_switch, sparsified after */
     int32_t hvp_switch;   /* hvp = 2: first outer iteration with sparsified products */
+    int32_t graphs;       /* nonzero: an outer iteration that starts with a single warm-up
+                             iteration and a first Newton round of one-block CGs (the common case
+                             once the warm start settles) is replayed as one captured HIP graph
+                             (shift, warm-up iteration, Newton pass, Sparsify, CG, first Armijo
+                             trial) instead of being launched kernel by kernel.  Needs a non-null
+                             stream and profile = 0 (otherwise ignored); results are bitwise
+                             those of the kernel-by-kernel launches */
+    int32_t reserved0;
 } pins_params;
 
 /* One problem instance.  For pins_solve the pointers are host pointers, for

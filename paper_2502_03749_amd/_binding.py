@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
                 ("rho_levels", ctypes.c_int32), ("rho", ctypes.c_double), ("budget", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("shift_mode", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("profile_mask", ctypes.c_int32), ("hvp", ctypes.c_int32),
-                ("hvp_switch", ctypes.c_int32)]
+                ("hvp_switch", ctypes.c_int32), ("graphs", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):

@@ -508,7 +508,9 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     kp.eta = p.eta;
     kp.inv_eta = 1.0 / p.eta;
     kp.warm_tol = p.warm_tol;
-    kp.tol = p.inner_tol;
+    kp.inner_tol = p.inner_tol;
+    kp.final_tol = p.final_tol;
+    kp.K = p.max_outer;
     kp.cg_rtol = p.cg_rtol;
     kp.ls_beta = p.ls_beta;
     kp.ls_c1 = p.ls_c1;
@@ -523,7 +525,6 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     kp.count = count;
     kp.toff = (const int*)(ws + B.offs);
     kp.roff = kp.toff + count + 1;
-    kp.last = 0;
 
     // a0: cost scale (1/max over the dense cost unless given) and finiteness
     if (need_max) {
@@ -556,12 +557,14 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
             const size_t D = sizeof(double);
             k_begin = S.outer_done;
             const double kap = (double)S.outer_done;
+            const int kprev = S.outer_done - 1;  // the coming shift advances it to outer_done
             const int fl = S.flags & 2;
             HIPCHK(hipMemcpyAsync(Dp(Lp.F), S.F, D * Lp.m, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(Dp(Lp.G), S.G, D * Lp.n, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(Dp(Lp.Ah), S.A, D * Lp.m, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(Dp(Lp.Bh), S.B, D * Lp.n, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(&d_ctrl[0].kappa, &kap, sizeof(double), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(&d_ctrl[0].k_out, &kprev, sizeof(int), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(&d_ctrl[0].flags, &fl, sizeof(int), hipMemcpyHostToDevice, st));
             HIPCHK(hipStreamSynchronize(st));
         }
@@ -570,14 +573,87 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     const bool f32 = p.precision != PINS_FP64;  // float warm-up sweeps
     // matrix-free Hessian products (no Sparsify) in outer iteration k
     auto matrix_free = [&](int k) { return p.hvp == 1 || (p.hvp == 2 && k < p.hvp_switch); };
-    const int K = p.max_outer;
     const int M_WARM = 1 << PH_WARM, M_FB = 1 << PH_FALLBACK;
     bool quick_warm = false;  // every warm-up of the last outer iteration took one iteration
+    // The launches of a Newton round up to its readback: Newton pass and merge,
+    // Sparsify, the one-block CG (sparsified products; the wide CG and the
+    // matrix-free products run their own loop), the first Armijo trial fused
+    // with the next Newton pass, and the early merge and decision.
+    auto newton_round = [&](bool mf) {
+        run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
+        run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, false); });
+        if (!mf) run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
+        // sparsified products: the one-block CG for the instances with m + n <=
+        // WCG_MAX_N and the wide CG for the others (the choice is each
+        // instance's own); matrix-free products: the wide CG for every instance
+        if (!mf && L.any_small) run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
+        if (mf || L.any_wide16 || L.any_wide32) {
+            // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
+            const int hsrc = mf ? src : -1;
+            run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_begin(L, hsrc); });
+            for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
+                const Ctrl* hc = readback(ctx, st, d_ctrl, count);
+                bool on = false;
+                for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
+                if (!on) break;
+                for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc); });
+            }
+            run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_end(L, hsrc); });
+        }
+        run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
+        // instances whose full step the fused first trial applied: the next
+        // gradient is formed, so merge it and take the convergence decision
+        // now (a subproblem that converged in one step then needs no further
+        // round of launches)
+        run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, true); });
+    };
+    // params.graphs: an outer iteration on the quick path (k > 0, the previous
+    // warm-ups all took one iteration, sparsified products, one-block CGs only)
+    // launches shift, one warm-up iteration and the first Newton round with no
+    // readback in between; that sequence is captured once as a HIP graph and
+    // replayed.  Every kernel argument is the same in every outer iteration
+    // (the per-instance state lives in the control blocks), so a replay runs
+    // exactly the launches the sequence would make.
+    struct GraphHolder {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t e = nullptr;
+        ~GraphHolder() {
+            if (e) (void)hipGraphExecDestroy(e);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    } gq;
+    const bool graphs_ok = p.graphs && !ctx->profile && st != nullptr && L.any_small && !L.any_wide16 &&
+                           !L.any_wide32 && p.max_sinkhorn > 0;
+    auto quick_sequence = [&] {
+        run(ctx, st, PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
+        run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
+        run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
+        run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
+        newton_round(false);
+    };
     for (int k = k_begin; k < k_end; ++k) {
         const bool mf = matrix_free(k);
-        kp.tol = (k == K - 1) ? p.final_tol : p.inner_tol;
-        kp.last = (k == K - 1) ? 1 : 0;
-        if (k > 0) run(ctx, st, PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
+        bool warm_unread = false, round_done = false;
+        if (graphs_ok && !mf && k > 0 && quick_warm) {
+            if (!gq.e) {
+                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                try {
+                    quick_sequence();
+                } catch (...) {
+                    hipGraph_t bad = nullptr;
+                    (void)hipStreamEndCapture(st, &bad);
+                    if (bad) (void)hipGraphDestroy(bad);
+                    throw;
+                }
+                HIPCHK(hipStreamEndCapture(st, &gq.g));
+                HIPCHK(hipGraphInstantiate(&gq.e, gq.g, nullptr, nullptr, 0));
+            }
+            HIPCHK(hipGraphLaunch(gq.e, st));
+            warm_unread = true;
+            round_done = true;
+        } else if (k > 0) {
+            run(ctx, st, PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
+        }
         // warm-up: chunks of W Sinkhorn iterations, then a readback
         // warm-up sweeps of the instances in the warm-up phase: chunks of W
         // iterations, a readback after each, until none is left; returns the
@@ -603,8 +679,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         // round follows without a readback: the Newton kernels act only on the
         // instances that iteration moved to the Newton phase, and any still in the
         // warm-up finish it after the round's readback and join the next round.
-        bool warm_unread = false;
-        if (p.max_sinkhorn > 0) {
+        if (p.max_sinkhorn > 0 && !round_done) {
             if (quick_warm) {
                 run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
                 run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
@@ -614,34 +689,11 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
                 quick_warm = warm_loop(1) == 1;
             }
         }
-        // Newton steps; a readback after each
+        // Newton steps; a readback after each (the first round may have gone out
+        // with the captured sequence)
         for (;;) {
-            run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
-            run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, false); });
-            if (!mf) run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
-            // sparsified products: the one-block CG for the instances with m + n <=
-            // WCG_MAX_N and the wide CG for the others (the choice is each
-            // instance's own); matrix-free products: the wide CG for every instance
-            if (!mf && L.any_small) run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
-            if (mf || L.any_wide16 || L.any_wide32) {
-                // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
-                const int hsrc = mf ? src : -1;
-                run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_begin(L, hsrc); });
-                for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
-                    const Ctrl* hc = readback(ctx, st, d_ctrl, count);
-                    bool on = false;
-                    for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
-                    if (!on) break;
-                    for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc); });
-                }
-                run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_end(L, hsrc); });
-            }
-            run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
-            // instances whose full step the fused first trial applied: the next
-            // gradient is formed, so merge it and take the convergence decision
-            // now (a subproblem that converged in one step then needs no further
-            // round of launches)
-            run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, true); });
+            if (!round_done) newton_round(mf);
+            round_done = false;
             // one readback per Newton step: who is still iterating, who needs more
             // Armijo trials, who will take the Sinkhorn fallback
             const Ctrl* h = readback(ctx, st, d_ctrl, count);

@@ -106,6 +106,11 @@ struct Ctrl {
     int margbad;             // set up: bit 0 a has an entry <= 0 or non-finite, bit 1 |sum a - 1| > 1e-10,
                              // bits 2, 3 the same for b
     double cg_rzs[2], cg_bnorm;  // wide CG: <res, z> of iteration t in cg_rzs[t & 1]; ||rhs||
+    // outer loop of this instance: the current subproblem k_out (advanced by the
+    // shift), the number K_out of outer iterations, and the marginal tolerances
+    // of the subproblems before the last (tol_in) and of the last (tol_fin)
+    int k_out, K_out;
+    double tol_in, tol_fin;
 };
 
 // pass kinds counted in Ctrl::work
@@ -114,11 +119,12 @@ enum WorkKind : int { W_ROW = 0, W_COL = 1, W_GRAD = 2, W_FILL = 3, W_CG = 4, W_
 // Kernel-wide parameters (passed by value).
 struct KP {
     double eta, inv_eta;
-    double warm_tol, tol;   // tol: marginal tolerance of the current subproblem
+    double warm_tol;
+    double inner_tol, final_tol;  // marginal tolerances (copied into each instance's Ctrl at set-up)
     double cg_rtol, ls_beta, ls_c1, log_rho;
     double budget;
     int T1, T2, cg_max, ls_max;
-    int nlev, shift_mode, last, count;  // count: instances in the batch
+    int nlev, shift_mode, K, count;  // K: outer iterations; count: instances in the batch
     // flat grids over uneven batches: toff / roff hold count + 1 prefix sums of
     // the per-instance tile counts (nrb * ncb) and row-block counts (ceil(m/4))
     const int* toff;

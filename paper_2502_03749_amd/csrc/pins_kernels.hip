@@ -689,10 +689,10 @@ __global__ __launch_bounds__(256) void k_grad_decide(const DevInst* __restrict__
         if (!isfinite(res)) {
             S.nonfinite = 1;
             S.phase = PH_DONE;
-        } else if (res <= kp.tol) {
+        } else if (res <= (S.k_out >= S.K_out - 1 ? S.tol_fin : S.tol_in)) {
             S.phase = PH_DONE;
         } else if (S.t >= kp.T2) {
-            S.flags |= kp.last ? 1 : 2;
+            S.flags |= (S.k_out >= S.K_out - 1) ? 1 : 2;
             S.phase = PH_DONE;
         } else {
             go = 1;
@@ -2000,6 +2000,7 @@ __global__ __launch_bounds__(1024) void k_shift_vec(const DevInst* __restrict__ 
     if (threadIdx.x == 0) {
         Ctrl& S = ctrl[b];
         if (!materialised) S.kappa += 1.0;
+        S.k_out += 1;
         S.t = 0;
         S.phase = S.nonfinite ? PH_DONE : start_phase;
     }
@@ -2067,6 +2068,10 @@ __global__ __launch_bounds__(1024) void k_init(const DevInst* __restrict__ insts
         S.margbad = mb;
         S.phase = (S.nonfinite || mb) ? PH_DONE : (kp.T1 > 0 ? PH_WARM : PH_NEWTON);
         S.kappa = 1.0;
+        S.k_out = 0;
+        S.K_out = kp.K;
+        S.tol_in = kp.inner_tol;
+        S.tol_fin = kp.final_tol;
     }
 }
 

@@ -19,7 +19,7 @@ def test_library_exports_every_declared_symbol():
     assert "pins_solve" in names and "pins_solve_batch_device" in names
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
-    assert L.pins_abi_version() == 1
+    assert L.pins_abi_version() == 2
 
 
 def test_struct_layout_matches_header(tmp_path):

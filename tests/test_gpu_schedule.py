@@ -93,3 +93,39 @@ def test_exp_probe_rate_is_plausible():
     assert ms > 0.0
     per_cu_cycle = rate / (256 * 2.4e9)
     assert 1.0 <= per_cu_cycle <= 64.0, per_cu_cycle
+
+
+@pytest.mark.parametrize("lanes", [1, 3])
+def test_graph_replay_equals_kernel_by_kernel(ctx, lanes):
+    """params.graphs: outer iterations on the quick path (one warm-up iteration,
+    one-block CGs) replay one captured HIP graph (shift, warm-up iteration,
+    Newton pass, Sparsify, CG, first Armijo trial) instead of launching kernel
+    by kernel.  The graph is replayed in most of the K = 60 outer iterations,
+    with the solver's readbacks and eager launches in between; every
+    instance's result must be bitwise the kernel-by-kernel one.  12 pairs of
+    28x28 histograms (grid cost), eta = 0.1, on a non-default caller stream,
+    one lane and three lanes."""
+    import workloads as W
+
+    s, n, K = 28, 784, 60
+    print("case graphs lanes %d" % lanes, flush=True)
+    t = lambda v: torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=DEV)
+    pairs = [W.blob_pair(i, s=s) for i in range(12)]
+    probs = [dict(kind=P.COST_GRID, m=n, n=n, grid_s=s, a=t(p["a"]), b=t(p["b"])) for p in pairs]
+    st = torch.cuda.Stream()
+    res = {}
+    for g in (0, 1):
+        outs = [dict(alpha=torch.empty(n, dtype=torch.float64, device=DEV),
+                     beta=torch.empty(n, dtype=torch.float64, device=DEV)) for _ in pairs]
+        torch.cuda.synchronize()
+        rc, rs = ctx.solve_batch_device(probs, P.params(eta=0.1, max_outer=K, streams=lanes, graphs=g), outs,
+                                        stream=st.cuda_stream)
+        st.synchronize()
+        assert rc == 0
+        res[g] = (rs, outs)
+    for q in range(len(pairs)):
+        r0, r1 = res[0][0][q], res[1][0][q]
+        assert r0["cost"] == r1["cost"] and r0["newton_iters"] == r1["newton_iters"], q
+        assert r0["cg_iters"] == r1["cg_iters"] and r0["sinkhorn_iters"] == r1["sinkhorn_iters"], q
+        assert torch.equal(res[0][1][q]["alpha"], res[1][1][q]["alpha"]), q
+        assert torch.equal(res[0][1][q]["beta"], res[1][1][q]["beta"]), q
