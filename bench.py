@@ -13,12 +13,14 @@ solves all 64 pairs; value = solves per second over the timed steps.  Inputs
 are resident in HBM before the timed region starts.  The Newton CG multiplies
 by the full Hessian (matrix-free) in the first 15 outer iterations, while the
 plans are diffuse, and by the sparsified Hessian (CSR/CSC) after
-(--hvp-switch).  The number of concurrent lanes is picked on the batch by the
-library's autotuner before the warm-up (--lanes fixes it instead).
+(--hvp-switch).  The number of concurrent lanes and the rows per tile of the dense
+passes are picked on the batch by the library's autotuner before the warm-up
+(--lanes fixes the lanes and keeps 16-row tiles instead).
 
 The JSON line also carries:
-  autotune     -- each lane count's time for one batched call (ms) and the
-                  count chosen;
+  autotune     -- every configuration the tuner tried (lanes, graph replay,
+                  rows per tile) with its time for one batched call, and the
+                  choice;
   roofline     -- the dominant kernel class, its algorithmic work per launch
                   over its average launch time (HIP events on the solver's
                   stream, recorded by the library in the timed region);
@@ -220,14 +222,20 @@ def main():
         return kms, kwork, kcalls
 
     hess = dict(hvp=2, hvp_switch=args.hvp_switch) if args.hvp_switch > 0 else dict(hvp=0)
-    lanes, autotune = args.lanes, None
+    lanes, autotune, tiles, graphs = args.lanes, None, [0, 0, 0, 0], 0
     if lanes <= 0:
-        best, ms = ctx.tune_batch_device(probs, P.params(eta=args.eta, max_outer=args.K, precision=prec, **hess),
-                                         outs, max_lanes=4, reps=2, stream=st)
-        lanes = best
-        autotune = dict(lanes=best, ms_by_lanes=[round(v, 1) for v in ms], reps=2,
-                        searched="params.streams = 1..4 (launch schedule only; results do not depend on it)")
-    base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=lanes, **hess)
+        # on the caller's stream, like the timed steps: every stream of the process
+        # takes one of its hardware queues (four here), so no extra stream is
+        # added (graph replay runs on the lanes' own streams when there are two or more)
+        best, trials = ctx.tune_batch_device(probs, P.params(eta=args.eta, max_outer=args.K, precision=prec, **hess),
+                                             outs, max_lanes=4, reps=2, stream=st)
+        torch.cuda.synchronize()
+        lanes, tiles, graphs = best.streams, list(best.tile_rows), best.graphs
+        autotune = dict(lanes=lanes, graphs=graphs, tile_rows=tiles, reps=2,
+                        trials=[dict(t, ms=round(t["ms"], 1)) for t in trials],
+                        searched="lanes 1..4 and graph replay (launch schedule; results unchanged), then 4 / 8 "
+                                 "rows per tile per size class present (0 = 16)")
+    base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=lanes, tile_rows=tiles, **hess)
     share_ms, _, _ = aggregate([step(P.params(profile=1, **base))])
     dom = max(share_ms, key=share_ms.get)
     prm = P.params(profile=0 if args.no_profile else 1, profile_mask=1 << P.KERNEL_NAMES.index(dom), **base)
@@ -286,7 +294,7 @@ def main():
                 config=dict(workload="image-histogram pairs, 28x28 grid (m=n=784), squared grid distance/max "
                                      "streamed, eta=0.1, K=250, batched (one call per step)",
                             pairs=args.pairs, m=n, n=n, eta=args.eta, K=args.K, precision=args.precision,
-                            mode="batched", lanes=lanes,
+                            mode="batched", lanes=lanes, tile_rows=tiles,
                             hessian=("matrix-free full Hessian for outer iterations k < %d, sparsified (CSR) after"
                                      % args.hvp_switch) if args.hvp_switch > 0 else "sparsified (CSR)"),
                 roofline=roofline, autotune=autotune)
@@ -309,6 +317,19 @@ def main():
             torch.cuda.synchronize()
             variants["batched_%s_solves_per_s" % oname] = args.pairs / (time.perf_counter() - t1)
         variants["pcg_single_instance"] = pcg_single(P, ctx, torch, probs[0], outs[0], st, args, prec)
+        # graph replay of the quick outer iterations (no per-launch events, which
+        # the timed steps record); the lanes' own streams replay it (one lane:
+        # a non-default caller stream)
+        gs = st if lanes >= 2 else torch.cuda.Stream().cuda_stream
+        prmg = P.params(graphs=1, **base)
+        torch.cuda.synchronize()
+        ctx.solve_batch_device(probs, prmg, outs, stream=gs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(2):
+            ctx.solve_batch_device(probs, prmg, outs, stream=gs)
+        torch.cuda.synchronize()
+        variants["batched_graphs_solves_per_s"] = 2 * args.pairs / (time.perf_counter() - t1)
         prm1 = P.params(eta=args.eta, max_outer=args.K, precision=prec, **hess)
         nplain = min(4, args.pairs)
         lat = []

@@ -119,7 +119,12 @@ typedef struct {
                              trial) instead of being launched kernel by kernel.  Needs a non-null
                              stream and profile = 0 (otherwise ignored); results are bitwise
                              those of the kernel-by-kernel launches */
-    int32_t reserved0;
+    int32_t tile_rows[4]; /* rows per tile of the dense passes (the tiles are 256 columns wide) for
+                             instances with m in [1, 64), [64, 256), [256, 1024), [1024, ...);
+                             0 = 16, else 1..16.  The order in which column partials are summed
+                             follows it, so results depend on it (last bits), but only through each
+                             instance's own m: an instance gets the same result alone and in any
+                             batch solved with the same parameters */
 } pins_params;
 
 /* One problem instance.  For pins_solve the pointers are host pointers, for
@@ -280,21 +285,33 @@ int pins_solve_resume(pins_ctx* ctx, const pins_problem* prob, const pins_params
 int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
                             pins_result* res, void* stream);
 
-/* Autotuner over the batch schedule.  The number of concurrent lanes
- * (params.streams) is the launch-schedule choice of pins_solve_batch_device
- * that leaves every result bitwise unchanged, and its best value depends on
+/* Autotuner over the batch schedule and the tile shape.  Three choices of
+ * pins_solve_batch_device are searched, each of whose best value depends on
  * the batch (how many instances, how uneven, how their Newton phases
- * overlap).  For each lane count g = 1 .. max_lanes (at most 4) the batch is
- * solved once untimed (workspace set-up) and then `reps` times, timed with the
- * host clock (each solve returns when it has finished); ms[g-1] (when ms is
- * non-NULL) receives the fastest of the reps and *best the fastest g.  Counts
- * above `count` are not tried (a batch runs on at most `count` lanes) and get
- * ms[g-1] = 0.  The
- * outputs in res (DEVICE arrays, as for pins_solve_batch_device) are those of
- * the last solve.  Returns the batch's worst status; PINS_EINVAL for
- * max_lanes outside [1, 4], reps < 1 or a NULL best. */
+ * overlap): the number of concurrent lanes (params.streams) and the graph
+ * replay (params.graphs), which leave every result bitwise unchanged, and the
+ * rows per tile of the dense passes (params.tile_rows), which changes the
+ * summation order but keeps each result a function of its own instance.  The
+ * search is greedy: lane counts 1 .. max_lanes (at most 4, at most `count`)
+ * with graphs off and 16-row tiles; then graphs on at the best count; then,
+ * for each size class of m present in the batch, 4 and 8 rows per tile.  Each
+ * configuration is solved once untimed (workspace set-up) and then `reps`
+ * times, timed with the host clock (each solve returns when it has finished),
+ * and scored by its fastest rep.  *best receives *p with streams, graphs and
+ * tile_rows set to the fastest configuration; trials (when non-NULL) receives
+ * up to max_trials of the tried configurations in order, *ntrials (when
+ * non-NULL) their number.  The outputs in res (DEVICE arrays, as for
+ * pins_solve_batch_device) are those of the last solve.  Returns the batch's
+ * worst status; PINS_EINVAL for max_lanes outside [1, 4], reps < 1 or a NULL
+ * best. */
+typedef struct {
+    int32_t streams, graphs;
+    int32_t tile_rows[4];
+    double ms; /* fastest of the reps */
+} pins_tune_trial;
 int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
-                           int max_lanes, int reps, pins_result* res, void* stream, int32_t* best, double* ms);
+                           int max_lanes, int reps, pins_result* res, void* stream, pins_params* best,
+                           pins_tune_trial* trials, int max_trials, int32_t* ntrials);
 
 /* ---- Measurement support ----
  * Issue rate of the hardware float exponential on HIP device `device`, the
@@ -314,17 +331,22 @@ int pins_probe_exp_rate(int device, int blocks, int iters, double* exps_per_s, d
  * arrays or n < 0; PINS_EDEVICE on runtime failure. */
 int pins_probe_texp(const double* x, double* y, int n, void* stream);
 
-/* ---- Serving (continuous admission of requests onto concurrent batches) ----
+/* ---- Serving (continuous batching) ----
  * A server owns `workers` (1..4) solver threads on HIP device `device`, each
- * with its own context and HIP stream.  A worker that becomes free takes every
- * queued request it can -- in arrival order, of the same cost-kind family
- * (grid, or dense/points) as the oldest one, at most max_batch of them, with
- * the batch's workspace (pins_workspace_bytes) within hbm_budget bytes
- * (0 = no limit; the oldest request is always admitted) -- and solves them as
- * one batch with the parameters *p (p->streams is ignored).  Requests that
- * arrive while other batches run are admitted as workers free up; batches of
- * different workers overlap on the device.  Each result is bitwise the one
- * its problem gets alone.  The server is used from any number of host threads. */
+ * with its own HIP stream and a live batch of up to max_batch requests whose
+ * workspaces (and input/output staging) are carved from a device arena of
+ * hbm_budget bytes (0 = 4 GiB) per worker.  A worker advances every request in
+ * its batch by one outer iteration of Alg. 2 per round; between two rounds it
+ * admits queued requests -- in arrival order, of the cost-kind family (grid,
+ * or dense/points) of its batch, while a slot and arena room are free -- so
+ * requests that arrive while others are on the GPU join them at the next
+ * outer-iteration boundary, and each request leaves its batch as soon as its
+ * own K outer iterations are done.  Batches of different workers overlap on
+ * the device.  Each result is bitwise the one its problem gets alone with the
+ * same parameters *p (p->streams, p->graphs and p->profile are ignored; the
+ * implicit shift and hvp 0 or 1 are required, else PINS_EUNSUPPORTED).  A
+ * request that does not fit into an empty batch's arena completes with
+ * PINS_ENOMEM.  The server is used from any number of host threads. */
 typedef struct pins_server pins_server;
 int pins_server_create(int device, int workers, int max_batch, size_t hbm_budget, const pins_params* p,
                        pins_server** out);

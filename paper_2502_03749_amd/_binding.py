@@ -42,7 +42,12 @@ class Params(ctypes.Structure):
                 ("rho_levels", ctypes.c_int32), ("rho", ctypes.c_double), ("budget", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("shift_mode", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("profile_mask", ctypes.c_int32), ("hvp", ctypes.c_int32),
-                ("hvp_switch", ctypes.c_int32), ("graphs", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("hvp_switch", ctypes.c_int32), ("graphs", ctypes.c_int32), ("tile_rows", ctypes.c_int32 * 4)]
+
+
+class TuneTrial(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int32), ("graphs", ctypes.c_int32), ("tile_rows", ctypes.c_int32 * 4),
+                ("ms", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -114,7 +119,8 @@ def lib():
                                         ctypes.c_int32, ctypes.POINTER(State), ctypes.POINTER(Result)]
         L.pins_tune_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
                                              ctypes.c_int, ctypes.c_int, ctypes.POINTER(Result), vp,
-                                             ctypes.POINTER(ctypes.c_int32), _D]
+                                             ctypes.POINTER(Params), ctypes.POINTER(TuneTrial), ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int32)]
         L.pins_probe_exp_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D]
         L.pins_probe_texp.argtypes = [vp, vp, ctypes.c_int, vp]
         L.pins_solve_batch_device.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(Params),
@@ -144,6 +150,8 @@ def params(**kw) -> Params:
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
+        if k == "tile_rows":
+            v = (ctypes.c_int32 * 4)(*v)
         setattr(p, k, v)
     return p
 
@@ -250,16 +258,21 @@ class Context:
         return P, R
 
     def tune_batch_device(self, problems, prm: Params, outs, max_lanes=4, reps=2, stream=None):
-        """pins_tune_batch_device: the fastest lane count (params.streams) for this batch.
+        """pins_tune_batch_device: the fastest lanes / graph replay / rows per tile for this batch.
 
-        Same arguments as solve_batch_device.  Returns (best, [ms with 1 .. max_lanes lanes]).
+        Same arguments as solve_batch_device.  Returns (best Params, [trials as dicts in order]).
         """
         P, R = self._batch_args(problems, outs)
-        best = ctypes.c_int32(0)
-        ms = (ctypes.c_double * max_lanes)()
+        best = Params()
+        maxt = 16
+        trials = (TuneTrial * maxt)()
+        nt = ctypes.c_int32(0)
         self._check(lib().pins_tune_batch_device(self.h, P, len(problems), ctypes.byref(prm), max_lanes, reps, R,
-                                                 ctypes.c_void_p(stream or 0), ctypes.byref(best), ms))
-        return best.value, list(ms)
+                                                 ctypes.c_void_p(stream or 0), ctypes.byref(best), trials, maxt,
+                                                 ctypes.byref(nt)))
+        out = [dict(streams=t.streams, graphs=t.graphs, tile_rows=list(t.tile_rows), ms=t.ms)
+               for t in trials[:min(nt.value, maxt)]]
+        return best, out
 
     def solve_device(self, problem, prm: Params, out, stream=None):
         cnt_rc, res = self.solve_batch_device([problem], prm, [out], stream)

@@ -13,6 +13,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
@@ -20,6 +22,7 @@
 #include "pins.h"
 #include "pins_internal.h"
 #include "pins_launch.h"
+#include "pins_live.h"
 
 using namespace pins;
 
@@ -92,6 +95,16 @@ struct InstPlan {
     size_t C, x, y, a, b, alpha, beta, X;  // host-API staging
 };
 
+// Size class of an instance for params.tile_rows: m in [1, 64), [64, 256),
+// [256, 1024), [1024, ...).
+int size_class(int m) { return m < 64 ? 0 : m < 256 ? 1 : m < 1024 ? 2 : 3; }
+
+// Rows per tile of the dense passes: params.tile_rows of the instance's class (0 = TILE_RMAX).
+int tile_rows_for(const pins_params& p, int m) {
+    const int r = p.tile_rows[size_class(m)];
+    return r > 0 ? r : TILE_RMAX;
+}
+
 long nnz_capacity(int m, int n, double budget) {
     const double lim = std::ceil(budget * (double)(m + n - 1));
     const double mn = (double)m * (double)n;
@@ -105,7 +118,7 @@ InstPlan plan_instance(Carver& cv, const pins_problem& P, const pins_params& p, 
     q.m = m;
     q.n = n;
     q.d = P.d;
-    q.R = std::min(TILE_RMAX, m);
+    q.R = std::min(tile_rows_for(p, m), m);
     q.nrb = (m + q.R - 1) / q.R;
     q.ncb = (n + TILE_C - 1) / TILE_C;
     // kept entries plus up to 3 pads per row of S or S^T, rounded to quads
@@ -217,6 +230,8 @@ void check_params(const pins_params& p) {
         fail(PINS_EINVAL, "unknown shift_mode");
     if (p.hvp < 0 || p.hvp > 2) fail(PINS_EINVAL, "hvp must be 0 (sparsified), 1 (matrix-free) or 2 (switch)");
     if (p.hvp_switch < 0) fail(PINS_EINVAL, "hvp_switch must be >= 0");
+    for (int c = 0; c < 4; ++c)
+        if (p.tile_rows[c] < 0 || p.tile_rows[c] > TILE_RMAX) fail(PINS_EINVAL, "tile_rows must be in [0, 16]");
 }
 
 void check_problem_shape(const pins_problem& P) {
@@ -240,6 +255,123 @@ void check_marginal(const double* v, int len, const char* name) {
         s += v[i];
     }
     if (std::fabs(s - 1.0) > 1e-10) fail(PINS_EINVAL, std::string(name) + " must sum to 1 (|sum-1| <= 1e-10)");
+}
+
+// Device descriptor of one instance whose arrays are carved at `base` by plan
+// L: with host_api the inputs are copied from the host into the staging areas
+// of the plan (and the outputs go to its staging areas), else the problem's
+// and result's device pointers are used; a point-cloud cost is formed on the
+// matrix cores into the plan's cost array.  Everything is enqueued on st.
+DevInst build_inst(const InstPlan& L, const pins_problem& P, char* base, bool host_api, bool mat, const pins_result& r,
+                   hipStream_t st) {
+    auto Dp = [&](size_t off) { return off == NONE ? (double*)nullptr : (double*)(base + off); };
+    auto Ip = [&](size_t off) { return (int*)(base + off); };
+    DevInst I;
+    std::memset(&I, 0, sizeof(I));
+    const double *dC = P.C, *dx = P.x, *dy = P.y, *da = P.a, *db = P.b;
+    if (host_api) {
+        const size_t D = sizeof(double);
+        if (P.kind == PINS_COST_DENSE) {
+            HIPCHK(hipMemcpyAsync(Dp(L.C), P.C, D * L.m * L.n, hipMemcpyHostToDevice, st));
+            dC = Dp(L.C);
+        }
+        if (P.kind == PINS_COST_POINTS) {
+            HIPCHK(hipMemcpyAsync(Dp(L.x), P.x, D * L.m * P.d, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(Dp(L.y), P.y, D * L.n * P.d, hipMemcpyHostToDevice, st));
+            dx = Dp(L.x);
+            dy = Dp(L.y);
+        }
+        HIPCHK(hipMemcpyAsync(Dp(L.a), P.a, D * L.m, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(Dp(L.b), P.b, D * L.n, hipMemcpyHostToDevice, st));
+        da = Dp(L.a);
+        db = Dp(L.b);
+    }
+    I.m = L.m;
+    I.n = L.n;
+    I.grid_s = P.grid_s;
+    I.R = L.R;
+    I.nrb = L.nrb;
+    I.ncb = L.ncb;
+    I.nnz_cap = L.cap;
+    I.cgfmt = cg_format(L.m, L.n);
+    I.ldc = L.n;
+    I.a = da;
+    I.b = db;
+    if (P.kind == PINS_COST_DENSE) {
+        I.cbase = dC;
+    } else if (P.kind == PINS_COST_POINTS) {
+        I.cbase = Dp(L.Cpts);
+        launch_points_cost(st, dx, dy, L.m, L.n, P.d, Dp(L.Cpts));
+        HIPCHK(hipGetLastError());
+    }
+    if (P.cost_scale > 0.0) {
+        I.bscale = P.cost_scale;
+    } else if (P.kind == PINS_COST_GRID) {
+        I.bscale = P.grid_s > 1 ? 1.0 / (2.0 * (double)(P.grid_s - 1) * (double)(P.grid_s - 1)) : 1.0;
+    } else {
+        I.bscale = -1.0;  // replaced by 1/max C on the device
+    }
+    I.Ck = Dp(L.Ck);
+    I.csrc = mat ? I.Ck : I.cbase;
+    I.cscale = mat ? 1.0 : I.bscale;
+    I.loga = Dp(L.loga);
+    I.logb = Dp(L.logb);
+    I.F = Dp(L.F);
+    I.G = Dp(L.G);
+    I.Ah = Dp(L.Ah);
+    I.Bh = Dp(L.Bh);
+    I.rc = Dp(L.rc);
+    I.d = Dp(L.dir);
+    I.cgw = Dp(L.cgw);
+    I.part = Dp(L.part);
+    I.part2 = Dp(L.part2);
+    I.blk = Dp(L.blk);
+    I.blk2 = Dp(L.blk2);
+    I.hist = Ip(L.hist);
+    I.cntr = Ip(L.cntr);
+    I.cntc = Ip(L.cntc);
+    I.rowptr = Ip(L.rowptr);
+    I.col = Ip(L.col);
+    I.val = Dp(L.val);
+    I.colptr = Ip(L.colptr);
+    I.rowT = Ip(L.rowT);
+    I.valT = Dp(L.valT);  // reinterpreted by the kernels per cgfmt and LaunchCtx::sp_f32
+    I.rowbin = Ip(L.rowbin);
+    if (host_api) {
+        I.alpha = Dp(L.alpha);
+        I.beta = Dp(L.beta);
+        I.X = Dp(L.X);
+    } else {
+        I.alpha = r.alpha;
+        I.beta = r.beta;
+        I.X = r.X;
+    }
+    return I;
+}
+
+// Launch-wide facts of a batch of descriptors: sizes, flat-grid totals, the CG
+// kinds present and the storage of S.
+void fill_launch(LaunchCtx& L, const DevInst* hI, int count, const pins_params& p) {
+    L.sp_f32 = p.precision == PINS_MIXED_FAST ? 1 : 0;
+    L.any_small = L.any_wide16 = L.any_wide32 = false;
+    L.max_mn_small = 0;
+    L.max_m = L.max_n = L.max_mn = L.max_tiles = 0;
+    for (int q = 0; q < count; ++q) {
+        const DevInst& I = hI[q];
+        L.max_m = std::max(L.max_m, I.m);
+        L.max_n = std::max(L.max_n, I.n);
+        L.max_mn = std::max(L.max_mn, I.m + I.n);
+        L.max_tiles = std::max(L.max_tiles, I.nrb * I.ncb);
+        const int f = I.cgfmt;
+        if (!(f & 1)) {
+            L.any_small = true;
+            L.max_mn_small = std::max(L.max_mn_small, I.m + I.n);
+        } else if (f & 2) {
+            L.any_wide16 = true;
+        } else {
+            L.any_wide32 = true;
+        }
+    }
 }
 
 // One event pair per launch when profiling; summed per kernel class at the end.
@@ -270,7 +402,7 @@ struct Prof {
 };
 
 template <class Fn>
-void run(Lane* c, hipStream_t st, int kind, Fn&& fn) {
+void run_launch(Lane* c, hipStream_t st, int kind, Fn&& fn) {
     Prof pr(c, st, kind);
     fn();
     HIPCHK(hipGetLastError());
@@ -321,6 +453,183 @@ const Ctrl* readback(Lane* c, hipStream_t st, const Ctrl* d_ctrl, int count) {
     return h;
 }
 
+// The host sequencing of one outer iteration of Alg. 2 over a batch: the
+// shift (when asked), the Sinkhorn warm-up and the Newton steps, until no
+// instance is warming up or iterating.  Kept across the outer iterations of a
+// solve (or of a live batch) for the warm-up heuristic and the captured graph.
+struct GraphHolder {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    ~GraphHolder() {
+        if (e) (void)hipGraphExecDestroy(e);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+struct OuterRunner {
+    Lane* ctx;
+    hipStream_t st;
+    const LaunchCtx& L;
+    Ctrl* d_ctrl;
+    int count;
+    const pins_params& p;
+    int src, base_src;
+    bool quick_warm = false;  // every warm-up of the last outer iteration took one iteration
+    bool graphs_ok = false;   // params.graphs and a batch the captured sequence covers
+    GraphHolder gq;
+
+    void run(bool mf, bool do_shift) {
+        const bool f32 = p.precision != PINS_FP64;  // float warm-up sweeps
+        const int M_WARM = 1 << PH_WARM, M_FB = 1 << PH_FALLBACK;
+        // The launches of a Newton round up to its readback: Newton pass and merge,
+        // Sparsify, the one-block CG (sparsified products; the wide CG and the
+        // matrix-free products run their own loop), the first Armijo trial fused
+        // with the next Newton pass, and the early merge and decision.
+        auto newton_round = [&](bool mf_) {
+            run_k(PINS_K_GRAD, [&] { launch_grad(L, src); });
+            run_k(PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, false); });
+            if (!mf_) run_k(PINS_K_FILL, [&] { launch_sparsify(L, src); });
+            // sparsified products: the one-block CG for the instances with m + n <=
+            // WCG_MAX_N and the wide CG for the others (the choice is each
+            // instance's own); matrix-free products: the wide CG for every instance
+            if (!mf_ && L.any_small) run_k(PINS_K_PCG, [&] { launch_pcg(L); });
+            if (mf_ || L.any_wide16 || L.any_wide32) {
+                // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
+                const int hsrc = mf_ ? src : -1;
+                run_k(PINS_K_PCG_WIDE, [&] { launch_wcg_begin(L, hsrc); });
+                for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
+                    const Ctrl* hc = readback(ctx, st, d_ctrl, count);
+                    bool on = false;
+                    for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
+                    if (!on) break;
+                    for (int c = 0; c < chunk; ++c) run_k(PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc); });
+                }
+                run_k(PINS_K_PCG_WIDE, [&] { launch_wcg_end(L, hsrc); });
+            }
+            run_k(PINS_K_LS, [&] { launch_ls(L, src, true); });
+            // instances whose full step the fused first trial applied: the next
+            // gradient is formed, so merge it and take the convergence decision
+            // now (a subproblem that converged in one step then needs no further
+            // round of launches)
+            run_k(PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, true); });
+        };
+        // params.graphs: an outer iteration on the quick path (a shift, the
+        // previous warm-ups all took one iteration, sparsified products,
+        // one-block CGs only) launches shift, one warm-up iteration and the first
+        // Newton round with no readback in between; that sequence is captured
+        // once as a HIP graph and replayed.  Every kernel argument is the same
+        // in every outer iteration (the per-instance state lives in the control
+        // blocks), so a replay runs exactly the launches the sequence would make.
+        auto quick_sequence = [&] {
+            run_k(PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
+            run_k(PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
+            run_k(PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
+            run_k(PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
+            newton_round(false);
+        };
+        bool warm_unread = false, round_done = false;
+        if (graphs_ok && !mf && do_shift && quick_warm) {
+            if (!gq.e) {
+                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                try {
+                    quick_sequence();
+                } catch (...) {
+                    hipGraph_t bad = nullptr;
+                    (void)hipStreamEndCapture(st, &bad);
+                    if (bad) (void)hipGraphDestroy(bad);
+                    throw;
+                }
+                HIPCHK(hipStreamEndCapture(st, &gq.g));
+                HIPCHK(hipGraphInstantiate(&gq.e, gq.g, nullptr, nullptr, 0));
+            }
+            HIPCHK(hipGraphLaunch(gq.e, st));
+            warm_unread = true;
+            round_done = true;
+        } else if (do_shift) {
+            run_k(PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
+        }
+        // warm-up sweeps of the instances in the warm-up phase: chunks of W
+        // iterations, a readback after each, until none is left; returns the
+        // number of chunks
+        auto warm_loop = [&](int W) {
+            int chunks = 0;
+            for (;;) {
+                for (int w = 0; w < W; ++w) {
+                    run_k(PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
+                    run_k(PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
+                    run_k(PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
+                }
+                ++chunks;
+                const Ctrl* h = readback(ctx, st, d_ctrl, count);
+                bool any = false;
+                for (int q = 0; q < count; ++q) any |= h[q].phase == PH_WARM;
+                if (!any) return chunks;
+                W = std::min(2 * W, 8);
+            }
+        };
+        // After the shift, when every warm-up of the previous outer iteration
+        // took a single iteration, one iteration is launched and the first Newton
+        // round follows without a readback: the Newton kernels act only on the
+        // instances that iteration moved to the Newton phase, and any still in the
+        // warm-up finish it after the round's readback and join the next round.
+        if (p.max_sinkhorn > 0 && !round_done) {
+            if (quick_warm) {
+                run_k(PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
+                run_k(PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
+                run_k(PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
+                warm_unread = true;
+            } else {
+                quick_warm = warm_loop(1) == 1;
+            }
+        }
+        // Newton steps; a readback after each (the first round may have gone out
+        // with the captured sequence)
+        for (;;) {
+            if (!round_done) newton_round(mf);
+            round_done = false;
+            // one readback per Newton step: who is still iterating, who needs more
+            // Armijo trials, who will take the Sinkhorn fallback
+            const Ctrl* h = readback(ctx, st, d_ctrl, count);
+            bool any = false, pending = false, failed = false, unapplied = false, warm = false;
+            for (int q = 0; q < count; ++q) {
+                any |= h[q].phase == PH_NEWTON;
+                pending |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_PENDING;
+                failed |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_FAILED;
+                unapplied |= h[q].phase == PH_NEWTON && h[q].ls_state != LS_APPLIED;
+                warm |= h[q].phase == PH_WARM;
+            }
+            if (warm_unread) {
+                warm_unread = false;
+                quick_warm = !warm;
+            }
+            if (!any && !warm) break;
+            for (int hh = 1; pending && hh < p.ls_max; hh += LS_T) {
+                run_k(PINS_K_LS, [&] { launch_ls(L, src, false); });
+                const Ctrl* h2 = readback(ctx, st, d_ctrl, count);
+                pending = false;
+                for (int q = 0; q < count; ++q) {
+                    pending |= h2[q].phase == PH_NEWTON && h2[q].ls_state == LS_PENDING;
+                    failed |= h2[q].phase == PH_NEWTON && h2[q].ls_state == LS_FAILED;
+                }
+            }
+            // the update (and the step's bookkeeping) of every instance whose full
+            // step the fused first trial has not already applied
+            if (unapplied) run_k(PINS_K_UPDATE, [&] { launch_update(L); });
+            if (failed) {
+                run_k(PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, false, M_FB); });
+                run_k(PINS_K_COL_LSE, [&] { launch_col_lse(L, src, false, M_FB); });
+                run_k(PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_FB); });
+            }
+            if (warm) warm_loop(2);  // the instances the single warm-up iteration left
+        }
+    }
+
+    template <class Fn>
+    void run_k(int kind, Fn&& fn) {
+        run_launch(ctx, st, kind, fn);
+    }
+};
+
 // A range of outer iterations for pins_solve_resume: start after
 // from->outer_done completed iterations (from = nullptr: at the start), stop
 // after `stop`, copy the state reached to *save when non-null.
@@ -366,7 +675,6 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     Ctrl* d_ctrl = (Ctrl*)(ws + B.ctrl);
     double* d_scratch = (double*)(ws + B.scratch);
     auto Dp = [&](size_t off) { return off == NONE ? (double*)nullptr : (double*)(ws + off); };
-    auto Ip = [&](size_t off) { return (int*)(ws + off); };
 
     const bool mat = p.shift_mode == PINS_SHIFT_MATERIALIZED;
     const int src = (grid0 && !mat) ? SRC_GRID : SRC_DENSE;  // exponent source
@@ -376,89 +684,8 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     std::vector<DevInst> hI(count);
     bool need_max = false;
     for (int q = 0; q < count; ++q) {
-        const pins_problem& P = probs[q];
-        const InstPlan& L = B.plans[q];
-        DevInst& I = hI[q];
-        std::memset(&I, 0, sizeof(I));
-        const double *dC = P.C, *dx = P.x, *dy = P.y, *da = P.a, *db = P.b;
-        if (host_api) {
-            const size_t D = sizeof(double);
-            if (P.kind == PINS_COST_DENSE) {
-                HIPCHK(hipMemcpyAsync(Dp(L.C), P.C, D * L.m * L.n, hipMemcpyHostToDevice, st));
-                dC = Dp(L.C);
-            }
-            if (P.kind == PINS_COST_POINTS) {
-                HIPCHK(hipMemcpyAsync(Dp(L.x), P.x, D * L.m * P.d, hipMemcpyHostToDevice, st));
-                HIPCHK(hipMemcpyAsync(Dp(L.y), P.y, D * L.n * P.d, hipMemcpyHostToDevice, st));
-                dx = Dp(L.x);
-                dy = Dp(L.y);
-            }
-            HIPCHK(hipMemcpyAsync(Dp(L.a), P.a, D * L.m, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(Dp(L.b), P.b, D * L.n, hipMemcpyHostToDevice, st));
-            da = Dp(L.a);
-            db = Dp(L.b);
-        }
-        I.m = L.m;
-        I.n = L.n;
-        I.grid_s = P.grid_s;
-        I.R = L.R;
-        I.nrb = L.nrb;
-        I.ncb = L.ncb;
-        I.nnz_cap = L.cap;
-        I.cgfmt = cg_format(L.m, L.n);
-        I.ldc = L.n;
-        I.a = da;
-        I.b = db;
-        if (P.kind == PINS_COST_DENSE) {
-            I.cbase = dC;
-        } else if (P.kind == PINS_COST_POINTS) {
-            I.cbase = Dp(L.Cpts);
-            launch_points_cost(st, dx, dy, L.m, L.n, P.d, Dp(L.Cpts));
-            HIPCHK(hipGetLastError());
-        }
-        if (P.cost_scale > 0.0) {
-            I.bscale = P.cost_scale;
-        } else if (P.kind == PINS_COST_GRID) {
-            I.bscale = P.grid_s > 1 ? 1.0 / (2.0 * (double)(P.grid_s - 1) * (double)(P.grid_s - 1)) : 1.0;
-        } else {
-            I.bscale = -1.0;  // replaced by 1/max C on the device
-        }
-        if (P.kind != PINS_COST_GRID) need_max = true;
-        I.Ck = Dp(L.Ck);
-        I.csrc = mat ? I.Ck : I.cbase;
-        I.cscale = mat ? 1.0 : I.bscale;
-        I.loga = Dp(L.loga);
-        I.logb = Dp(L.logb);
-        I.F = Dp(L.F);
-        I.G = Dp(L.G);
-        I.Ah = Dp(L.Ah);
-        I.Bh = Dp(L.Bh);
-        I.rc = Dp(L.rc);
-        I.d = Dp(L.dir);
-        I.cgw = Dp(L.cgw);
-        I.part = Dp(L.part);
-        I.part2 = Dp(L.part2);
-        I.blk = Dp(L.blk);
-        I.blk2 = Dp(L.blk2);
-        I.hist = Ip(L.hist);
-        I.cntr = Ip(L.cntr);
-        I.cntc = Ip(L.cntc);
-        I.rowptr = Ip(L.rowptr);
-        I.col = Ip(L.col);
-        I.val = Dp(L.val);
-        I.colptr = Ip(L.colptr);
-        I.rowT = Ip(L.rowT);
-        I.valT = Dp(L.valT);  // reinterpreted by the kernels per cgfmt and LaunchCtx::sp_f32
-        I.rowbin = Ip(L.rowbin);
-        if (host_api) {
-            I.alpha = Dp(L.alpha);
-            I.beta = Dp(L.beta);
-            I.X = Dp(L.X);
-        } else {
-            I.alpha = res[q].alpha;
-            I.beta = res[q].beta;
-            I.X = res[q].X;
-        }
+        hI[q] = build_inst(B.plans[q], probs[q], ws, host_api, mat, res[q], st);
+        if (probs[q].kind != PINS_COST_GRID) need_max = true;
     }
     {
         char* pin = (char*)pinned(ctx, sizeof(Ctrl) * count + sizeof(DevInst) * count +
@@ -481,28 +708,11 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
     L.insts_mut = d_insts;
     L.ctrl = d_ctrl;
     L.count = count;
-    L.max_m = B.max_m;
-    L.max_n = B.max_n;
-    L.max_mn = B.max_mn;
-    L.max_tiles = B.max_tiles;
+    // sizes, the CG kinds present in the batch; the CG's copy of S holds float
+    // values in the fast-mixed precision only (CG vectors and sums stay double)
+    fill_launch(L, hI.data(), count, p);
     L.total_tiles = B.toff.back();
     L.total_rowblk = B.roff.back();
-    // the CG's copy of S: float values in the fast-mixed precision only (the
-    // CG vectors and all sums stay double); the CG kinds present in the batch
-    L.sp_f32 = p.precision == PINS_MIXED_FAST ? 1 : 0;
-    L.any_small = L.any_wide16 = L.any_wide32 = false;
-    L.max_mn_small = 0;
-    for (int q = 0; q < count; ++q) {
-        const int f = hI[q].cgfmt;
-        if (!(f & 1)) {
-            L.any_small = true;
-            L.max_mn_small = std::max(L.max_mn_small, hI[q].m + hI[q].n);
-        } else if (f & 2) {
-            L.any_wide16 = true;
-        } else {
-            L.any_wide32 = true;
-        }
-    }
     KP& kp = L.kp;
     std::memset(&kp, 0, sizeof(kp));
     kp.eta = p.eta;
@@ -558,6 +768,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
             k_begin = S.outer_done;
             const double kap = (double)S.outer_done;
             const int kprev = S.outer_done - 1;  // the coming shift advances it to outer_done
+            const int done_phase = PH_DONE;      // outer iteration outer_done - 1 finished: the shift applies
             const int fl = S.flags & 2;
             HIPCHK(hipMemcpyAsync(Dp(Lp.F), S.F, D * Lp.m, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(Dp(Lp.G), S.G, D * Lp.n, hipMemcpyHostToDevice, st));
@@ -565,174 +776,21 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
             HIPCHK(hipMemcpyAsync(Dp(Lp.Bh), S.B, D * Lp.n, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(&d_ctrl[0].kappa, &kap, sizeof(double), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(&d_ctrl[0].k_out, &kprev, sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(&d_ctrl[0].phase, &done_phase, sizeof(int), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(&d_ctrl[0].flags, &fl, sizeof(int), hipMemcpyHostToDevice, st));
             HIPCHK(hipStreamSynchronize(st));
         }
     }
 
-    const bool f32 = p.precision != PINS_FP64;  // float warm-up sweeps
     // matrix-free Hessian products (no Sparsify) in outer iteration k
     auto matrix_free = [&](int k) { return p.hvp == 1 || (p.hvp == 2 && k < p.hvp_switch); };
-    const int M_WARM = 1 << PH_WARM, M_FB = 1 << PH_FALLBACK;
-    bool quick_warm = false;  // every warm-up of the last outer iteration took one iteration
-    // The launches of a Newton round up to its readback: Newton pass and merge,
-    // Sparsify, the one-block CG (sparsified products; the wide CG and the
-    // matrix-free products run their own loop), the first Armijo trial fused
-    // with the next Newton pass, and the early merge and decision.
-    auto newton_round = [&](bool mf) {
-        run(ctx, st, PINS_K_GRAD, [&] { launch_grad(L, src); });
-        run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, false); });
-        if (!mf) run(ctx, st, PINS_K_FILL, [&] { launch_sparsify(L, src); });
-        // sparsified products: the one-block CG for the instances with m + n <=
-        // WCG_MAX_N and the wide CG for the others (the choice is each
-        // instance's own); matrix-free products: the wide CG for every instance
-        if (!mf && L.any_small) run(ctx, st, PINS_K_PCG, [&] { launch_pcg(L); });
-        if (mf || L.any_wide16 || L.any_wide32) {
-            // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
-            const int hsrc = mf ? src : -1;
-            run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_begin(L, hsrc); });
-            for (int chunk = 4;; chunk = std::min(2 * chunk, 32)) {
-                const Ctrl* hc = readback(ctx, st, d_ctrl, count);
-                bool on = false;
-                for (int q = 0; q < count; ++q) on |= hc[q].phase == PH_NEWTON && hc[q].cg_on;
-                if (!on) break;
-                for (int c = 0; c < chunk; ++c) run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_iter(L, hsrc); });
-            }
-            run(ctx, st, PINS_K_PCG_WIDE, [&] { launch_wcg_end(L, hsrc); });
-        }
-        run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, true); });
-        // instances whose full step the fused first trial applied: the next
-        // gradient is formed, so merge it and take the convergence decision
-        // now (a subproblem that converged in one step then needs no further
-        // round of launches)
-        run(ctx, st, PINS_K_GRAD_MERGE, [&] { launch_grad_merge(L, true); });
-    };
-    // params.graphs: an outer iteration on the quick path (k > 0, the previous
-    // warm-ups all took one iteration, sparsified products, one-block CGs only)
-    // launches shift, one warm-up iteration and the first Newton round with no
-    // readback in between; that sequence is captured once as a HIP graph and
-    // replayed.  Every kernel argument is the same in every outer iteration
-    // (the per-instance state lives in the control blocks), so a replay runs
-    // exactly the launches the sequence would make.
-    struct GraphHolder {
-        hipGraph_t g = nullptr;
-        hipGraphExec_t e = nullptr;
-        ~GraphHolder() {
-            if (e) (void)hipGraphExecDestroy(e);
-            if (g) (void)hipGraphDestroy(g);
-        }
-    } gq;
-    const bool graphs_ok = p.graphs && !ctx->profile && st != nullptr && L.any_small && !L.any_wide16 &&
-                           !L.any_wide32 && p.max_sinkhorn > 0;
-    auto quick_sequence = [&] {
-        run(ctx, st, PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
-        run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
-        run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
-        run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
-        newton_round(false);
-    };
-    for (int k = k_begin; k < k_end; ++k) {
-        const bool mf = matrix_free(k);
-        bool warm_unread = false, round_done = false;
-        if (graphs_ok && !mf && k > 0 && quick_warm) {
-            if (!gq.e) {
-                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-                try {
-                    quick_sequence();
-                } catch (...) {
-                    hipGraph_t bad = nullptr;
-                    (void)hipStreamEndCapture(st, &bad);
-                    if (bad) (void)hipGraphDestroy(bad);
-                    throw;
-                }
-                HIPCHK(hipStreamEndCapture(st, &gq.g));
-                HIPCHK(hipGraphInstantiate(&gq.e, gq.g, nullptr, nullptr, 0));
-            }
-            HIPCHK(hipGraphLaunch(gq.e, st));
-            warm_unread = true;
-            round_done = true;
-        } else if (k > 0) {
-            run(ctx, st, PINS_K_SHIFT, [&] { launch_shift(L, base_src); });
-        }
-        // warm-up: chunks of W Sinkhorn iterations, then a readback
-        // warm-up sweeps of the instances in the warm-up phase: chunks of W
-        // iterations, a readback after each, until none is left; returns the
-        // number of chunks
-        auto warm_loop = [&](int W) {
-            int chunks = 0;
-            for (;;) {
-                for (int w = 0; w < W; ++w) {
-                    run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
-                    run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
-                    run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
-                }
-                ++chunks;
-                const Ctrl* h = readback(ctx, st, d_ctrl, count);
-                bool any = false;
-                for (int q = 0; q < count; ++q) any |= h[q].phase == PH_WARM;
-                if (!any) return chunks;
-                W = std::min(2 * W, 8);
-            }
-        };
-        // After the shift, when every warm-up of the previous outer iteration
-        // took a single iteration, one iteration is launched and the first Newton
-        // round follows without a readback: the Newton kernels act only on the
-        // instances that iteration moved to the Newton phase, and any still in the
-        // warm-up finish it after the round's readback and join the next round.
-        if (p.max_sinkhorn > 0 && !round_done) {
-            if (quick_warm) {
-                run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, f32, M_WARM); });
-                run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, f32, M_WARM); });
-                run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_WARM); });
-                warm_unread = true;
-            } else {
-                quick_warm = warm_loop(1) == 1;
-            }
-        }
-        // Newton steps; a readback after each (the first round may have gone out
-        // with the captured sequence)
-        for (;;) {
-            if (!round_done) newton_round(mf);
-            round_done = false;
-            // one readback per Newton step: who is still iterating, who needs more
-            // Armijo trials, who will take the Sinkhorn fallback
-            const Ctrl* h = readback(ctx, st, d_ctrl, count);
-            bool any = false, pending = false, failed = false, unapplied = false, warm = false;
-            for (int q = 0; q < count; ++q) {
-                any |= h[q].phase == PH_NEWTON;
-                pending |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_PENDING;
-                failed |= h[q].phase == PH_NEWTON && h[q].ls_state == LS_FAILED;
-                unapplied |= h[q].phase == PH_NEWTON && h[q].ls_state != LS_APPLIED;
-                warm |= h[q].phase == PH_WARM;
-            }
-            if (warm_unread) {
-                warm_unread = false;
-                quick_warm = !warm;
-            }
-            if (!any && !warm) break;
-            for (int hh = 1; pending && hh < p.ls_max; hh += LS_T) {
-                run(ctx, st, PINS_K_LS, [&] { launch_ls(L, src, false); });
-                const Ctrl* h2 = readback(ctx, st, d_ctrl, count);
-                pending = false;
-                for (int q = 0; q < count; ++q) {
-                    pending |= h2[q].phase == PH_NEWTON && h2[q].ls_state == LS_PENDING;
-                    failed |= h2[q].phase == PH_NEWTON && h2[q].ls_state == LS_FAILED;
-                }
-            }
-            // the update (and the step's bookkeeping) of every instance whose full
-            // step the fused first trial has not already applied
-            if (unapplied) run(ctx, st, PINS_K_UPDATE, [&] { launch_update(L); });
-            if (failed) {
-                run(ctx, st, PINS_K_ROW_LSE, [&] { launch_row_lse(L, src, false, M_FB); });
-                run(ctx, st, PINS_K_COL_LSE, [&] { launch_col_lse(L, src, false, M_FB); });
-                run(ctx, st, PINS_K_COL_MERGE, [&] { launch_col_merge(L, M_FB); });
-            }
-            if (warm) warm_loop(2);  // the instances the single warm-up iteration left
-        }
-    }
+    OuterRunner R{ctx, st, L, d_ctrl, count, p, src, base_src};
+    R.graphs_ok = p.graphs && !ctx->profile && st != nullptr && L.any_small && !L.any_wide16 && !L.any_wide32 &&
+                  p.max_sinkhorn > 0;
+    for (int k = k_begin; k < k_end; ++k) R.run(matrix_free(k), k > 0);
     bool want_x = false;
     for (int q = 0; q < count; ++q) want_x |= hI[q].X != nullptr;
-    run(ctx, st, PINS_K_FINAL, [&] { launch_final(L, base_src, (double)k_end, want_x); });
+    run_launch(ctx, st, PINS_K_FINAL, [&] { launch_final(L, base_src, (double)k_end, want_x); });
     const Ctrl* h = readback(ctx, st, d_ctrl, count);
     if (rio && rio->save) {
         pins_state& S = *rio->save;
@@ -921,6 +979,437 @@ int guarded(pins_ctx* ctx, Fn&& fn) {
 
 }  // namespace
 
+
+// ---------------------------------------------------------------------------
+// Live batch (pins_live.h): the serving runtime's engine.
+// ---------------------------------------------------------------------------
+namespace pins {
+
+struct LiveSlot {
+    bool live = false, fresh = false;
+    bool scaled = false;        // the set-up computes its scale 1/max C on the device
+    int64_t id = 0;
+    size_t off = 0, bytes = 0;  // arena region
+    InstPlan plan;              // offsets relative to the region
+    pins_problem prob{};        // sizes and kind (input pointers are not kept)
+    int k_done = 0;             // completed outer iterations
+    double* alpha_out = nullptr;
+    double* beta_out = nullptr;
+};
+
+struct LiveBatch {
+    int device = 0;
+    pins_params p{};
+    int max_slots = 0;
+    Lane lane;  // its own non-blocking stream and pinned staging; no profiling
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::map<size_t, size_t> freel;  // free regions of the arena: offset -> bytes
+    char* meta = nullptr;            // descriptors, control blocks, offsets, scratch, gates
+    size_t o_insts = 0, o_ctrl = 0, o_offs = 0, o_scr = 0, o_gate = 0;
+    std::vector<LiveSlot> slots;
+    std::vector<DevInst> hI;
+    bool grid = false;
+    int nlive = 0;
+    bool dirty = true;
+    LaunchCtx L{};
+    std::unique_ptr<OuterRunner> R;
+    int src = SRC_DENSE, base_src = SRC_DENSE;
+    ~LiveBatch() {
+        (void)hipSetDevice(device);
+        R.reset();
+        if (arena) (void)hipFree(arena);
+        if (meta) (void)hipFree(meta);
+        for (hipEvent_t e : lane.events) (void)hipEventDestroy(e);
+        if (lane.pinned) (void)hipHostFree(lane.pinned);
+        if (lane.stream) (void)hipStreamDestroy(lane.stream);
+    }
+};
+
+namespace {
+
+size_t plan_bytes(const pins_problem& P, const pins_params& p, InstPlan* out) {
+    Carver cv;
+    const InstPlan q = plan_instance(cv, P, p, true, false);
+    if (out) *out = q;
+    return al256(cv.off);
+}
+
+bool arena_take(LiveBatch* B, size_t need, size_t* off) {
+    for (auto it = B->freel.begin(); it != B->freel.end(); ++it) {
+        if (it->second < need) continue;
+        *off = it->first;
+        const size_t rest = it->second - need;
+        const size_t at = it->first + need;
+        B->freel.erase(it);
+        if (rest) B->freel[at] = rest;
+        return true;
+    }
+    return false;
+}
+
+void arena_give(LiveBatch* B, size_t off, size_t bytes) {
+    auto it = B->freel.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != B->freel.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        B->freel.erase(nx);
+    }
+    if (it != B->freel.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            B->freel.erase(it);
+        }
+    }
+}
+
+// result scalars of a finished (or rejected) instance from its control block
+pins_result live_result(const LiveBatch* B, const Ctrl& S, int K, double scale) {
+    pins_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.cost = S.cost;
+    r.eps = B->p.eta / (double)K;
+    r.resid = S.resid;
+    r.dual = S.dual;
+    r.gap = S.cost - S.dual;
+    r.entropy = S.entropy;
+    r.cost_scale = scale;
+    r.flags = S.flags | (S.nonfinite ? 4 : 0);
+    r.outer_iters = K;
+    r.sinkhorn_iters = S.sink_total;
+    r.newton_iters = S.newton_total;
+    r.cg_iters = S.cg_total;
+    r.fallbacks = S.fb_total;
+    r.nnz_last = S.nnz;
+    r.status = S.nonfinite ? PINS_ENUMERIC : ((S.flags & 1) ? PINS_NOT_CONVERGED : PINS_OK);
+    return r;
+}
+
+// The slot leaves: its control block is cleared on the stream (phase DONE, no
+// outer iteration left, so no later launch acts on it) before its arena region
+// can be handed to another problem.
+void live_kill(LiveBatch* B, int q) {
+    LiveSlot& Sl = B->slots[q];
+    if (!Sl.live) return;
+    launch_zero(B->lane.stream, B->meta + B->o_ctrl + sizeof(Ctrl) * (size_t)q, sizeof(Ctrl));
+    arena_give(B, Sl.off, Sl.bytes);
+    Sl.live = false;
+    Sl.fresh = false;
+    B->nlive -= 1;
+    B->dirty = true;
+}
+
+// descriptors and flat-grid offsets of the current slots (dead slots: no tiles,
+// phase DONE in their control blocks, so no kernel acts on them)
+void live_upload(LiveBatch* B, int count) {
+    std::vector<int> toff(1, 0), roff(1, 0);
+    std::vector<DevInst> live;
+    for (int q = 0; q < count; ++q) {
+        const LiveSlot& Sl = B->slots[q];
+        const DevInst& I = B->hI[q];
+        toff.push_back(toff.back() + (Sl.live ? I.nrb * I.ncb : 0));
+        roff.push_back(roff.back() + (Sl.live ? (I.m + 3) / 4 : 0));
+        if (Sl.live) live.push_back(I);
+    }
+    LaunchCtx& L = B->L;
+    fill_launch(L, live.data(), (int)live.size(), B->p);
+    L.count = count;
+    L.kp.count = count;
+    L.total_tiles = toff.back();
+    L.total_rowblk = roff.back();
+    const hipStream_t st = B->lane.stream;
+    char* pin = (char*)pinned(&B->lane, sizeof(DevInst) * count + sizeof(int) * 2 * (size_t)(count + 1) + 64);
+    std::memcpy(pin, B->hI.data(), sizeof(DevInst) * count);
+    HIPCHK(hipMemcpyAsync(B->meta + B->o_insts, pin, sizeof(DevInst) * count, hipMemcpyHostToDevice, st));
+    int* ho = (int*)(pin + sizeof(DevInst) * count);
+    std::memcpy(ho, toff.data(), sizeof(int) * (count + 1));
+    std::memcpy(ho + count + 1, roff.data(), sizeof(int) * (count + 1));
+    HIPCHK(hipMemcpyAsync(B->meta + B->o_offs, ho, sizeof(int) * 2 * (count + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));  // the pinned area is reused by the readbacks
+    L.kp.toff = (const int*)(B->meta + B->o_offs);
+    L.kp.roff = L.kp.toff + count + 1;
+    B->dirty = false;
+}
+
+int live_round_impl(LiveBatch* B, std::vector<LiveDone>& done) {
+    HIPCHK(hipSetDevice(B->device));
+    const hipStream_t st = B->lane.stream;
+    int count = 0;
+    for (int q = 0; q < B->max_slots; ++q)
+        if (B->slots[q].live) count = q + 1;
+    if (count == 0) return PINS_OK;
+    DevInst* d_insts = (DevInst*)(B->meta + B->o_insts);
+    Ctrl* d_ctrl = (Ctrl*)(B->meta + B->o_ctrl);
+    double* d_scr = (double*)(B->meta + B->o_scr);
+    int* d_gate = (int*)(B->meta + B->o_gate);
+    // set-up of the problems admitted since the last round
+    bool any_fresh = false, any_old = false;
+    for (int q = 0; q < count; ++q) {
+        any_fresh |= B->slots[q].live && B->slots[q].fresh;
+        any_old |= B->slots[q].live && !B->slots[q].fresh;
+    }
+    if (B->dirty) live_upload(B, count);
+    if (any_fresh) {
+        for (int q = 0; q < count; ++q) {
+            LiveSlot& Sl = B->slots[q];
+            if (!Sl.live || !Sl.fresh) continue;
+            LaunchCtx Ls = B->L;
+            Ls.insts = d_insts + q;
+            Ls.insts_mut = d_insts + q;
+            Ls.ctrl = d_ctrl + q;
+            Ls.count = 1;
+            launch_zero(st, d_ctrl + q, sizeof(Ctrl));
+            Sl.scaled = Sl.prob.kind != PINS_COST_GRID && !(B->hI[q].bscale > 0.0);
+            if (Sl.scaled) launch_cost_max(Ls, d_scr + (size_t)SCRATCH_BLK * q, SCRATCH_BLK, 1);
+            launch_init(Ls, B->base_src);
+            HIPCHK(hipGetLastError());
+        }
+        const Ctrl* h = readback(&B->lane, st, d_ctrl, count);
+        for (int q = 0; q < count; ++q) {
+            LiveSlot& Sl = B->slots[q];
+            if (!Sl.live || !Sl.fresh) continue;
+            Sl.fresh = false;
+            if (h[q].margbad || h[q].nonfinite) {
+                LiveDone d;
+                d.id = Sl.id;
+                d.rc = PINS_EINVAL;
+                std::memset(&d.res, 0, sizeof(d.res));
+                d.res.status = PINS_EINVAL;
+                done.push_back(d);
+                live_kill(B, q);
+                continue;
+            }
+            // the scale the set-up chose (1/max C) is kept in the host copy of the descriptor
+            if (Sl.scaled) {
+                B->hI[q].bscale = h[q].scale;
+                B->hI[q].cscale = h[q].scale;
+            }
+        }
+        if (B->dirty) {
+            if (B->nlive == 0) return PINS_OK;
+            live_upload(B, count);
+        }
+    }
+    // one outer iteration of every problem (the shift acts on those past their first)
+    B->R->count = count;
+    B->R->run(B->p.hvp == 1, any_old);
+    int K = B->p.max_outer;
+    bool any_fin = false;
+    int* gate = (int*)pinned(&B->lane, sizeof(int) * count);
+    for (int q = 0; q < count; ++q) {
+        LiveSlot& Sl = B->slots[q];
+        gate[q] = 0;
+        if (!Sl.live) continue;
+        Sl.k_done += 1;
+        if (Sl.k_done >= K) {
+            gate[q] = 1;
+            any_fin = true;
+        }
+    }
+    if (!any_fin) return PINS_OK;
+    HIPCHK(hipMemcpyAsync(d_gate, gate, sizeof(int) * count, hipMemcpyHostToDevice, st));
+    run_launch(&B->lane, st, PINS_K_FINAL, [&] { launch_final(B->L, B->base_src, (double)K, false, d_gate); });
+    std::vector<char> fin(count, 0);
+    for (int q = 0; q < count; ++q) fin[q] = (char)gate[q];  // gate's staging is reused by the readback
+    const Ctrl* h = readback(&B->lane, st, d_ctrl, count);
+    std::vector<Ctrl> hc(h, h + count);
+    for (int q = 0; q < count; ++q) {
+        if (!fin[q]) continue;
+        LiveSlot& Sl = B->slots[q];
+        char* base = B->arena + Sl.off;
+        HIPCHK(hipMemcpyAsync(Sl.alpha_out, base + Sl.plan.alpha, sizeof(double) * Sl.plan.m, hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipMemcpyAsync(Sl.beta_out, base + Sl.plan.beta, sizeof(double) * Sl.plan.n, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int q = 0; q < count; ++q) {
+        if (!fin[q]) continue;
+        LiveSlot& Sl = B->slots[q];
+        LiveDone d;
+        d.id = Sl.id;
+        d.res = live_result(B, hc[q], K, B->hI[q].bscale);
+        d.rc = d.res.status;
+        done.push_back(d);
+        live_kill(B, q);
+    }
+    return PINS_OK;
+}
+
+}  // namespace
+
+LiveBatch* live_create(int device, const pins_params& p, int max_slots, size_t arena_bytes, std::string* err) {
+    try {
+        check_params(p);
+        if (p.shift_mode != PINS_SHIFT_IMPLICIT) fail(PINS_EUNSUPPORTED, "serving needs the implicit shift");
+        if (p.hvp == 2) fail(PINS_EUNSUPPORTED, "serving needs one kind of Hessian product throughout (hvp 0 or 1)");
+        if (max_slots < 1 || arena_bytes < 4096) fail(PINS_EINVAL, "bad live batch size");
+        std::unique_ptr<LiveBatch> B(new LiveBatch);
+        B->device = device;
+        B->p = p;
+        B->p.profile = 0;
+        B->p.graphs = 0;
+        B->max_slots = max_slots;
+        B->lane.device = device;
+        HIPCHK(hipSetDevice(device));
+        HIPCHK(hipStreamCreateWithFlags(&B->lane.stream, hipStreamNonBlocking));
+        Carver cv;
+        B->o_insts = cv.take(sizeof(DevInst) * max_slots);
+        B->o_ctrl = cv.take(sizeof(Ctrl) * max_slots);
+        B->o_offs = cv.take(sizeof(int) * 2 * (size_t)(max_slots + 1));
+        B->o_scr = cv.take(sizeof(double) * (size_t)SCRATCH_BLK * max_slots);
+        B->o_gate = cv.take(sizeof(int) * max_slots);
+        if (hipMalloc(&B->meta, cv.off) != hipSuccess || hipMalloc(&B->arena, arena_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(PINS_ENOMEM, "live batch allocation failed");
+        }
+        B->arena_bytes = arena_bytes;
+        B->freel[0] = arena_bytes;
+        B->slots.resize(max_slots);
+        B->hI.resize(max_slots);
+        std::memset(B->hI.data(), 0, sizeof(DevInst) * max_slots);
+        LaunchCtx& L = B->L;
+        std::memset(&L, 0, sizeof(L));
+        L.stream = B->lane.stream;
+        L.insts = (const DevInst*)(B->meta + B->o_insts);
+        L.insts_mut = (DevInst*)(B->meta + B->o_insts);
+        L.ctrl = (Ctrl*)(B->meta + B->o_ctrl);
+        KP& kp = L.kp;
+        kp.eta = p.eta;
+        kp.inv_eta = 1.0 / p.eta;
+        kp.warm_tol = p.warm_tol;
+        kp.inner_tol = p.inner_tol;
+        kp.final_tol = p.final_tol;
+        kp.K = p.max_outer;
+        kp.cg_rtol = p.cg_rtol;
+        kp.ls_beta = p.ls_beta;
+        kp.ls_c1 = p.ls_c1;
+        kp.log_rho = std::log(p.rho);
+        kp.budget = p.budget;
+        kp.T1 = p.max_sinkhorn;
+        kp.T2 = p.max_newton;
+        kp.cg_max = p.cg_max_iter;
+        kp.ls_max = p.ls_max;
+        kp.nlev = p.rho_levels;
+        kp.shift_mode = PINS_SHIFT_IMPLICIT;
+        B->R.reset(new OuterRunner{&B->lane, B->lane.stream, B->L, L.ctrl, 0, B->p, SRC_DENSE, SRC_DENSE});
+        // the control blocks of unused slots: phase DONE, no outer iteration left
+        launch_zero(B->lane.stream, L.ctrl, sizeof(Ctrl) * max_slots);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(B->lane.stream));
+        return B.release();
+    } catch (const Fail& f) {
+        if (err) *err = f.msg;
+    } catch (const HipError& e) {
+        (void)hipGetLastError();
+        if (err) *err = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
+    } catch (...) {
+        if (err) *err = "live batch creation failed";
+    }
+    return nullptr;
+}
+
+void live_destroy(LiveBatch* B) { delete B; }
+
+int live_count(const LiveBatch* B) { return B ? B->nlive : 0; }
+
+bool live_grid(const LiveBatch* B) { return B && B->grid; }
+
+size_t live_bytes(const LiveBatch* B, const pins_problem& prob) {
+    try {
+        check_problem_shape(prob);
+        return plan_bytes(prob, B->p, nullptr);
+    } catch (...) {
+        return 0;
+    }
+}
+
+bool live_admit(LiveBatch* B, int64_t id, const pins_problem& prob, double* alpha_out, double* beta_out) {
+    if (!B || !alpha_out || !beta_out) return false;
+    const bool g = prob.kind == PINS_COST_GRID;
+    if (B->nlive > 0 && g != B->grid) return false;
+    int q = -1;
+    for (int k = 0; k < B->max_slots; ++k)
+        if (!B->slots[k].live) {
+            q = k;
+            break;
+        }
+    if (q < 0) return false;
+    try {
+        check_problem_shape(prob);
+        InstPlan plan;
+        const size_t need = plan_bytes(prob, B->p, &plan);
+        size_t off = 0;
+        if (!arena_take(B, need, &off)) return false;
+        HIPCHK(hipSetDevice(B->device));
+        pins_result r;
+        std::memset(&r, 0, sizeof(r));
+        B->hI[q] = build_inst(plan, prob, B->arena + off, true, false, r, B->lane.stream);
+        LiveSlot& Sl = B->slots[q];
+        Sl.live = true;
+        Sl.fresh = true;
+        Sl.id = id;
+        Sl.off = off;
+        Sl.bytes = need;
+        Sl.plan = plan;
+        Sl.prob = prob;
+        Sl.prob.C = Sl.prob.x = Sl.prob.y = Sl.prob.a = Sl.prob.b = nullptr;
+        Sl.k_done = 0;
+        Sl.alpha_out = alpha_out;
+        Sl.beta_out = beta_out;
+        // the input copies out of the caller's host arrays complete before admission returns
+        HIPCHK(hipStreamSynchronize(B->lane.stream));
+        if (B->nlive == 0) {
+            B->grid = g;
+            B->src = g ? SRC_GRID : SRC_DENSE;
+            B->base_src = B->src;
+            B->R->src = B->src;
+            B->R->base_src = B->base_src;
+        }
+        B->nlive += 1;
+        B->dirty = true;
+        return true;
+    } catch (...) {
+        (void)hipGetLastError();
+        return false;
+    }
+}
+
+int live_round(LiveBatch* B, std::vector<LiveDone>& done, std::string* err) {
+    try {
+        return live_round_impl(B, done);
+    } catch (const Fail& f) {
+        if (err) *err = f.msg;
+        for (int q = 0; q < B->max_slots; ++q)
+            if (B->slots[q].live) {
+                LiveDone d;
+                d.id = B->slots[q].id;
+                d.rc = f.code;
+                std::memset(&d.res, 0, sizeof(d.res));
+                d.res.status = f.code;
+                done.push_back(d);
+                live_kill(B, q);
+            }
+        return f.code;
+    } catch (const HipError& e) {
+        (void)hipGetLastError();
+        if (err) *err = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
+        for (int q = 0; q < B->max_slots; ++q)
+            if (B->slots[q].live) {
+                LiveDone d;
+                d.id = B->slots[q].id;
+                d.rc = PINS_EDEVICE;
+                std::memset(&d.res, 0, sizeof(d.res));
+                d.res.status = PINS_EDEVICE;
+                done.push_back(d);
+                live_kill(B, q);
+            }
+        return PINS_EDEVICE;
+    }
+}
+
+}  // namespace pins
+
 extern "C" {
 
 int pins_abi_version(void) { return PINS_ABI_VERSION; }
@@ -1063,39 +1552,70 @@ int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count,
 }
 
 int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, const pins_params* p,
-                           int max_lanes, int reps, pins_result* res, void* stream, int32_t* best, double* ms) {
+                           int max_lanes, int reps, pins_result* res, void* stream, pins_params* best,
+                           pins_tune_trial* trials, int max_trials, int32_t* ntrials) {
     return guarded(ctx, [&] {
         if (!probs || !p || !res || !best) fail(PINS_EINVAL, "null argument");
         if (max_lanes < 1 || max_lanes > 4) fail(PINS_EINVAL, "max_lanes must be in [1, 4]");
         if (reps < 1) fail(PINS_EINVAL, "reps must be >= 1");
-        using clk = std::chrono::steady_clock;
         if (count < 1) fail(PINS_EINVAL, "count must be >= 1");
-        pins_params q = *p;
-        int rc = PINS_OK, best_g = 1;
-        double best_ms = 0.0;
-        // a batch runs on at most `count` lanes: larger counts are not tried
-        const int gmax = std::min(max_lanes, count);
-        if (ms)
-            for (int g = gmax; g < max_lanes; ++g) ms[g] = 0.0;
-        for (int g = 1; g <= gmax; ++g) {
-            q.streams = g;
+        check_params(*p);
+        using clk = std::chrono::steady_clock;
+        int rc = PINS_OK, nt = 0;
+        pins_params cur = *p, top = *p;
+        double top_ms = -1.0;
+        // one configuration: an untimed solve, then the fastest of `reps` timed ones
+        auto trial = [&](const pins_params& q) {
             rc = solve_entry(ctx, probs, count, q, res, (hipStream_t)stream, false);
-            if (rc < 0) return rc;
+            if (rc < 0) return;
             double t = 0.0;
             for (int r = 0; r < reps; ++r) {
                 const auto t0 = clk::now();
                 rc = solve_entry(ctx, probs, count, q, res, (hipStream_t)stream, false);
-                if (rc < 0) return rc;
+                if (rc < 0) return;
                 const double e = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
                 t = (r == 0) ? e : std::min(t, e);
             }
-            if (ms) ms[g - 1] = t;
-            if (g == 1 || t < best_ms) {
-                best_ms = t;
-                best_g = g;
+            if (trials && nt < max_trials) {
+                pins_tune_trial& T = trials[nt];
+                T.streams = q.streams;
+                T.graphs = q.graphs;
+                for (int c = 0; c < 4; ++c) T.tile_rows[c] = q.tile_rows[c];
+                T.ms = t;
+            }
+            ++nt;
+            if (top_ms < 0.0 || t < top_ms) {
+                top_ms = t;
+                top = q;
+            }
+        };
+        // lanes (a batch runs on at most `count` lanes), graphs off, 16-row tiles
+        cur.graphs = 0;
+        for (int c = 0; c < 4; ++c) cur.tile_rows[c] = 0;
+        for (int g = 1; g <= std::min(max_lanes, count); ++g) {
+            cur.streams = g;
+            trial(cur);
+            if (rc < 0) return rc;
+        }
+        // graph replay at the best lane count
+        cur = top;
+        cur.graphs = 1;
+        trial(cur);
+        if (rc < 0) return rc;
+        // rows per tile, per size class present in the batch
+        bool present[4] = {false, false, false, false};
+        for (int q = 0; q < count; ++q) present[size_class(probs[q].m)] = true;
+        for (int c = 0; c < 4; ++c) {
+            if (!present[c]) continue;
+            for (int rows : {4, 8}) {
+                cur = top;
+                cur.tile_rows[c] = rows;
+                trial(cur);
+                if (rc < 0) return rc;
             }
         }
-        *best = best_g;
+        *best = top;
+        if (ntrials) *ntrials = nt;
         return rc;
     });
 }

@@ -1983,6 +1983,10 @@ __global__ __launch_bounds__(1024) void k_update(const DevInst* __restrict__ ins
 __global__ __launch_bounds__(1024) void k_shift_vec(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
                                                     int materialised, int start_phase) {
     const int b = blockIdx.x;
+    // only instances that finished an outer iteration and have another to run
+    // (in a batch solved together that is every instance; in a live batch the
+    // ones admitted this round have just been set up and are warming up)
+    if (ctrl[b].phase != PH_DONE || ctrl[b].k_out + 1 >= ctrl[b].K_out) return;
     const DevInst& I = insts[b];
     const int m = I.m, N = I.m + I.n;
     for (int k = threadIdx.x; k < N; k += 1024) {
@@ -2188,8 +2192,9 @@ __global__ void k_set_scale(DevInst* insts, Ctrl* ctrl, int count, int exponent_
 // marginals.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_potentials(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
-                                                     double K) {
+                                                     double K, const int* __restrict__ gate) {
     const int b = blockIdx.x;
+    if (gate && !gate[b]) return;  // live batch: only the instances finishing now
     const DevInst& I = insts[b];
     const int m = I.m, N = I.m + I.n;
     const bool mat = kp.shift_mode != 0;
@@ -2227,9 +2232,10 @@ __global__ __launch_bounds__(1024) void k_potentials(const DevInst* __restrict__
 
 template <class Src>
 __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp,
-                                               double K, int write_x) {
+                                               double K, int write_x, const int* __restrict__ gate) {
     const BlkRef br = blk_ref(kp.toff, kp.count);
     const int b = br.b, tl = br.l;
+    if (gate && !gate[b]) return;
     const DevInst& I = insts[b];
     const int rb = tl / I.ncb, cb = tl - rb * I.ncb;
     const int m = I.m, n = I.n;
@@ -2278,8 +2284,10 @@ __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts
     }
 }
 
-__global__ __launch_bounds__(256) void k_final_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
+__global__ __launch_bounds__(256) void k_final_merge(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl,
+                                                     const int* __restrict__ gate) {
     const int b = blockIdx.y;
+    if (gate && !gate[b]) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
     const int nb = (N + 255) / 256;
@@ -2574,13 +2582,15 @@ int noalloc_scratch(int device, void** out) {
     return PINS_OK;
 }
 
-void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x) {
-    hipLaunchKernelGGL(k_potentials, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, K);
+void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x, const int* gate) {
+    hipLaunchKernelGGL(k_potentials, dim3(L.count), dim3(1024), 0, L.stream, L.insts, L.ctrl, L.kp, K, gate);
     const dim3 g(L.total_tiles);
-#define K_(S) hipLaunchKernelGGL((k_final<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, K, write_x ? 1 : 0)
+#define K_(S) \
+    hipLaunchKernelGGL((k_final<S>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp, K, write_x ? 1 : 0, gate)
     PINS_SRC_DISPATCH(base_src, K_);
 #undef K_
-    hipLaunchKernelGGL(k_final_merge, g2((L.max_mn + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl);
+    hipLaunchKernelGGL(k_final_merge, g2((L.max_mn + 255) / 256, L.count), dim3(256), 0, L.stream, L.insts, L.ctrl,
+                       gate);
 }
 
 }  // namespace pins

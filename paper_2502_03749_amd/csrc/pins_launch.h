@@ -48,7 +48,8 @@ void launch_shift(const LaunchCtx& L, int base_src);
 void launch_init(const LaunchCtx& L, int base_src);
 void launch_points_cost(hipStream_t st, const double* x, const double* y, int m, int n, int d, double* C);
 void launch_cost_max(const LaunchCtx& L, double* scratch, int nblk, int exponent_uses_base);
-void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x);
+// outputs of every instance (gate = nullptr) or of those with gate[b] != 0 (device array)
+void launch_final(const LaunchCtx& L, int base_src, double K, bool write_x, const int* gate = nullptr);
 void launch_zero(hipStream_t st, void* p, size_t bytes);  // bytes: a multiple of 8
 // device address of the fixed scratch of pins_solve_device_noalloc on `device`
 // (PINS_NOALLOC_SCRATCH_BYTES bytes); PINS_OK or PINS_EDEVICE

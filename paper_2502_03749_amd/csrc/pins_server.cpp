@@ -1,12 +1,13 @@
 // pins_server.cpp -- serving runtime: continuous admission of solve requests
-// onto concurrent batched solves (one worker thread, context and HIP stream
-// each).  A worker that becomes free takes every queued request it can (in
-// arrival order, same cost-kind family, at most max_batch, workspace within the
-// HBM budget, at least one) and solves them in one pins_solve_batch_device
-// call; requests that arrive while other batches are on the GPU are admitted
-// as workers free up, and the batches of different workers overlap on the
-// device.  Each instance's arithmetic does not depend on its batch, so a result
-// is bitwise the one its problem gets alone.
+// into running batches.  Each worker thread owns a live batch (pins_live.h) on
+// its own HIP stream and device arena.  Between two outer iterations of its
+// batch a worker admits queued requests (arrival order, the batch's cost
+// family, while a slot and arena room are free); each request runs its own
+// K outer iterations and leaves the batch when they are done, so requests that
+// arrive while others are on the GPU join them at the next outer-iteration
+// boundary, and the batches of different workers overlap on the device.  Each
+// instance's arithmetic does not depend on the batch it shares, so a result is
+// bitwise the one its problem gets alone.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -23,6 +24,7 @@
 #include <vector>
 
 #include "pins.h"
+#include "pins_live.h"
 
 namespace {
 
@@ -76,137 +78,80 @@ struct pins_server {
 
 namespace {
 
-// Device staging of one batch: inputs and outputs of every request, carved
-// from one allocation that grows as needed.
-struct Staging {
-    void* base = nullptr;
-    size_t bytes = 0;
-    ~Staging() {
-        if (base) (void)hipFree(base);
-    }
-    bool reserve(size_t need) {
-        if (need <= bytes) return true;
-        if (base) (void)hipFree(base);
-        base = nullptr;
-        bytes = 0;
-        if (hipMalloc(&base, need) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        bytes = need;
-        return true;
-    }
-};
+// Default device arena of a worker's live batch when hbm_budget is 0.
+constexpr size_t DEFAULT_ARENA = (size_t)4 << 30;
 
-size_t doubles_of(const pins_problem& p) {
-    size_t c = (size_t)2 * (p.m + p.n);  // a, b, alpha, beta
-    if (p.kind == PINS_COST_DENSE) c += (size_t)p.m * p.n;
-    if (p.kind == PINS_COST_POINTS) c += (size_t)(p.m + p.n) * p.d;
-    return c;
+void complete(pins_server* S, Request* r, int rc, const pins_result* res) {
+    // caller holds S->mu
+    if (res) r->res = *res;
+    else std::memset(&r->res, 0, sizeof(r->res));
+    r->res.status = rc;
+    r->res.alpha = r->alpha.data();
+    r->res.beta = r->beta.data();
+    r->res.X = nullptr;
+    r->rc = rc;
+    r->done = true;
+    r->t_done = Clock::now();
 }
 
+// One worker: a live batch on its own stream.  Between two rounds (outer
+// iterations of the batch) it admits queued requests -- arrival order, the
+// batch's cost family, while a slot and arena room are free (a request that
+// cannot fit even into an empty batch is completed with PINS_ENOMEM) -- then
+// runs one round and completes the requests whose K outer iterations are done.
 void worker_loop(pins_server* S) {
-    if (hipSetDevice(S->device) != hipSuccess) return;
-    pins_ctx* ctx = nullptr;
-    const int crc = pins_create(S->device, &ctx);
-    hipStream_t st = nullptr;
-    // non-blocking: no implicit synchronisation with other workers' work through the null stream
-    const bool ok = crc == PINS_OK && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
-    Staging stage;
-    pins_params p = S->params;
-    p.streams = 0;  // this worker is one lane
+    if (hipSetDevice(S->device) != hipSuccess) (void)hipGetLastError();
+    std::string err;
+    pins::LiveBatch* B = pins::live_create(S->device, S->params, S->max_batch,
+                                           S->budget > 0 ? S->budget : DEFAULT_ARENA, &err);
+    if (!B) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->err = err.empty() ? "worker set-up failed" : err;
+    }
+    std::vector<pins::LiveDone> done;
     for (;;) {
-        std::vector<Request*> batch;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
-            if (S->queue.empty()) break;  // stopping and nothing left
-            // admission: arrival order, one cost-kind family, at most max_batch,
-            // workspace within the budget (the first request is always taken)
-            const bool fam = grid_family(S->reqs[S->queue.front()]->prob);
-            std::vector<pins_problem> probs;
-            for (auto it = S->queue.begin(); it != S->queue.end() && (int)batch.size() < S->max_batch;) {
+            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || pins::live_count(B) > 0; });
+            if (S->queue.empty() && pins::live_count(B) == 0) break;  // stopping and nothing left
+            for (auto it = S->queue.begin(); it != S->queue.end();) {
                 Request* r = S->reqs[*it].get();
-                if (grid_family(r->prob) != fam) {
+                if (!B) {  // no live batch on this worker: its requests fail
+                    complete(S, r, PINS_EDEVICE, nullptr);
+                    it = S->queue.erase(it);
+                    continue;
+                }
+                if (pins::live_count(B) > 0 && grid_family(r->prob) != pins::live_grid(B)) {
                     ++it;
                     continue;
                 }
-                probs.push_back(r->prob);
-                size_t ws = 0;
-                if (!batch.empty() && S->budget > 0 &&
-                    (pins_workspace_bytes(probs.data(), (int)probs.size(), &p, &ws) != PINS_OK || ws > S->budget)) {
-                    probs.pop_back();
-                    break;
+                if (pins::live_admit(B, *it, r->prob, r->alpha.data(), r->beta.data())) {
+                    it = S->queue.erase(it);
+                    continue;
                 }
-                batch.push_back(r);
-                it = S->queue.erase(it);
+                if (pins::live_count(B) == 0) {  // does not fit into an empty batch
+                    complete(S, r, PINS_ENOMEM, nullptr);
+                    it = S->queue.erase(it);
+                    continue;
+                }
+                break;  // no room now: later requests wait their turn
             }
         }
-        const int cnt = (int)batch.size();
-        int rc = ok ? PINS_OK : PINS_EDEVICE;
-        std::vector<pins_problem> dp(cnt);
-        std::vector<pins_result> dr(cnt);
-        if (rc == PINS_OK) {
-            size_t need = 0;
-            for (Request* r : batch) need += doubles_of(r->prob) * sizeof(double) + 256;
-            if (!stage.reserve(need)) rc = PINS_ENOMEM;
-        }
-        if (rc == PINS_OK) {
-            char* at = (char*)stage.base;
-            auto put = [&](const std::vector<double>& v) {
-                double* d = (double*)at;
-                if (!v.empty() && hipMemcpyAsync(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice,
-                                                 st) != hipSuccess)
-                    rc = PINS_EDEVICE;
-                at += v.size() * sizeof(double);
-                return d;
-            };
-            for (int q = 0; q < cnt; ++q) {
-                Request* r = batch[q];
-                dp[q] = r->prob;
-                dp[q].a = put(r->a);
-                dp[q].b = put(r->b);
-                dp[q].C = r->C.empty() ? nullptr : put(r->C);
-                dp[q].x = r->x.empty() ? nullptr : put(r->x);
-                dp[q].y = r->y.empty() ? nullptr : put(r->y);
-                std::memset(&dr[q], 0, sizeof(pins_result));
-                dr[q].alpha = (double*)at;
-                at += (size_t)r->prob.m * sizeof(double);
-                dr[q].beta = (double*)at;
-                at += (size_t)r->prob.n * sizeof(double);
-                at = (char*)(((uintptr_t)at + 255) & ~(uintptr_t)255);
-            }
-        }
-        if (rc == PINS_OK) rc = pins_solve_batch_device(ctx, dp.data(), cnt, &p, dr.data(), st);
-        std::string msg = (rc < 0 && ctx) ? pins_last_error(ctx) : "";
-        for (int q = 0; q < cnt && rc >= 0; ++q) {
-            Request* r = batch[q];
-            if (hipMemcpyAsync(r->alpha.data(), dr[q].alpha, r->alpha.size() * sizeof(double), hipMemcpyDeviceToHost,
-                               st) != hipSuccess ||
-                hipMemcpyAsync(r->beta.data(), dr[q].beta, r->beta.size() * sizeof(double), hipMemcpyDeviceToHost,
-                               st) != hipSuccess)
-                rc = PINS_EDEVICE;
-        }
-        if (rc >= 0 && hipStreamSynchronize(st) != hipSuccess) rc = PINS_EDEVICE;
+        S->cv_done.notify_all();
+        if (!B) continue;
+        done.clear();
+        const int rc = pins::live_round(B, done, &err);
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            const auto now = Clock::now();
-            for (int q = 0; q < cnt; ++q) {
-                Request* r = batch[q];
-                r->res = dr[q];
-                r->res.alpha = r->alpha.data();
-                r->res.beta = r->beta.data();
-                r->res.X = nullptr;
-                r->rc = rc < 0 ? rc : dr[q].status;
-                r->done = true;
-                r->t_done = now;
+            for (const pins::LiveDone& d : done) {
+                auto f = S->reqs.find(d.id);
+                if (f != S->reqs.end()) complete(S, f->second.get(), d.rc, &d.res);
             }
-            if (rc < 0) S->err = msg.empty() ? "device error in a served batch" : msg;
+            if (rc < 0) S->err = err.empty() ? "device error in a live batch" : err;
         }
         S->cv_done.notify_all();
     }
-    if (st) (void)hipStreamDestroy(st);
-    if (ctx) pins_destroy(ctx);
+    pins::live_destroy(B);
 }
 
 }  // namespace
@@ -216,6 +161,7 @@ extern "C" {
 int pins_server_create(int device, int workers, int max_batch, size_t hbm_budget, const pins_params* p,
                        pins_server** out) {
     if (!out || !p || workers < 1 || workers > 4 || max_batch < 1) return PINS_EINVAL;
+    if (p->shift_mode != PINS_SHIFT_IMPLICIT || p->hvp == 2) return PINS_EUNSUPPORTED;
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
@@ -264,6 +210,12 @@ int pins_server_submit(pins_server* S, const pins_problem* prob, int64_t* ticket
         r->x.assign(prob->x, prob->x + (size_t)prob->m * prob->d);
         r->y.assign(prob->y, prob->y + (size_t)prob->n * prob->d);
     }
+    // the request's problem points at its own copies (read at admission)
+    r->prob.a = r->a.data();
+    r->prob.b = r->b.data();
+    r->prob.C = r->C.empty() ? nullptr : r->C.data();
+    r->prob.x = r->x.empty() ? nullptr : r->x.data();
+    r->prob.y = r->y.empty() ? nullptr : r->y.data();
     r->alpha.assign(prob->m, 0.0);
     r->beta.assign(prob->n, 0.0);
     r->t_submit = Clock::now();

@@ -102,9 +102,10 @@ def test_entry_points_reject_a_null_context():
     assert L.pins_solve_device(None, None, ctypes.byref(prm), None, None) == B.PINS_EINVAL
     assert L.pins_solve_batch_device(None, None, 1, ctypes.byref(prm), None, None) == B.PINS_EINVAL
     assert L.pins_solve_resume(None, None, ctypes.byref(prm), None, 0, None, None) == B.PINS_EINVAL
-    best = ctypes.c_int32(0)
+    best = B.Params()
     assert L.pins_tune_batch_device(None, None, 1, ctypes.byref(prm), 4, 1, None, None, ctypes.byref(best),
-                                    None) == B.PINS_EINVAL
+                                    None, 0, None) == B.PINS_EINVAL
+    assert L.pins_solve_device_noalloc(None, None, ctypes.byref(prm), None, None) == B.PINS_EINVAL
 
 
 def test_exp_probe_argument_checks():

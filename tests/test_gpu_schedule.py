@@ -42,37 +42,73 @@ def _host(outs):
     return [(o["alpha"].cpu().numpy().copy(), o["beta"].cpu().numpy().copy()) for o in outs]
 
 
-def test_tuner_picks_a_lane_count_and_keeps_results(ctx):
+def test_tuner_picks_a_schedule_and_tiles_and_keeps_results(ctx):
+    """The tuner tries lanes 1..4, graph replay and 4 / 8 rows per tile for each
+    size class present; the lane count and the graphs leave every result bitwise
+    unchanged, and a solve with the chosen parameters reproduces the tuner's
+    last outputs exactly (results depend on the tile rows only through each
+    instance's own size class)."""
     print("case tuner 8 uneven dense instances", flush=True)
     probs, outs = _batch()
     prm = P.params(eta=0.03, max_outer=6)
-    st = torch.cuda.current_stream().cuda_stream
-    rc, ref = ctx.solve_batch_device(probs, P.params(eta=0.03, max_outer=6, streams=1), outs, stream=st)
-    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    rc, ref = ctx.solve_batch_device(probs, P.params(eta=0.03, max_outer=6, streams=1), outs, stream=st.cuda_stream)
+    st.synchronize()
     assert rc == 0
     want = _host(outs)
-    best, ms = ctx.tune_batch_device(probs, prm, outs, max_lanes=4, reps=1, stream=st)
-    torch.cuda.synchronize()
-    assert 1 <= best <= 4 and len(ms) == 4
-    assert all(v > 0 for v in ms) and ms[best - 1] == min(ms)
-    for (a1, b1), (a2, b2) in zip(want, _host(outs)):
-        assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
-    # the chosen count gives the same results as one lane
-    rc, got = ctx.solve_batch_device(probs, P.params(eta=0.03, max_outer=6, streams=best), outs, stream=st)
-    torch.cuda.synchronize()
+    best, trials = ctx.tune_batch_device(probs, prm, outs, max_lanes=4, reps=1, stream=st.cuda_stream)
+    st.synchronize()
+    assert 1 <= best.streams <= 4 and best.graphs in (0, 1)
+    # the batch's m span three size classes: 4 lane counts, graphs, 2 tile choices per class
+    classes = {0 if p["m"] < 64 else 1 if p["m"] < 256 else 2 for p in probs}
+    assert len(trials) == 4 + 1 + 2 * len(classes)
+    assert all(t["ms"] > 0 for t in trials)
+    chosen = [t for t in trials if t["streams"] == best.streams and t["graphs"] == best.graphs and
+              t["tile_rows"] == list(best.tile_rows)]
+    assert chosen and chosen[0]["ms"] == min(t["ms"] for t in trials)
+    # lanes and graphs alone: bitwise the one-lane results
+    for t in trials[:5]:
+        o2 = [dict(alpha=torch.empty_like(o["alpha"]), beta=torch.empty_like(o["beta"])) for o in outs]
+        rc, got = ctx.solve_batch_device(probs, P.params(eta=0.03, max_outer=6, streams=t["streams"],
+                                                         graphs=t["graphs"]), o2, stream=st.cuda_stream)
+        st.synchronize()
+        for (a1, b1), (a2, b2) in zip(want, _host(o2)):
+            assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+    # the chosen configuration reproduces itself, and each instance alone equals its batched result
+    o3 = [dict(alpha=torch.empty_like(o["alpha"]), beta=torch.empty_like(o["beta"])) for o in outs]
+    rc, got = ctx.solve_batch_device(probs, best, o3, stream=st.cuda_stream)
+    st.synchronize()
     assert rc == 0
-    for (a1, b1), (a2, b2) in zip(want, _host(outs)):
-        assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
-    for r1, r2 in zip(ref, got):
-        assert r1["cost"] == r2["cost"] and r1["resid"] == r2["resid"]
+    alone = P.params(eta=0.03, max_outer=6, tile_rows=list(best.tile_rows))
+    for q in range(len(probs)):
+        o1 = dict(alpha=torch.empty_like(outs[q]["alpha"]), beta=torch.empty_like(outs[q]["beta"]))
+        _, r1 = ctx.solve_device(probs[q], alone, o1, stream=st.cuda_stream)
+        st.synchronize()
+        assert torch.equal(o1["alpha"], o3[q]["alpha"]) and r1["cost"] == got[q]["cost"], q
+
+
+@pytest.mark.parametrize("rows", [1, 3, 8])
+def test_tile_rows_parity(ctx, rows):
+    """Dense passes with 1, 3 and 8 rows per tile (every size class): parity
+    with the oracle at the FP64 bar."""
+    import oracle
+    from test_gpu_parity import check_parity, gpu_solve
+
+    print("case tile rows %d" % rows, flush=True)
+    C, a, b = _rand(150, 97, 31337)
+    prm = P.params(eta=0.03, max_outer=8, tile_rows=[rows] * 4)
+    g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), prm)
+    g["_C"] = C
+    o = oracle.pins(C, a, b, eta=0.03, K=8)
+    check_parity(g, o, a, b)
 
 
 def test_tuner_tries_no_more_lanes_than_instances(ctx):
     print("case tuner 2 instances", flush=True)
     probs, outs = _batch()
-    best, ms = ctx.tune_batch_device(probs[:2], P.params(eta=0.03, max_outer=2), outs[:2], max_lanes=4, reps=1)
+    best, trials = ctx.tune_batch_device(probs[:2], P.params(eta=0.03, max_outer=2), outs[:2], max_lanes=4, reps=1)
     torch.cuda.synchronize()
-    assert best in (1, 2) and ms[0] > 0 and ms[1] > 0 and ms[2] == 0.0 and ms[3] == 0.0
+    assert best.streams in (1, 2) and max(t["streams"] for t in trials) == 2
 
 
 def test_tuner_rejects_bad_arguments(ctx):
@@ -83,6 +119,9 @@ def test_tuner_rejects_bad_arguments(ctx):
         with pytest.raises(P.PinsError) as e:
             ctx.tune_batch_device(probs[:2], prm, outs[:2], **kw)
         assert e.value.code == P._binding.PINS_EINVAL
+    with pytest.raises(P.PinsError) as e:
+        ctx.solve_batch_device(probs[:2], P.params(eta=0.03, max_outer=2, tile_rows=[17, 0, 0, 0]), outs[:2])
+    assert e.value.code == P._binding.PINS_EINVAL
 
 
 def test_exp_probe_rate_is_plausible():

@@ -1,6 +1,7 @@
-"""Serving (pins_server_*): requests from several host threads, admitted as
-workers free up onto concurrent batches.  Each result must be bitwise the one
-its problem gets alone, and match the oracle."""
+"""Serving (pins_server_*): continuous batching.  Requests from several host
+threads join a worker's running batch at its next outer-iteration boundary
+and leave it when their own K outer iterations are done.  Each result must be
+bitwise the one its problem gets alone, and match the oracle."""
 import threading
 import time
 
@@ -74,3 +75,94 @@ def test_server_rejects_invalid_requests():
         assert srv.wait(ok)["rc"] in (0, 1)
     finally:
         srv.close()
+
+
+def _alone(prm, reqs):
+    ctx = P.Context(0)
+    try:
+        return [ctx.solve(P.COST_GRID, a, b, prm, grid_s=s) for s, a, b in reqs]
+    finally:
+        ctx.close()
+
+
+def test_requests_join_a_running_batch():
+    """One worker, the same K for every request: a first request is running when
+    three more arrive 10 ms later.  Admitted only between whole batches they
+    would wait for the first to finish and then take as long again (latency
+    about twice the first's); joining its batch at the next outer-iteration
+    boundary they finish within about one solve time of arriving.  Every result
+    is bitwise the one its problem gets alone."""
+    print("case serving join", flush=True)
+    eta, K = 0.1, 150
+    prm = P.params(eta=eta, max_outer=K)
+    reqs = [(20,) + tuple(W.blob_pair(300 + i, s=20).values())[:2] for i in range(4)]
+    srv = P.Server(prm, workers=1, max_batch=8)
+    # warm the worker (code load, first allocations) so that timings are the solves'
+    srv.wait(srv.submit(P.COST_GRID, reqs[0][1], reqs[0][2], grid_s=20))
+    t0 = time.perf_counter()
+    first = srv.submit(P.COST_GRID, reqs[0][1], reqs[0][2], grid_s=20)
+    time.sleep(0.01)
+    later = [srv.submit(P.COST_GRID, a, b, grid_s=s) for s, a, b in reqs[1:]]
+    t_sub = time.perf_counter()
+    out = [srv.wait(first)] + [srv.wait(t) for t in later]
+    srv.close()
+    lat0 = out[0]["latency_ms"]
+    assert (t_sub - t0) * 1e3 < lat0, (t_sub - t0, lat0)  # they arrived while the first was running
+    for o in out[1:]:
+        assert o["latency_ms"] < 1.5 * lat0, (o["latency_ms"], lat0)
+    for o, al in zip(out, _alone(prm, reqs)):
+        assert o["rc"] == 0 and al["cost"] == o["cost"]
+        assert np.array_equal(al["alpha"], o["alpha"]) and np.array_equal(al["beta"], o["beta"])
+
+
+def test_hbm_budget_limits_the_batch():
+    """An arena that holds two 16x16 requests at a time: the others wait for room
+    (no request fails), each result bitwise the one it gets alone; a request that
+    cannot fit into the empty arena completes with PINS_ENOMEM."""
+    print("case serving hbm budget", flush=True)
+    eta, K = 0.1, 8
+    prm = P.params(eta=eta, max_outer=K)
+    one = P.workspace_bytes([dict(kind=P.COST_GRID, m=256, n=256, grid_s=16)], prm)
+    budget = int(2.6 * one)
+    reqs = [(16,) + tuple(W.blob_pair(400 + i, s=16).values())[:2] for i in range(6)]
+    srv = P.Server(prm, workers=1, max_batch=8, hbm_budget=budget)
+    tickets = [srv.submit(P.COST_GRID, a, b, grid_s=s) for s, a, b in reqs]
+    big = W.blob_pair(499, s=40)
+    tb = srv.submit(P.COST_GRID, big["a"], big["b"], grid_s=40)
+    out = [srv.wait(t) for t in tickets]
+    with pytest.raises(P.PinsError) as e:
+        srv.wait(tb)
+    assert e.value.code == -2
+    srv.close()
+    for o, al in zip(out, _alone(prm, reqs)):
+        assert o["rc"] == 0 and al["cost"] == o["cost"]
+        assert np.array_equal(al["alpha"], o["alpha"]) and np.array_equal(al["beta"], o["beta"])
+
+
+def test_dense_requests_with_a_non_finite_cost_are_rejected_at_submit():
+    """A dense request whose cost holds a NaN is refused at submit; the valid
+    requests around it are served and equal their solo solves."""
+    print("case serving nan cost", flush=True)
+    g = np.random.default_rng(5)
+    prm = P.params(eta=0.05, max_outer=4)
+    srv = P.Server(prm, workers=1, max_batch=4)
+    good = []
+    for q in range(3):
+        C = g.uniform(0, 1, (30, 20))
+        a, b = g.uniform(0.2, 1, 30), g.uniform(0.2, 1, 20)
+        good.append((C, a / a.sum(), b / b.sum()))
+    t = [srv.submit(P.COST_DENSE, a, b, C=C, cost_scale=1.0) for C, a, b in good[:2]]
+    Cn = good[2][0].copy()
+    Cn[3, 4] = np.nan
+    with pytest.raises(P.PinsError):
+        srv.submit(P.COST_DENSE, good[2][1], good[2][2], C=Cn, cost_scale=1.0)
+    t.append(srv.submit(P.COST_DENSE, good[2][1], good[2][2], C=good[2][0], cost_scale=1.0))
+    out = [srv.wait(x) for x in t]
+    srv.close()
+    ctx = P.Context(0)
+    try:
+        for o, (C, a, b) in zip(out, good):
+            al = ctx.solve(P.COST_DENSE, a, b, prm, C=C, cost_scale=1.0)
+            assert o["rc"] == 0 and al["cost"] == o["cost"] and np.array_equal(al["alpha"], o["alpha"])
+    finally:
+        ctx.close()
