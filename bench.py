@@ -124,6 +124,16 @@ def parse():
                          "Sinkhorn + EPPA with the same K (n = 50..400, eta = 1e-2) and the eta sweep at n = 400 "
                          "against Sinkhorn without EPPA (cap 50 000 iterations); about a minute")
     ap.add_argument("--paper-tables-only", action="store_true", help="only run --paper-tables")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other stated configurations (plane instance at K = 2000, nine 64x64 grid pairs, "
+                         "256 uneven point clouds at the calibrated K = 1200)")
+    ap.add_argument("--configs-only", action="store_true", help="only run the other stated configurations")
+    ap.add_argument("--c5", action="store_true",
+                    help="only run the served protocol: saturated capacity of the request mix, then Poisson "
+                         "arrivals at 0.3, 0.5, 0.9 (400 requests each) and 0.7 (2000 requests) of it, with "
+                         "accuracy against stored oracle outputs of sampled requests")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="only run the 256 uneven point clouds (K = 20), the batch whose cost the matrix cores form")
     ap.add_argument("--pcg-only", action="store_true",
                     help="only run the single-instance CG measurement (pair 0 alone, sparsified Hessian products "
                          "throughout, events around the one-block CG launches)")
@@ -184,6 +194,20 @@ def main():
         print(json.dumps(dict(served=served(P, W, args.served, args.rate))), flush=True)
         return
     ctx = P.Context(0)
+    if args.c5:
+        print(json.dumps(dict(served_protocol=c5_protocol(P, W, np))), flush=True)
+        ctx.close()
+        return
+    if args.uneven_only:
+        print(json.dumps(dict(batched_uneven_points=uneven_points(P, ctx, torch, np, dev, W,
+                                                                  torch.cuda.current_stream().cuda_stream))),
+              flush=True)
+        ctx.close()
+        return
+    if args.configs_only:
+        print(json.dumps(dict(configs=other_configs(P, W, torch, np, ctx, dev))), flush=True)
+        ctx.close()
+        return
     if args.pcg_only:
         print(json.dumps(dict(pcg_single_instance=pcg_single(P, ctx, torch, probs[0], outs[0],
                                                              torch.cuda.current_stream().cuda_stream, args, prec))),
@@ -357,6 +381,8 @@ def main():
         line["sinkhorn_sweep_streamed"] = streamed_sweep(P, ctx, torch, np, dev, W)
     if not args.no_served:
         line["served"] = served(P, W, 120, args.rate)
+    if not args.no_configs:
+        line["configs"] = other_configs(P, W, torch, np, ctx, dev)
 
     if args.paper_tables:
         line["paper_tables"] = paper_tables(P, W, torch, np)
@@ -366,12 +392,22 @@ def main():
 
         C = oracle.cost_grid(s)
         p0 = pairs[0]
-        t1 = time.perf_counter()
-        ref = oracle.pins(C, p0["a"], p0["b"], want_plan=False, eta=args.eta, K=args.K)
-        dt = time.perf_counter() - t1
-        line["cpu_baseline"] = dict(value=1.0 / dt, unit="solves/s", cores=1, kind="oracle",
-                                    sample="1 of the %d pairs (pair 0), full solve at the same K=%d, "
-                                           "single-threaded C oracle, %.1f s" % (args.pairs, args.K, dt))
+        one = []
+        ref = None
+        for _ in range(5):
+            t1 = time.perf_counter()
+            ref = oracle.pins(C, p0["a"], p0["b"], want_plan=False, eta=args.eta, K=args.K)
+            one.append(time.perf_counter() - t1)
+        dt = float(np.median(one))
+        allc = cpu_all_cores(pairs, args, np)
+        line["cpu_baseline"] = dict(value=allc["solves_per_s"], unit="solves/s", cores=allc["cores"], kind="oracle",
+                                    sample="pairs 0..%d of the %d, one full solve each at the same K=%d by %d "
+                                           "single-threaded C oracle processes at once; median of 5 runs"
+                                           % (allc["cores"] - 1, args.pairs, args.K, allc["cores"]),
+                                    cpu_model=allc["cpu_model"], nproc=allc["nproc"],
+                                    runs_s=allc["runs_s"],
+                                    single_thread=dict(value=1.0 / dt, unit="solves/s", cores=1,
+                                                       sample="pair 0, median of 5 runs", runs_s=[round(v, 2) for v in one]))
         g0 = last[0]
         line["accuracy"] = dict(rel_cost_diff_vs_oracle=abs(g0["cost"] - ref["cost"]) / ref["cost"],
                                 gpu_resid=g0["resid"], oracle_resid=ref["resid"], bar=1e-6)
@@ -399,6 +435,228 @@ def pcg_single(P, ctx, torch, prob, out, st, args, prec):
         res.update(us_per_iteration=round(1e3 * ms / it, 3), stored_entries_per_iteration=round(entries / it, 1),
                    bytes_per_entry=bpe, achieved_GBs_one_cu=round(gbs, 2), cu_l2_ceiling_GBs=CU_L2_GBS,
                    frac_of_cu_l2=round(gbs / CU_L2_GBS, 4))
+    return res
+
+
+def _oracle_solve(item):
+    """One single-threaded oracle solve of an image-histogram pair (a worker of cpu_all_cores)."""
+    import oracle
+
+    a, b, s, eta, K = item
+    t0 = time.perf_counter()
+    oracle.pins(oracle.cost_grid(s), a, b, want_plan=False, eta=eta, K=K)
+    return time.perf_counter() - t0
+
+
+def cpu_all_cores(pairs, args, np):
+    """The oracle on the host's cores: as many single-threaded processes as the
+    GPU's share of host cores (16, or fewer if the host has fewer), each solving
+    a different pair at the same K; solves per second over the wall time of one
+    run; median of 5 runs."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+
+    nproc = os.cpu_count() or 1
+    cores = max(1, min(16, nproc))
+    model = "unknown"
+    try:
+        for line_ in open("/proc/cpuinfo"):
+            if line_.startswith("model name"):
+                model = line_.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    items = [(pairs[q % len(pairs)]["a"], pairs[q % len(pairs)]["b"], args.side, args.eta, args.K)
+             for q in range(cores)]
+    runs = []
+    # fresh interpreters (spawned children), not forks of this GPU process
+    with ProcessPoolExecutor(max_workers=cores, mp_context=multiprocessing.get_context("spawn")) as ex:
+        list(ex.map(_oracle_solve, items[:cores]))  # warm the workers (oracle build, imports)
+        for _ in range(5):
+            t0 = time.perf_counter()
+            list(ex.map(_oracle_solve, items))
+            runs.append(time.perf_counter() - t0)
+    wall = float(np.median(runs))
+    return dict(solves_per_s=cores / wall, cores=cores, nproc=nproc, cpu_model=model,
+                runs_s=[round(v, 2) for v in runs])
+
+
+def _lp_optimum(C, a, b):
+    """The transport LP's optimal value by scipy's HiGHS (reference for the stated error bars)."""
+    import numpy as np
+    from scipy.optimize import linprog
+    from scipy.sparse import coo_matrix, vstack
+
+    m, n = C.shape
+    rows = coo_matrix((np.ones(m * n), (np.repeat(np.arange(m), n), np.arange(m * n))), shape=(m, m * n))
+    cols = coo_matrix((np.ones(m * n), (np.tile(np.arange(n), m), np.arange(m * n))), shape=(n, m * n))
+    res = linprog(C.ravel(), A_eq=vstack([rows, cols]).tocsr(), b_eq=np.concatenate([a, b]), bounds=(0, None),
+                  method="highs")
+    return float(res.fun)
+
+
+def other_configs(P, W, torch, np, ctx, dev):
+    """The other stated configurations, each timed on the GPU with inputs
+    resident:
+      plane  -- one 100x100 point-cloud instance in the plane, eta = 1e-2,
+                K = 2000 (the K at which the oracle reaches 1e-8 of the LP
+                optimum), FP64: time per solve on a non-default stream with and
+                without graph replay, error against scipy's HiGHS;
+      grids  -- nine 64x64 grid pairs (three of each histogram class), eta =
+                1e-3, K = 10, mixed precision, one batched call; accuracy of
+                pair 0 of each class against the stored oracle outputs
+                (tests/golden/c3_oracle.npz);
+      uneven -- the 256 uneven point clouds at K = 1200 (the K at which the six
+                smallest reach 1e-6 of the HiGHS optimum), mixed precision, one
+                batched call; error of the three smallest against HiGHS."""
+    t = lambda v: torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev)
+    out = {}
+    sst = torch.cuda.Stream()
+    # plane instance
+    inst = W.points_instance(0)
+    m = n = 100
+    prob = dict(kind=P.COST_POINTS, m=m, n=n, d=2, x=t(inst["x"]), y=t(inst["y"]), a=t(inst["a"]), b=t(inst["b"]))
+    o1 = dict(alpha=torch.empty(m, dtype=torch.float64, device=dev), beta=torch.empty(n, dtype=torch.float64, device=dev))
+    K = 2000
+    plane = dict(workload="100x100 points in [0,1]^2, squared Euclidean / max, eta = 1e-2, K = %d, FP64" % K)
+    for g in (0, 1):
+        prm = P.params(eta=1e-2, max_outer=K, graphs=g)
+        ctx.solve_device(prob, prm, o1, stream=sst.cuda_stream)
+        sst.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            rc, r = ctx.solve_device(prob, prm, o1, stream=sst.cuda_stream)
+            sst.synchronize()
+            ts.append(time.perf_counter() - t0)
+        plane["graphs" if g else "kernel_by_kernel"] = dict(ms_per_solve=round(1e3 * min(ts), 2),
+                                                            solves_per_s=1.0 / min(ts), status=rc)
+    xs, ys = inst["x"], inst["y"]
+    Cp = ((xs[:, None, :] - ys[None, :, :]) ** 2).sum(-1)
+    Cp = Cp / Cp.max()
+    ot = _lp_optimum(Cp, inst["a"], inst["b"])
+    plane["rel_error_vs_lp"] = abs(r["cost"] - ot) / ot
+    plane["newton_iters"] = r["newton_iters"]
+    out["plane"] = plane
+    # nine 64x64 grid pairs
+    s = 64
+    gp = [(cls, i, W.grid_pair(cls, i, s=s)) for cls in ("white", "gmm", "cauchy") for i in range(3)]
+    probs = [dict(kind=P.COST_GRID, m=s * s, n=s * s, grid_s=s, a=t(p["a"]), b=t(p["b"])) for _, _, p in gp]
+    outs = [dict(alpha=torch.empty(s * s, dtype=torch.float64, device=dev),
+                 beta=torch.empty(s * s, dtype=torch.float64, device=dev)) for _ in gp]
+    prm = P.params(eta=1e-3, max_outer=10, precision=P.MIXED)
+    st = torch.cuda.current_stream().cuda_stream
+    ctx.solve_batch_device(probs, prm, outs, stream=st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, rs = ctx.solve_batch_device(probs, prm, outs, stream=st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    acc = {}
+    fx = os.path.join(ROOT, "tests", "golden", "c3_oracle.npz")
+    if os.path.exists(fx):
+        f = np.load(fx)
+        for q, (cls, i, _) in enumerate(gp):
+            if i == 0:
+                acc[cls] = abs(rs[q]["cost"] - f[cls + "_scalars"][0]) / f[cls + "_scalars"][0]
+    out["grids"] = dict(workload="9 pairs of 64x64 grids (white noise, 5-component Gaussian mixtures, Cauchy bumps; "
+                                 "3 each), grid cost streamed, eta = 1e-3, K = 10, mixed precision, one batched call",
+                        solves_per_s=len(gp) / dt, ms=round(1e3 * dt, 1), statuses=sorted({r["status"] for r in rs}),
+                        max_resid=max(r["resid"] for r in rs), rel_cost_diff_vs_oracle_pair0=acc)
+    # 256 uneven point clouds at the calibrated K
+    insts = [W.batch_instance(i) for i in range(256)]
+    probs = [dict(kind=P.COST_POINTS, m=x["x"].shape[0], n=x["y"].shape[0], d=x["d"], x=t(x["x"]), y=t(x["y"]),
+                  a=t(x["a"]), b=t(x["b"])) for x in insts]
+    outs = [dict(alpha=torch.empty(p["m"], dtype=torch.float64, device=dev),
+                 beta=torch.empty(p["n"], dtype=torch.float64, device=dev)) for p in probs]
+    Kc = 1200
+    prm = P.params(eta=1e-2, max_outer=Kc, precision=P.MIXED)
+    print("bench: uneven point clouds at K = %d" % Kc, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    rc, rs = ctx.solve_batch_device(probs, prm, outs, stream=st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    small = sorted(range(256), key=lambda q: probs[q]["m"] * probs[q]["n"])[:3]
+    err = {}
+    for q in small:
+        xs, ys = insts[q]["x"], insts[q]["y"]
+        Cq = ((xs[:, None, :] - ys[None, :, :]) ** 2).sum(-1)
+        Cq = Cq / Cq.max()
+        otq = _lp_optimum(Cq, insts[q]["a"], insts[q]["b"])
+        err[str(q)] = abs(rs[q]["cost"] - otq) / otq
+    out["uneven"] = dict(workload="256 point clouds, m, n log-uniform in [64, 2048], d in {2, 8, 32}, Dirichlet(1) "
+                                  "marginals, eta = 1e-2, K = %d, mixed precision, one batched call (one lane)" % Kc,
+                         solves_per_s=256 / dt, ms=round(1e3 * dt, 1), statuses=sorted({r["status"] for r in rs}),
+                         max_resid=max(r["resid"] for r in rs), rel_error_vs_lp_smallest=err)
+    return out
+
+
+def c5_protocol(P, W, np, K=10, workers=3, max_batch=32):
+    """The served protocol: the request mix's saturated capacity (all of 300
+    requests submitted at once; completions per second), then Poisson arrivals
+    at 0.3, 0.5 and 0.9 of it (400 requests each) and at 0.7 of it (the 2000
+    requests of the stream); p50 / p99 latency and solves/s at each rate;
+    accuracy of the sampled requests that have stored oracle outputs
+    (tests/golden/c5_oracle.npz: six 32x32 and two 64x64 requests of the
+    stream) against them."""
+    import threading
+
+    prm = P.params(eta=1e-3, max_outer=K, precision=P.MIXED)
+
+    def run(reqs, rate, label):
+        srv = P.Server(prm, workers=workers, max_batch=max_batch)
+        tickets = [None] * len(reqs)
+        t0 = time.perf_counter()
+
+        def submitter():
+            for q, r in enumerate(reqs):
+                if rate:
+                    delay = r["t"] * (1.0 / rate) - (time.perf_counter() - t0)
+                    if delay > 0:
+                        time.sleep(delay)
+                tickets[q] = srv.submit(P.COST_GRID, r["a"], r["b"], grid_s=r["s"])
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        outs = []
+        for q, tk in enumerate(tickets):
+            outs.append(srv.wait(tk))
+            if (q + 1) % 200 == 0:
+                print("bench: served %s: %d of %d done" % (label, q + 1, len(reqs)), file=sys.stderr, flush=True)
+        t_end = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([o["latency_ms"] for o in outs])
+        span = t_end - (reqs[0]["t"] / rate if rate else 0.0)
+        return outs, dict(requests=len(reqs), solves_per_s=len(reqs) / span, p50_ms=float(np.percentile(lat, 50)),
+                          p99_ms=float(np.percentile(lat, 99)),
+                          statuses=sorted(set(int(o["rc"]) for o in outs)),
+                          max_resid=float(max(o["resid"] for o in outs)))
+
+    # arrival times at unit rate, scaled per run (the problems do not depend on the rate)
+    stream = W.serve_requests(2000, 1.0)
+    _, cap = run(stream[:300], 0.0, "capacity")
+    capacity = cap["solves_per_s"]
+    res = dict(workload="Poisson arrivals of grid requests: 60%% 32x32, 30%% 64x64, 10%% 128x128, Gaussian-mixture "
+                        "or white-noise histograms, eta = 1e-3, K = %d, mixed precision; %d workers (live batches of "
+                        "up to %d requests)" % (K, workers, max_batch),
+               capacity=dict(cap, what="300 requests submitted at once"), rates={})
+    outs07 = None
+    for f, count in ((0.3, 400), (0.5, 400), (0.7, 2000), (0.9, 400)):
+        outs, r = run(stream[:count], f * capacity, "%.1f" % f)
+        res["rates"]["%.1f" % f] = dict(r, rate_per_s=f * capacity)
+        if f == 0.7:
+            outs07 = outs
+    fx = os.path.join(ROOT, "tests", "golden", "c5_oracle.npz")
+    if os.path.exists(fx) and outs07 is not None:
+        f = np.load(fx)
+        acc = []
+        for q, c in zip(f["index"], f["cost"]):
+            o = outs07[int(q)]
+            acc.append(dict(request=int(q), side=stream[int(q)]["s"], rel_cost_diff=abs(o["cost"] - c) / c,
+                            max_potential_diff=float(max(np.abs(o["alpha"] - f["alpha_%d" % q]).max(),
+                                                         np.abs(o["beta"] - f["beta_%d" % q]).max()))))
+        res["accuracy_vs_oracle"] = acc
     return res
 
 

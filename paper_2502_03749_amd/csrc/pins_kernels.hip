@@ -151,6 +151,14 @@ template <>
 __device__ __forceinline__ double ex<double>(double y, const double* T64) { return texp(y, T64); }
 template <>
 __device__ __forceinline__ float ex<float>(double y, const double*) { return __expf((float)y); }
+// exp in the sweep's precision of an argument <= 0 (the log-sum-exp sweeps'
+// exp(z - max)): double takes the table method's non-positive form
+template <class T>
+__device__ __forceinline__ T exn(double y, const double* T64);
+template <>
+__device__ __forceinline__ double exn<double>(double y, const double* T64) { return texp_eval_nonpos(y, T64); }
+template <>
+__device__ __forceinline__ float exn<float>(double y, const double*) { return __expf((float)y); }
 // the same without a table (the few merges of partial pairs)
 template <class T>
 __device__ __forceinline__ T exs(double y);
@@ -387,13 +395,13 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
                 cm = fmax(cm, z[u]);
             }
             if (cm > mx) {
-                sm *= ex<T>(mx - cm, sT);
+                sm *= exn<T>(mx - cm, sT);
                 mx = cm;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * 64 + lane;
-                if (j < n) sm += ex<T>(z[u] - mx, sT);
+                if (j < n) sm += exn<T>(z[u] - mx, sT);
             }
         }
         wave_lse(mx, sm);
@@ -449,12 +457,12 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
             cm = fmax(cm, z[u]);
         }
         if (cm > mx) {
-            sm *= ex<T>(mx - cm, sT);
+            sm *= exn<T>(mx - cm, sT);
             mx = cm;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (i + u < i1) sm += ex<T>(z[u] - mx, sT);
+            if (i + u < i1) sm += exn<T>(z[u] - mx, sT);
     }
     reinterpret_cast<double2*>(I.part)[(long)rb * n + j] = make_double2(mx, (double)sm);
 }

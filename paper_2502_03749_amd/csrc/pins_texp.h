@@ -37,4 +37,22 @@ __host__ __device__ inline double texp_eval(double x, const double* T) {
     return ldexp(fma(tj, q, tj), nk >> 6);
 }
 
+// The same for arguments x <= 0 or -inf (the log-sum-exp sweeps' exp(z - max)):
+// one maximum replaces the clamps and the NaN guard (a NaN argument is not
+// expected here and gives 0).  Bitwise the value of texp_eval for x <= 0.
+__host__ __device__ inline double texp_eval_nonpos(double x, const double* T) {
+    x = fmax(x, -746.0);
+    const double nd = rint(x * 92.33248261689366);  // 64 / ln 2
+    const int nk = (int)nd;
+    double r = fma(-nd, 0x1.62e42fefa39efp-7, x);   // ln 2 / 64, leading part
+    r = fma(-nd, 0x1.abc9e3b39803fp-62, r);         // ln 2 / 64, trailing part
+    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    q *= r;
+    const double tj = T[nk & 63];
+    return ldexp(fma(tj, q, tj), nk >> 6);
+}
+
 }  // namespace pins

@@ -20,3 +20,4 @@ def test_texp_against_libm(tmp_path):
     assert int(res["special_ok"]) == 1
     assert int(res["n"]) > 5_000_000
     assert float(res["max_ulp"]) <= 1.0, res
+    assert int(res["nonpos_diff"]) == 0, res  # the sweeps' form for x <= 0 is bitwise the general one

@@ -55,6 +55,15 @@ int main(int argc, char** argv) {
                    pins::texp_eval(-INFINITY, T) == 0.0 && std::isinf(pins::texp_eval(710.5, T)) &&
                    std::isinf(pins::texp_eval(INFINITY, T)) && std::isinf(pins::texp_eval(1e300, T)) &&
                    std::isnan(pins::texp_eval(NAN, T)) && pins::texp_eval(0.0, T) == 1.0;
-    std::printf("max_ulp %.6g worst_x %.17g n %ld special_ok %d\n", worst, wx, count, special ? 1 : 0);
+    // the non-positive form: bitwise the general one for x <= 0 (and 0 for -inf)
+    long nonpos_diff = 0;
+    for (long i = 0; i < n / 4; ++i) {
+        const double x = -std::fabs(U(g));
+        if (pins::texp_eval_nonpos(x, T) != pins::texp_eval(x, T)) ++nonpos_diff;
+    }
+    for (double x : {0.0, -0.0, -746.0, -745.5, -1e6, -(double)INFINITY})
+        if (pins::texp_eval_nonpos(x, T) != pins::texp_eval(x, T)) ++nonpos_diff;
+    std::printf("max_ulp %.6g worst_x %.17g n %ld special_ok %d nonpos_diff %ld\n", worst, wx, count,
+                special ? 1 : 0, nonpos_diff);
     return 0;
 }
