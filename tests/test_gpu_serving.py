@@ -166,3 +166,26 @@ def test_dense_requests_with_a_non_finite_cost_are_rejected_at_submit():
             assert o["rc"] == 0 and al["cost"] == o["cost"] and np.array_equal(al["alpha"], o["alpha"])
     finally:
         ctx.close()
+
+
+def test_served_requests_match_stored_oracle_outputs():
+    """The sampled requests of the served workload that have stored oracle
+    outputs (tests/golden/c5_oracle.npz: six 32x32 and two 64x64 grid requests,
+    eta = 1e-3, K = 10), served together in mixed precision: relative cost
+    difference and potentials within 1e-6 of the oracle."""
+    import os
+
+    print("case serving vs stored oracle", flush=True)
+    f = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle.npz"))
+    stream = W.serve_requests(int(f["stream"]), 1.0)
+    prm = P.params(eta=float(f["eta"]), max_outer=int(f["K"]), precision=P.MIXED)
+    srv = P.Server(prm, workers=2, max_batch=8)
+    idx = [int(q) for q in f["index"]]
+    tickets = [srv.submit(P.COST_GRID, stream[q]["a"], stream[q]["b"], grid_s=stream[q]["s"]) for q in idx]
+    out = [srv.wait(t) for t in tickets]
+    srv.close()
+    for q, o, c in zip(idx, out, f["cost"]):
+        assert o["rc"] == 0 and o["resid"] <= 1e-10, q
+        assert abs(o["cost"] - c) <= 1e-6 * c, (q, o["cost"], c)
+        assert np.abs(o["alpha"] - f["alpha_%d" % q]).max() <= 1e-6, q
+        assert np.abs(o["beta"] - f["beta_%d" % q]).max() <= 1e-6, q
