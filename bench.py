@@ -74,7 +74,6 @@ FLOPS_PER_ENTRY = {
     "col_lse": 7.0 + EXP_FLOPS,
     # exponent (3) + level test (3); exp only on kept entries (not counted)
     "fill": 7.0,
-    "csc": 7.0,
     # exponent (3) + exp + cost/entropy/marginal accumulations (6)
     "final": 10.0 + EXP_FLOPS,
     # matrix-free Hessian products: exponent (3) + exp + product/accumulate (2) per entry and half
@@ -851,8 +850,10 @@ def sweep_roofline(P, ctx, torch, np, dev, side=16384, sweeps=7):
         res[name] = ent
     del C
     torch.cuda.empty_cache()
+    # Alg. 1's f-update and g-update each read the cost once: the g-update uses
+    # the new f (Gauss-Seidel), so the two cannot share one pass over C
     return dict(workload="dense %dx%d FP64 cost (%.2f GB), %d warm-up iterations" % (m, n, 8.0 * m * n / 1e9, sweeps),
-                bytes_per_half_sweep=bytes_per_sweep, peak_GBs=PEAK_HBM_GBS, **res)
+                bytes_per_half_sweep=bytes_per_sweep, cost_reads_per_iteration=2, peak_GBs=PEAK_HBM_GBS, **res)
 
 
 def streamed_sweep(P, ctx, torch, np, dev, W, side=128, sweeps=7):

@@ -169,7 +169,8 @@ typedef struct {
     int32_t kern_calls[PINS_NKERN];
     double kern_work[PINS_NKERN]; /* work per kernel class by this instance, always filled:
                                      dense passes: matrix entries visited;
-                                     PCG: stored CSR+CSC entries read (2 nnz per CG iteration) */
+                                     CG classes: stored CSR+CSC entries read (2 nnz per CG
+                                     iteration), by the class that ran this instance's CG */
     int32_t group;        /* batch entry point: lane that solved this instance (kern_* are that
                              lane's totals, shared by the instances of the group) */
     int32_t reserved;
@@ -182,8 +183,9 @@ typedef struct {
 #define PINS_K_GRAD 3      /* Newton pass: Xt row/col sums, Sparsify histogram */
 #define PINS_K_GRAD_MERGE 4 /* gradient merge, convergence, Sparsify level, CSR row pointers */
 #define PINS_K_FILL 5      /* Sparsify: counts, pointer scans, CSR+CSC fill */
-#define PINS_K_CSC 6       /* (unused) */
-#define PINS_K_PCG 7       /* preconditioned CG */
+#define PINS_K_PCG_ROWS 6  /* one-block CG over row-contiguous S (instances whose S has too many
+                              row pieces for the jagged-diagonal form) */
+#define PINS_K_PCG 7       /* preconditioned CG, one block per instance (jagged-diagonal S) */
 #define PINS_K_LS 8        /* Armijo trial pass */
 #define PINS_K_UPDATE 9    /* dual update */
 #define PINS_K_SHIFT 10    /* outer shift */

@@ -28,7 +28,7 @@ FP64, MIXED, MIXED_FAST = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 64 << 20
 SHIFT_IMPLICIT, SHIFT_MATERIALIZED = 0, 1
 NKERN = 16
-KERNEL_NAMES = ["row_lse", "col_lse", "col_merge", "grad", "grad_merge", "fill", "csc", "pcg", "ls", "update",
+KERNEL_NAMES = ["row_lse", "col_lse", "col_merge", "grad", "grad_merge", "fill", "pcg_rows", "pcg", "ls", "update",
                 "shift", "final", "setup", "pcg_wide"]
 
 _D = ctypes.POINTER(ctypes.c_double)

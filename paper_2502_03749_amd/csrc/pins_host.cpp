@@ -492,7 +492,12 @@ struct OuterRunner {
             // sparsified products: the one-block CG for the instances with m + n <=
             // WCG_MAX_N and the wide CG for the others (the choice is each
             // instance's own); matrix-free products: the wide CG for every instance
-            if (!mf_ && L.any_small) run_k(PINS_K_PCG, [&] { launch_pcg(L); });
+            // (the storage form of each instance's S is chosen on the device: both
+            // forms' kernels are launched, each returning at once for the others)
+            if (!mf_ && L.any_small) {
+                run_k(PINS_K_PCG, [&] { launch_pcg(L, true); });
+                run_k(PINS_K_PCG_ROWS, [&] { launch_pcg(L, false); });
+            }
             if (mf_ || L.any_wide16 || L.any_wide32) {
                 // wide or matrix-free CG: iterations in chunks between readbacks of cg_on
                 const int hsrc = mf_ ? src : -1;
@@ -861,6 +866,7 @@ int solve_impl(Lane* ctx, const pins_problem* probs, int count, const pins_param
         r.kern_work[PINS_K_GRAD] = S.work[W_GRAD];
         r.kern_work[PINS_K_FILL] = S.work[W_FILL];
         r.kern_work[PINS_K_PCG] = S.work[W_CG];
+        r.kern_work[PINS_K_PCG_ROWS] = S.work[W_CG_ROWS];
         r.kern_work[PINS_K_PCG_WIDE] = S.work[W_CG_WIDE];
         r.kern_work[PINS_K_LS] = S.work[W_LS];
         r.kern_work[PINS_K_FINAL] = S.work[W_FINAL];

@@ -24,6 +24,7 @@ constexpr int LS_T = 8;      // trial step sizes per line-search pass (after the
 constexpr int TILE_C = 256;  // columns per tile (one per thread)
 constexpr int TILE_RMAX = 16;  // maximum rows per tile
 constexpr int NBIN = 6;        // CG row bins: <= 1, 2, 4, 8, 16 and more quads
+constexpr int JDS_PQ = 16;     // one-block CG, jagged-diagonal storage: quads per row piece
 constexpr int WCG_NT = 256;        // wide CG: threads per block of a half-product (256/512/1024 measured)
 constexpr int WCG_ROWS = WCG_NT / 8;  // wide CG: rows of one half of M per block
 constexpr int WCG_MAX_N = 4096;  // instances with m+n above this take the wide CG
@@ -83,7 +84,8 @@ struct DevInst {
     int* colptr;    // n+1
     void* rowT;     // nnz_cap row indices of S^T
     void* valT;     // nnz_cap values of S^T
-    int* rowbin;    // m+n rows of M = [. S; S^T .]: rows of S by quad count (NBIN bins), then rows of S^T
+    int* rowbin;    // m+n rows of M = [. S; S^T .]: rows of S by quad count (NBIN bins), then rows of S^T;
+                    // with Ctrl::jds, per row k the positions of its pieces instead (jds_info)
     double* Ck;     // materialised shifted cost (m*n) or nullptr
     double* alpha;  // outputs
     double* beta;
@@ -99,7 +101,7 @@ struct Ctrl {
     double kappa, err, resid, alpha;
     double gd, dab, fa, cost;
     double entropy, dual, scale, pad2;
-    double work[8];  // matrix entries visited per pass kind (W_* below); W_CG: stored entries read by CG
+    double work[9];  // matrix entries visited per pass kind (W_* below); W_CG*: stored entries read by CG
     int binoff[16];  // rowbin offsets: NBIN bins of rows of S, then NBIN bins of rows of S^T; [2 NBIN] = m+n
     int cg_it, cg_on;        // wide CG (many blocks per instance): iterations, still iterating
     int decided;             // 1: the next round's gradient already merged and decided (after the fused trial)
@@ -111,10 +113,20 @@ struct Ctrl {
     // of the subproblems before the last (tol_in) and of the last (tol_fin)
     int k_out, K_out;
     double tol_in, tol_fin;
+    // one-block CG storage of S and S^T chosen at the last Sparsify: jds = 1 for
+    // the jagged-diagonal form (rows cut into pieces of at most JDS_PQ quads,
+    // pieces of one half ordered by length, longest first; quad q of the piece
+    // at position v is quad jdp[h][q] + v of the half's arrays), else 0 for the
+    // row-contiguous form with the binned row list
+    int jds;
+    int jdp[2][JDS_PQ + 1];
 };
 
 // pass kinds counted in Ctrl::work
-enum WorkKind : int { W_ROW = 0, W_COL = 1, W_GRAD = 2, W_FILL = 3, W_CG = 4, W_LS = 5, W_FINAL = 6, W_CG_WIDE = 7 };
+// (W_CG: one-block CG over jagged-diagonal S, W_CG_ROWS: over row-contiguous S)
+enum WorkKind : int {
+    W_ROW = 0, W_COL = 1, W_GRAD = 2, W_FILL = 3, W_CG = 4, W_LS = 5, W_FINAL = 6, W_CG_WIDE = 7, W_CG_ROWS = 8
+};
 
 // Kernel-wide parameters (passed by value).
 struct KP {

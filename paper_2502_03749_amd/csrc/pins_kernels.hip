@@ -37,6 +37,13 @@ namespace pins {
 
 static constexpr double INV_LN10 = 0.43429448190325182765;
 
+// load through the global address space (the pointers live in descriptors,
+// so the compiler cannot infer it and would otherwise emit flat loads)
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // cost sources
 // ---------------------------------------------------------------------------
@@ -49,7 +56,7 @@ struct DenseSrc {
     double s;
     __device__ __forceinline__ DenseSrc(const DevInst& I, bool base = false)
         : C(base ? I.cbase : I.csrc), ld(I.ldc), s(base ? I.bscale : I.cscale) {}
-    __device__ __forceinline__ double at(int i, int j) const { return C[(long)i * ld + j] * s; }
+    __device__ __forceinline__ double at(int i, int j) const { return ldg(C + ((long)i * ld + j)) * s; }
 };
 
 // Squared distance between pixels p = row*s + col of an s x s grid, times the
@@ -71,12 +78,6 @@ struct GridSrc {
     }
 };
 
-// load through the global address space (the pointers live in descriptors,
-// so the compiler cannot infer it and would otherwise emit flat loads)
-template <class T>
-__device__ __forceinline__ T ldg(const T* p) {
-    return *(const __attribute__((address_space(1))) T*)p;
-}
 
 // log of the recovery map, eq. (eppa_x): (F_i + G_j - kappa*C_ij)/eta
 __device__ __forceinline__ double expo(double Fi, double Gj, double kap, double c, double ie) {
@@ -385,7 +386,28 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
         double mx = -INFINITY;
         T sm = T(0);
         constexpr int U = 4;
-        for (int j0 = 0; j0 < n; j0 += 64 * U) {
+        // chunks of 64 U columns: the full ones without bounds tests (so that
+        // their U loads of C and G are issued together), then the last partial
+        // one; the same operations in the same order either way
+        const int nfull = n - n % (64 * U);
+        int j0 = 0;
+        for (; j0 < nfull; j0 += 64 * U) {
+            double z[U];
+            double cm = -INFINITY;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * 64 + lane;
+                z[u] = (ldg(G + j) - kap * src.at(i, j)) * ie;
+                cm = fmax(cm, z[u]);
+            }
+            if (cm > mx) {
+                sm *= exn<T>(mx - cm, sT);
+                mx = cm;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) sm += exn<T>(z[u] - mx, sT);
+        }
+        if (j0 < n) {
             double z[U];
             double cm = -INFINITY;
 #pragma unroll
@@ -447,7 +469,26 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
     double mx = -INFINITY;
     T sm = T(0);
     constexpr int U = 4;
-    for (int i = i0; i < i1; i += U) {
+    // groups of U rows: the full ones without bounds tests (their U loads
+    // issued together), then the last partial one; the same operations in the
+    // same order either way
+    int i = i0;
+    for (; i + U <= i1; i += U) {
+        double z[U];
+        double cm = -INFINITY;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            z[u] = (sF[i + u - i0] - kap * src.at(i + u, j)) * ie;
+            cm = fmax(cm, z[u]);
+        }
+        if (cm > mx) {
+            sm *= exn<T>(mx - cm, sT);
+            mx = cm;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) sm += exn<T>(z[u] - mx, sT);
+    }
+    if (i < i1) {
         double z[U];
         double cm = -INFINITY;
 #pragma unroll
@@ -607,14 +648,20 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
     const Src src(I);
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
     double colacc = 0.0;
+    const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
     for (int r0 = 0; r0 < rows; r0 += 4) {
+        // the group's 4 cost values first (clamped in range, so that their
+        // loads are issued together), then the entries
+        double cv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cv[u] = src.at(i0 + min(r0 + u, rows - 1), jc);
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int r = r0 + u;
             double e = 0.0;
             if (valid && r < rows) {
-                const double x = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
+                const double x = expo(sF[r], Gj, kap, cv[u], ie);
                 e = texp(x, sT);
                 const double q = lev_q(x, lrho, sLa[r], lbj);
                 if (q >= 0.0) {
@@ -749,9 +796,12 @@ __global__ __launch_bounds__(256) void k_grad_decide(const DevInst* __restrict__
 // a6: Sparsify at the chosen level: keep Xt_ij >= rho*10^lev*min(a_i,b_j).
 // Three steps, all tile-parallel and deterministic:
 //   k_count  kept entries per (row, column block) and per (row block, column)
-//   k_scan   CSR row pointers and CSC column pointers (exclusive scans)
+//   k_scan   CSR row pointers and CSC column pointers (exclusive scans), and
+//            the CG's storage form: jagged-diagonal (one-block CG instances,
+//            when it fits) or row-contiguous with a binned row list
 //   k_fill   both copies of S in one pass: CSR rows in column order (ballot
-//            prefix within the tile row), CSC columns in row order.
+//            prefix within the tile row), CSC columns in row order, each entry
+//            at the slot the storage form gives it.
 // count and fill take the keep decision with the same arithmetic, so the
 // pointers match what the fill writes.
 // ---------------------------------------------------------------------------
@@ -788,12 +838,22 @@ __global__ __launch_bounds__(256) void k_count(const DevInst* __restrict__ insts
     const Src src(I);
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
     int cc = 0;
-    for (int r = 0; r < rows; ++r) {
-        bool keep = false;
-        if (valid) keep = lev_q(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), lrho, sLa[r], lbj) >= lev;
-        cc += keep ? 1 : 0;
-        const unsigned long long bal = __ballot(keep);
-        if (lane == 0) wc[r][w] = (int)__popcll(bal);
+    const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
+    for (int r0 = 0; r0 < rows; r0 += 4) {
+        double cv[4];  // the group's cost values first (loads issued together)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cv[u] = src.at(i0 + min(r0 + u, rows - 1), jc);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u;
+            if (r < rows) {
+                bool keep = false;
+                if (valid) keep = lev_q(expo(sF[r], Gj, kap, cv[u], ie), lrho, sLa[r], lbj) >= lev;
+                cc += keep ? 1 : 0;
+                const unsigned long long bal = __ballot(keep);
+                if (lane == 0) wc[r][w] = (int)__popcll(bal);
+            }
+        }
     }
     __syncthreads();
     if (valid) I.cntc[(long)rb * n + j] = cc;
@@ -838,6 +898,80 @@ __global__ __launch_bounds__(256) void k_scan_totals(const DevInst* __restrict__
                           : prefix_in_place(I.cntc + (k - m), n, I.nrb);
 }
 
+// Entries per thread of the one-block CG for an instance with m + n = N (the
+// kernel is launched with the largest over its batch, never fewer).
+__device__ __forceinline__ int pcg_ept(int N) { return N <= 1024 ? 1 : N <= 2048 ? 2 : 4; }
+
+// Jagged-diagonal storage for the one-block CG (see Ctrl::jds).  Each row of a
+// half (rows of S, then rows of S^T) of nq quads is cut into nq / JDS_PQ full
+// pieces and, if nq is not a multiple, one shorter piece; the pieces of a half
+// are ordered by length, longest first, so that the pieces longer than q take
+// positions 0 .. cnt(q) - 1 and quad q of the piece at position v is stored
+// at quad jdp[q] + v, jdp[q] = cnt(0) + ... + cnt(q - 1).  The lanes of a
+// wave, one piece each, then read consecutive quads.  Per row k, rowbin[k]
+// receives jds_info: the position of its first full piece (the full pieces
+// are consecutive) in the low 16 bits, 1 + the position of its shorter piece
+// (0: none) in the high bits.  Positions within a length are handed out by
+// atomics, so the layout may differ from run to run; each row's entries, their
+// order and every sum formed from them do not.  Returns false, writing
+// nothing but Ctrl::jds = 0, when a half has more pieces than the CG's LDS
+// array of partial sums holds (1024 * pcg_ept(N)).
+template <class NQ>
+__device__ bool jds_layout(const DevInst& I, Ctrl& C, int m, int N, NQ nq_of) {
+    __shared__ int hist[2][JDS_PQ + 1];
+    const int tid = threadIdx.x;
+    if (tid < 2 * (JDS_PQ + 1)) (&hist[0][0])[tid] = 0;
+    __syncthreads();
+    for (int k = tid; k < N; k += 1024) {
+        const int nq = nq_of(k), h = k >= m;
+        const int F = nq / JDS_PQ, rem = nq - F * JDS_PQ;
+        if (F) atomicAdd(&hist[h][JDS_PQ], F);
+        if (rem) atomicAdd(&hist[h][rem], 1);
+    }
+    __syncthreads();
+    if (tid < 2) {
+        const int h = tid;
+        // hist[h][L] (count of pieces of length L) -> first position of that
+        // length = number of pieces longer than L; hist[h][0] = all pieces
+        int acc = 0;
+        for (int L = JDS_PQ; L >= 1; --L) {
+            const int c = hist[h][L];
+            hist[h][L] = acc;
+            acc += c;
+        }
+        hist[h][0] = acc;
+        int d = 0;
+        C.jdp[h][0] = 0;
+        for (int q = 0; q < JDS_PQ; ++q) {
+            d += hist[h][q];  // pieces longer than q
+            C.jdp[h][q + 1] = d;
+        }
+    }
+    __syncthreads();
+    const int vmax = 1024 * pcg_ept(N);
+    if (hist[0][0] > vmax || hist[1][0] > vmax) {
+        if (tid == 0) C.jds = 0;
+        return false;
+    }
+    for (int k = tid; k < N; k += 1024) {
+        const int nq = nq_of(k), h = k >= m;
+        const int F = nq / JDS_PQ, rem = nq - F * JDS_PQ;
+        const int fb = F ? atomicAdd(&hist[h][JDS_PQ], F) : 0;
+        const int pp = rem ? atomicAdd(&hist[h][rem], 1) : -1;
+        I.rowbin[k] = fb | ((pp + 1) << 16);
+    }
+    if (tid == 0) C.jds = 1;
+    return true;
+}
+
+// Slot (entry index in the half's arrays) of entry e of a row of nq quads
+// with jds_info `info` (see jds_layout); entry e lies in piece e / (4 JDS_PQ).
+__device__ __forceinline__ int jds_slot(const int* jdp, int info, int nq, int e) {
+    const int p = e / (4 * JDS_PQ), e2 = e - p * (4 * JDS_PQ);
+    const int v = (p < nq / JDS_PQ) ? (info & 0xffff) + p : (info >> 16) - 1;
+    return 4 * (jdp[e2 >> 2] + v) + (e2 & 3);
+}
+
 __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl) {
     const int b = blockIdx.x;
     if (ctrl[b].phase != PH_NEWTON) return;
@@ -869,18 +1003,24 @@ __global__ __launch_bounds__(1024) void k_scan(const DevInst* __restrict__ insts
             ctrl[b].nnz = (int)(t < I.nnz_cap ? t : I.nnz_cap);
         }
     }
-    // rows of M grouped by quad count for the CG's product, in row order
-    // within each bin: a counting pass (per-wave ballots, wave totals in LDS),
-    // the bin offsets, then a placing pass over 1024-row chunks in order; the
-    // pointers written above are visible to the whole block after the barrier
+    // the pointers written above are visible to the whole block after the barrier
     __syncthreads();
+    auto nq_of = [&](int k) {
+        return (k < m) ? (I.rowptr[k + 1] - I.rowptr[k]) >> 2 : (I.colptr[k - m + 1] - I.colptr[k - m]) >> 2;
+    };
+    // one-block CG instances: the jagged-diagonal form when it fits
+    if (!(I.cgfmt & 1) && jds_layout(I, ctrl[b], m, N, nq_of)) return;
+    if (threadIdx.x == 0) ctrl[b].jds = 0;
+    // otherwise rows of M grouped by quad count for the CG's product, in row
+    // order within each bin: a counting pass (per-wave ballots, wave totals in
+    // LDS), the bin offsets, then a placing pass over 1024-row chunks in order
     constexpr int NG2 = 2 * NBIN;
     __shared__ int wcnt[16][NG2];
     __shared__ int boff[NG2];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     auto bin_of = [&](int k) {
-        const int nq = (k < m) ? (I.rowptr[k + 1] - I.rowptr[k]) >> 2 : (I.colptr[k - m + 1] - I.colptr[k - m]) >> 2;
+        const int nq = nq_of(k);
         const int t = nq <= 1 ? 0 : nq <= 2 ? 1 : nq <= 4 ? 2 : nq <= 8 ? 3 : nq <= 16 ? 4 : 5;
         return (k < m ? 0 : NBIN) + t;
     };
@@ -964,10 +1104,12 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     const int m = I.m, n = I.n;
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
     __shared__ double sF[TILE_RMAX], sLa[TILE_RMAX];
-    __shared__ int sStart[TILE_RMAX], sNq[TILE_RMAX], sE0[TILE_RMAX];
+    __shared__ int sStart[TILE_RMAX], sNq[TILE_RMAX], sE0[TILE_RMAX], sInfo[TILE_RMAX];
+    __shared__ int sJd[2][JDS_PQ + 1];
     __shared__ double sT[64];
     texp_table(sT);
     __shared__ int wc[TILE_RMAX][4];
+    const int jds = ctrl[b].jds;  // storage form chosen by k_scan (uniform over the block)
     if ((int)threadIdx.x < rows) {
         const int i = i0 + threadIdx.x;
         sF[threadIdx.x] = I.F[i];
@@ -975,8 +1117,14 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
         sE0[threadIdx.x] = I.cntr[(long)i * I.ncb + cb];  // prefix over the column blocks (k_scan)
         sStart[threadIdx.x] = I.rowptr[i];
         sNq[threadIdx.x] = (I.rowptr[i + 1] - I.rowptr[i]) >> 2;
+        sInfo[threadIdx.x] = jds ? I.rowbin[i] : 0;
     }
+    if (jds && (int)threadIdx.x < 2 * (JDS_PQ + 1)) (&sJd[0][0])[threadIdx.x] = (&ctrl[b].jdp[0][0])[threadIdx.x];
     __syncthreads();
+    // slot of entry e of a row of S (jd = sJd[0]) or of S^T (sJd[1])
+    auto slot_of = [&](const int* jd, int start, int nq, int info, int e) {
+        return jds ? jds_slot(jd, info, nq, e) : quad_slot(start, nq, e);
+    };
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -990,20 +1138,25 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     };
     const Src src(I);
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
-    int ce = 0, cstart = 0, cnq = 0;  // entry index within column j, its start and quad count
+    int ce = 0, cstart = 0, cnq = 0, cinfo = 0;  // entry index within column j, its start and quad count
     if (valid) {
         ce = I.cntc[(long)rb * n + j];  // prefix over the row blocks (k_scan)
         cstart = I.colptr[j];
         cnq = (I.colptr[j + 1] - cstart) >> 2;
+        if (jds) cinfo = I.rowbin[m + j];
     }
     double xr[TILE_RMAX];
     unsigned keepm = 0;
+    const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
+#pragma unroll
+    for (int r = 0; r < TILE_RMAX; ++r) xr[r] = src.at(i0 + min(r, rows - 1), jc);  // loads issued together
 #pragma unroll
     for (int r = 0; r < TILE_RMAX; ++r) {
+        const double cr = xr[r];
         xr[r] = 0.0;
         bool keep = false;
         if (r < rows && valid) {
-            xr[r] = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
+            xr[r] = expo(sF[r], Gj, kap, cr, ie);
             keep = lev_q(xr[r], lrho, sLa[r], lbj) >= lev;
         }
         if (r < rows) {
@@ -1025,12 +1178,12 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
             const VT v = (VT)texp(xr[r], sT);
             const int nq = sNq[r];
             if (e < 4 * nq) {
-                const int slot = quad_slot(sStart[r], nq, e);
+                const int slot = slot_of(sJd[0], sStart[r], nq, sInfo[r], e);
                 put(I.col, slot, j, m);
                 static_cast<VT*>(I.val)[slot] = v;
             }
             if (ce < 4 * cnq) {
-                const int slot = quad_slot(cstart, cnq, ce);
+                const int slot = slot_of(sJd[1], cstart, cnq, cinfo, ce);
                 put(I.rowT, slot, i0 + r, 0);
                 static_cast<VT*>(I.valT)[slot] = v;
             }
@@ -1041,14 +1194,14 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     // last column block, columns of S^T in the last row block
     if (rb == I.nrb - 1 && valid)
         for (; ce < 4 * cnq; ++ce) {
-            const int slot = quad_slot(cstart, cnq, ce);
+            const int slot = slot_of(sJd[1], cstart, cnq, cinfo, ce);
             put(I.rowT, slot, 0, 0);
             static_cast<VT*>(I.valT)[slot] = (VT)0;
         }
     if (cb == I.ncb - 1 && (int)threadIdx.x < rows) {
         const int r = threadIdx.x, nq = sNq[r];
         for (int e = sE0[r] + wc[r][0] + wc[r][1] + wc[r][2] + wc[r][3]; e < 4 * nq; ++e) {
-            const int slot = quad_slot(sStart[r], nq, e);
+            const int slot = slot_of(sJd[0], sStart[r], nq, sInfo[r], e);
             put(I.col, slot, 0, m);
             static_cast<VT*>(I.val)[slot] = (VT)0;
         }
@@ -1069,13 +1222,15 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
 // ||b||_2 (or cg_max iterations) is the rule for M's system itself.  For
 // m + n <= WCG_MAX_N one block of 1024 threads per instance; each thread owns
 // the vector entries k = tid + 1024 t (the row iterate, residual and direction
-// in registers, the rest in LDS); the products are done by lane groups over the
-// binned rows, gathering from LDS.  Larger instances take the wide CG below.
+// in registers, the rest in LDS); the products gather from LDS, one lane per
+// row piece when S is stored in the jagged-diagonal form (jds_layout; the
+// piece sums then added per row in order), else by lane groups over the
+// binned rows.  Larger instances take the wide CG below.
 // Afterwards the line-search inputs <grad P, d>, <a,dF>+<b,dG> and the
 // resolution test.
 // ---------------------------------------------------------------------------
-// Off-diagonal part of M times p (S v for a row k < m, S^T u for k >= m).
-// Rows are stored in aligned, transposed quads (see quad_slot); the entry
+// Off-diagonal part of M times p (S v for a row k < m, S^T u for k >= m), row-
+// contiguous form.  Rows are stored in aligned, transposed quads (see quad_slot); the entry
 // order inside a row does not matter for the product.  The rows of one bin
 // (similar quad counts) are handled by groups of G lanes, so the lanes of a
 // wave do rows of about the same length; a lane loads each quad (its 4
@@ -1187,7 +1342,7 @@ __device__ __forceinline__ void spmv_bin(const SpArrays<IX, VT>& A, int m, const
                 if (q + u * G < q1) {
                     x[u] = ldg(ix + q + u * G);
                     w[u] = ldg(vl + q + u * G);
-                }
+                    }
 #pragma unroll
             for (int u = 0; u < U - 1; ++u)
                 if (q + u * G < q1) s[u] += quad_dot<IX>(x[u], w[u], pvo);
@@ -1224,11 +1379,89 @@ __device__ __forceinline__ void spmv_part(const SpArrays<IX, VT>& A, int m, cons
     spmv_bin<cg_lanes(32), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[5], bo[6], rp, cp, pv, fin);
 }
 
+// One half of M's off-diagonal product in the jagged-diagonal form (see
+// jds_layout): lane v of the block sums piece v (its quads in order, U in
+// flight) into part[v]; jd = the half's quad offsets jdp[0..JDS_PQ] in LDS.
+// The lanes of a wave take consecutive pieces of about the same length, so
+// each of its quad loads reads consecutive memory and no lane waits for a
+// cross-lane reduction.
+// element k of an array of V, the byte offset formed in 32 bits (so that the
+// load takes the array's base from scalar registers; one-block instances' S
+// arrays are far below 4 GiB)
+template <class V>
+__device__ __forceinline__ V ld32(const V* base, int k) {
+    return ldg(reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + (unsigned)k * (unsigned)sizeof(V)));
+}
+
+template <int U, class IX, class VT>
+__device__ __forceinline__ void jds_half(const IX* ixa, const VT* vla, const int* jd, const double* __restrict__ pv,
+                                         double* __restrict__ part) {
+    typedef typename QuadIx<IX>::T XV;
+    typedef typename QuadVal<VT>::T WV;
+    const XV* ix = reinterpret_cast<const XV*>(ixa);
+    const WV* vl = reinterpret_cast<const WV*>(vla);
+    const int V = jd[1];  // every piece has at least one quad
+    for (int v = threadIdx.x; v < V; v += 1024) {
+        double s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s[u] = 0.0;
+        int q = 0;
+        // quads q .. q+U-1 exist while the piece is longer than q+U-1 (not
+        // unrolled: U quads in flight per lane, not all of the piece's)
+#pragma unroll 1
+        for (; q + U <= JDS_PQ && v < jd[q + U] - jd[q + U - 1]; q += U) {
+            XV x[U];
+            WV w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                x[u] = ld32(ix, jd[q + u] + v);
+                w[u] = ld32(vl, jd[q + u] + v);
+            }
+            // every gather of the U quads is issued before the first product
+            double g[U][4];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                g[u][0] = gat<IX>(pv, (int)x[u].x);
+                g[u][1] = gat<IX>(pv, (int)x[u].y);
+                g[u][2] = gat<IX>(pv, (int)x[u].z);
+                g[u][3] = gat<IX>(pv, (int)x[u].w);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                s[u] += ((double)w[u].x * g[u][0] + (double)w[u].y * g[u][1]) +
+                        ((double)w[u].z * g[u][2] + (double)w[u].w * g[u][3]);
+        }
+        // the piece's last quads (fewer than U)
+        if (U > 1) {
+            XV x[U > 1 ? U - 1 : 1];
+            WV w[U > 1 ? U - 1 : 1];
+            bool h[U > 1 ? U - 1 : 1];
+#pragma unroll
+            for (int u = 0; u < U - 1; ++u) {
+                h[u] = q + u < JDS_PQ && v < jd[q + u + 1] - jd[q + u];
+                if (h[u]) {
+                    x[u] = ld32(ix, jd[q + u] + v);
+                    w[u] = ld32(vl, jd[q + u] + v);
+                    }
+            }
+#pragma unroll
+            for (int u = 0; u < U - 1; ++u)
+                if (h[u]) s[u] += quad_dot<IX>(x[u], w[u], pv);
+        }
+        double tot = s[0];
+#pragma unroll
+        for (int u = 1; u < U; ++u) tot += s[u];
+        part[v] = tot;
+    }
+}
+constexpr int JDS_QUADS = 4;  // quads in flight per lane in jds_half
+
+// kind: the CG's work class (W_CG, W_CG_ROWS or W_CG_WIDE)
 __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp,
-                                         int wide = 0) {
+                                         int kind) {
     S.last_cg = it;
     S.cg_total += it;
-    S.work[wide ? W_CG_WIDE : W_CG] += 2.0 * (double)S.nnz * (double)it;
+    S.work[kind] += 2.0 * (double)S.nnz * (double)it;
     S.fused = 0;
     S.gd = gd;
     S.dab = dab;
@@ -1244,10 +1477,11 @@ __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab,
     }
 }
 
-template <int EPT, class IX, class VT>
+template <int EPT, class IX, class VT, bool JDS>
 __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.x;
-    if (ctrl[b].phase != PH_NEWTON || (insts[b].cgfmt & 1)) return;  // wide instances take the wide CG
+    // wide instances take the wide CG; the instances stored the other way the other instantiation
+    if (ctrl[b].phase != PH_NEWTON || (insts[b].cgfmt & 1) || ctrl[b].jds != (JDS ? 1 : 0)) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
     // LDS: sp, the direction p on the rows and D_c^-1 S^T p on the columns;
@@ -1260,15 +1494,38 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     __shared__ int sptr[1024 * EPT + 2];
     __shared__ int sbin[1024 * EPT];
     __shared__ int sbo[2 * NBIN + 1];
+    __shared__ int sjd[2][JDS_PQ + 1];
     const int tid = threadIdx.x;
     const SpArrays<IX, VT> A(I);
     for (int k = tid; k <= m; k += 1024) sptr[k] = I.rowptr[k];
     for (int k = tid; k <= n; k += 1024) sptr[m + 1 + k] = I.colptr[k];
-    for (int k = tid; k < N; k += 1024) sbin[k] = I.rowbin[k];
+    for (int k = tid; k < N; k += 1024) sbin[k] = I.rowbin[k];  // row list, or jds_info per row
     const int* rp = sptr;
     const int* cp = sptr + m + 1;
     const int* bins = sbin;
     if (tid <= 2 * NBIN) sbo[tid] = ctrl[b].binoff[tid];
+    if (tid < 2 * (JDS_PQ + 1)) (&sjd[0][0])[tid] = (&ctrl[b].jdp[0][0])[tid];
+    // half h of M's off-diagonal product of the vector in sp: row-contiguous
+    // form, (M p)_k into sAp[k]; jagged-diagonal form, piece sums into sAp
+    auto prod = [&](int h) {
+        if constexpr (!JDS)
+            spmv_part<IX, VT>(A, m, bins, sbo + h * NBIN, rp, cp, sp, sAp);
+        else if (h == 0)
+            jds_half<JDS_QUADS, IX, VT>(A.col, A.val, sjd[0], sp, sAp);
+        else
+            jds_half<JDS_QUADS, IX, VT>(A.rowT, A.valT, sjd[1], sp, sAp);
+    };
+    // (M p)_k after prod (and a barrier): the sum of row k's pieces in order
+    auto rowval = [&](int k) -> double {
+        if constexpr (!JDS) return sAp[k];
+        const int info = sbin[k];
+        const int nf = ((k < m) ? (rp[k + 1] - rp[k]) >> 2 : (cp[k - m + 1] - cp[k - m]) >> 2) / JDS_PQ;
+        const int fb = info & 0xffff, pp = (info >> 16) - 1;
+        double v = 0.0;
+        for (int p = 0; p < nf; ++p) v += sAp[fb + p];
+        if (pp >= 0) v += sAp[pp];
+        return v;
+    };
     const double eta = kp.eta;
     // right-hand side eta (target - diagonal) of entry k (recomputed where needed)
     auto rhs = [&](int k) { return eta * (((k < m) ? I.a[k] : I.b[k - m]) - sdg[k]); };
@@ -1290,14 +1547,14 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     }
     bb = block_sum<1024>(bb, sh);  // also orders the LDS writes above
     const double bn = sqrt(bb);
-    spmv_part<IX, VT>(A, m, bins, sbo, rp, cp, sp, sAp);  // S D_c^-1 b_2 on the rows
+    prod(0);  // S D_c^-1 b_2 on the rows
     __syncthreads();
     double rr = 0.0, rz = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const int k = tid + 1024 * t;
         if (k < m) {
-            r[t] = rhs(k) - sAp[k];
+            r[t] = rhs(k) - rowval(k);
             p[t] = r[t] / sdg[k];
             sp[k] = p[t];
             rr += r[t] * r[t];
@@ -1305,29 +1562,28 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
         }
     }
     block_sum2<1024>(rr, rz, sh);
+    // q_k = ((D_r - S D_c^-1 S^T) p)_k, read twice per iteration from the same
+    // products (nothing writes sAp in between)
+    auto qval = [&](int k, double pk) { return sdg[k] * pk - rowval(k); };
     int it = 0;
     if (bn > 0.0 && sqrt(rr) > kp.cg_rtol * bn) {
         while (it < kp.cg_max) {
             __syncthreads();
-            spmv_part<IX, VT>(A, m, bins, sbo + NBIN, rp, cp, sp, sAp);  // S^T p
+            prod(1);  // S^T p
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
-                if (k >= m && k < N) sp[k] = sAp[k] / sdg[k];
+                if (k >= m && k < N) sp[k] = rowval(k) / sdg[k];
             }
             __syncthreads();
-            spmv_part<IX, VT>(A, m, bins, sbo, rp, cp, sp, sAp);  // S D_c^-1 S^T p
+            prod(0);  // S D_c^-1 S^T p
             __syncthreads();
             double pq = 0.0;
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
-                if (k < m) {
-                    const double q = sdg[k] * p[t] - sAp[k];
-                    sAp[k] = q;
-                    pq += p[t] * q;
-                }
+                if (k < m) pq += p[t] * qval(k, p[t]);
             }
             pq = block_sum<1024>(pq, sh);
             if (!(pq > 0.0)) break;
@@ -1339,7 +1595,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
                 const int k = tid + 1024 * t;
                 if (k < m) {
                     x[t] += al * p[t];
-                    r[t] -= al * sAp[k];
+                    r[t] -= al * qval(k, p[t]);
                     rr += r[t] * r[t];
                     rz2 += r[t] * (r[t] / sdg[k]);
                 }
@@ -1367,14 +1623,14 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
         if (k < m) sp[k] = x[t];
     }
     __syncthreads();
-    spmv_part<IX, VT>(A, m, bins, sbo + NBIN, rp, cp, sp, sAp);
+    prod(1);
     __syncthreads();
     double gd = 0.0, dab = 0.0, fa = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const int k = tid + 1024 * t;
         if (k < N) {
-            if (k >= m) x[t] = (rhs(k) - sAp[k]) / sdg[k];
+            if (k >= m) x[t] = (rhs(k) - rowval(k)) / sdg[k];
             const double tg = (k < m) ? I.a[k] : I.b[k - m];
             I.d[k] = x[t];
             gd += (tg - sdg[k]) * x[t];
@@ -1385,7 +1641,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     gd = block_sum<1024>(gd, sh);
     dab = block_sum<1024>(dab, sh);
     fa = block_sum<1024>(fa, sh);
-    if (tid == 0) ls_setup(ctrl[b], it, gd, dab, fa, kp);
+    if (tid == 0) ls_setup(ctrl[b], it, gd, dab, fa, kp, JDS ? W_CG : W_CG_ROWS);
 }
 
 // ---------------------------------------------------------------------------
@@ -1719,7 +1975,7 @@ __global__ __launch_bounds__(1024) void k_wcg_finish(const DevInst* __restrict__
     gd = block_sum<1024>(gd, sh);
     dab = block_sum<1024>(dab, sh);
     fa = block_sum<1024>(fa, sh);
-    if (threadIdx.x == 0) ls_setup(ctrl[b], ctrl[b].cg_it, gd, dab, fa, kp, 1);
+    if (threadIdx.x == 0) ls_setup(ctrl[b], ctrl[b].cg_it, gd, dab, fa, kp, W_CG_WIDE);
 }
 
 // ---------------------------------------------------------------------------
@@ -1769,14 +2025,18 @@ __global__ __launch_bounds__(256) void k_ls_first(const DevInst* __restrict__ in
     const double lbj = valid ? ldg(I.logb + j) : 0.0;
     // expm1(a_i + b_j) = A_i + B_j (1 + A_i) with A_i = expm1(a_i), B_j = expm1(b_j)
     const double Bj = expm1(dGj);
+    const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
     for (int r0 = 0; r0 < rows; r0 += 4) {
+        double cv[4];  // the group's cost values first (loads issued together)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cv[u] = src.at(i0 + min(r0 + u, rows - 1), jc);
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int r = r0 + u;
             double e1 = 0.0;
             if (valid && r < rows) {
-                const double x = expo(sF[r], Gj, kap, src.at(i0 + r, j), ie);
+                const double x = expo(sF[r], Gj, kap, cv[u], ie);
                 const double e = texp(x, sT);
                 const double del = sD[r] + dGj;
                 const double t = e * fma(Bj, sA1[r], sA[r]);
@@ -2414,16 +2674,16 @@ void launch_sparsify(const LaunchCtx& L, int src) {
 // thread owns beyond an instance's m + n add zeros to its sums, so the
 // instance's arithmetic does not depend on the batch's largest m + n.
 static_assert(WCG_MAX_N <= 4 * 1024, "k_pcg_lds holds at most 4096 vector entries");
-template <class IX, class VT>
+template <class IX, class VT, bool JDS>
 static void launch_pcg_t(const LaunchCtx& L) {
     const int ept = (L.max_mn_small + 1023) / 1024;
     const dim3 g(L.count), blk(1024);
     if (ept <= 1)
-        hipLaunchKernelGGL((k_pcg_lds<1, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<1, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else if (ept <= 2)
-        hipLaunchKernelGGL((k_pcg_lds<2, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<2, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else
-        hipLaunchKernelGGL((k_pcg_lds<4, IX, VT>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<4, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
 template <class IX, class VT>
@@ -2490,11 +2750,18 @@ void launch_wcg_end(const LaunchCtx& L, int src) {
 }
 
 // the one-block instances always store int32 byte offsets
-void launch_pcg(const LaunchCtx& L) {
-    if (L.sp_f32)
-        launch_pcg_t<int, float>(L);
-    else
-        launch_pcg_t<int, double>(L);
+void launch_pcg(const LaunchCtx& L, bool jds) {
+    if (jds) {
+        if (L.sp_f32)
+            launch_pcg_t<int, float, true>(L);
+        else
+            launch_pcg_t<int, double, true>(L);
+    } else {
+        if (L.sp_f32)
+            launch_pcg_t<int, float, false>(L);
+        else
+            launch_pcg_t<int, double, false>(L);
+    }
 }
 
 void launch_ls(const LaunchCtx& L, int src, bool first) {

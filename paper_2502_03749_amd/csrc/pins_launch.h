@@ -41,7 +41,9 @@ void launch_sparsify(const LaunchCtx& L, int src);
 void launch_wcg_begin(const LaunchCtx& L, int src);
 void launch_wcg_iter(const LaunchCtx& L, int src);  // one iteration; no per-iteration argument
 void launch_wcg_end(const LaunchCtx& L, int src);
-void launch_pcg(const LaunchCtx& L);  // the one-block CG of the instances with m+n <= WCG_MAX_N
+// the one-block CG of the instances with m+n <= WCG_MAX_N whose S is stored in
+// the jagged-diagonal form (jds) or row-contiguous (the others)
+void launch_pcg(const LaunchCtx& L, bool jds);
 void launch_ls(const LaunchCtx& L, int src, bool first);
 void launch_update(const LaunchCtx& L);
 void launch_shift(const LaunchCtx& L, int base_src);

@@ -544,6 +544,29 @@ def test_sparsify_no_level_within_budget(ctx):
     assert g["nnz_last"] == o["nnz_last"], (g["nnz_last"], o["nnz_last"])
 
 
+def test_cg_storage_forms_against_oracle(ctx):
+    """The one-block CG's two storage forms of S against the oracle: the
+    jagged-diagonal form (rows cut into pieces of up to 16 quads, one lane per
+    piece), and the row-contiguous form it falls back to when a half has more
+    pieces than the CG's LDS array of piece sums holds (1024 for m + n <= 1024,
+    2048 up to 2048, else 4096).  A 100x100 instance at eta = 0.01 keeps a sparse
+    set (jagged-diagonal); a 300x300 instance at eta = 0.5 with a budget of 256
+    spanning trees keeps all 90 000 entries: per half 300 rows of 75 quads, five
+    pieces each, 1500 > 1024 (row-contiguous).  Each form must have done the
+    instance's CG work."""
+    for m, eta, K, budget, cls in ((100, 0.01, 10, 64.0, "pcg"), (300, 0.5, 3, 256.0, "pcg_rows")):
+        print("case cg storage %s m=n=%d" % (cls, m), flush=True)
+        C, a, b = _rand(m, m, 4242 + m)
+        g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), P.params(eta=eta, max_outer=K, budget=budget))
+        g["_C"] = C
+        o = oracle.pins(C, a, b, eta=eta, K=K, budget=budget)
+        check_parity(g, o, a, b)
+        other = "pcg_rows" if cls == "pcg" else "pcg"
+        assert g["kern_work"][cls] > 0 and g["kern_work"][other] == 0, g["kern_work"]
+        if cls == "pcg_rows":
+            assert g["nnz_last"] == m * m
+
+
 def test_mixed_cg_kinds_batch_equals_alone(ctx):
     """The CG an instance takes (one block for m + n <= 4096, else the wide CG
     with 16-bit or 32-bit indices) is its own: a batch that mixes all three
