@@ -439,10 +439,16 @@ def test_gpu_matches_stored_oracle_fixtures(ctx):
     """The HIP path (FP64) against the stored oracle outputs of
     tests/golden/oracle_fixtures.json: the cost at the FP64 parity bar, the
     residual, and the gauge-fixed potentials to 1e-8, except for the
-    random-assignment fixture (1e-5).  Near an assignment (that case at
-    eps = eta / K = 5e-4) the plan is almost a permutation, and moving alpha_i up and beta_sigma(i) down by the same amount
-    changes only its tiny off-permutation entries: the potentials are fixed far
-    less tightly than the cost (measured: 8.5e-7 apart with costs 1e-9 apart)."""
+    random-assignment fixture.  Near an assignment (that case at eps = eta / K
+    = 5e-4) the plan is almost a permutation sigma, and moving alpha_i up and
+    beta_sigma(i) down by the same amount changes only its tiny
+    off-permutation entries, so the dual's Hessian (the plan's entries over
+    eta) barely sees that direction and the method fixes it only loosely: the
+    oracle itself, run with other valid inner settings (CG tolerance 1e-9 or
+    1e-3, warm-up cap 5), moves the potentials by up to 2e-3 while alpha_i +
+    beta_sigma(i) and the cost stay within 2e-16.  There the check is on what
+    the plan determines: alpha_i + beta_sigma(i) to 1e-8 and the dual value
+    <a, alpha> + <b, beta> to 1e-9 relative."""
     import json
     import os
     import sys
@@ -459,9 +465,16 @@ def test_gpu_matches_stored_oracle_fixtures(ctx):
         f = ref[name]
         assert g["rc"] == 0 and g["resid"] <= 1e-10, (name, g["resid"])
         assert abs(g["cost"] - f["cost"]) <= 1e-9 * abs(f["cost"]), name
-        ptol = 1e-5 if name.startswith("assignment") else 1e-8
-        assert np.abs(g["alpha"] - np.array(f["alpha"])).max() <= ptol, name
-        assert np.abs(g["beta"] - np.array(f["beta"])).max() <= ptol, name
+        fa, fb = np.array(f["alpha"]), np.array(f["beta"])
+        if name.startswith("assignment"):
+            sig = np.argmax(fa[:, None] + fb[None, :] - C, axis=1)  # the plan's dominant entry per row
+            assert len(set(sig.tolist())) == len(sig), name  # a permutation
+            assert np.abs((g["alpha"] + g["beta"][sig]) - (fa + fb[sig])).max() <= 1e-8, name
+            dual, fdual = a @ g["alpha"] + b @ g["beta"], a @ fa + b @ fb
+            assert abs(dual - fdual) <= 1e-9 * abs(fdual), name
+        else:
+            assert np.abs(g["alpha"] - fa).max() <= 1e-8, name
+            assert np.abs(g["beta"] - fb).max() <= 1e-8, name
 
 
 def test_c3_grids_match_stored_oracle(ctx):
