@@ -24,7 +24,7 @@ constexpr int LS_T = 8;      // trial step sizes per line-search pass (after the
 constexpr int TILE_C = 256;  // columns per tile (one per thread)
 constexpr int TILE_RMAX = 16;  // maximum rows per tile
 constexpr int NBIN = 6;        // CG row bins: <= 1, 2, 4, 8, 16 and more quads
-constexpr int JDS_PQ = 16;     // one-block CG, jagged-diagonal storage: quads per row piece
+constexpr int JDS_PQ = 16;     // one-block CG, jagged-diagonal storage: quads per row piece (8, 32 measured slower)
 constexpr int WCG_NT = 256;        // wide CG: threads per block of a half-product (256/512/1024 measured)
 constexpr int WCG_ROWS = WCG_NT / 8;  // wide CG: rows of one half of M per block
 constexpr int WCG_MAX_N = 4096;  // instances with m+n above this take the wide CG

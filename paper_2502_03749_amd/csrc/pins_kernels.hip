@@ -901,6 +901,9 @@ __global__ __launch_bounds__(256) void k_scan_totals(const DevInst* __restrict__
 // Entries per thread of the one-block CG for an instance with m + n = N (the
 // kernel is launched with the largest over its batch, never fewer).
 __device__ __forceinline__ int pcg_ept(int N) { return N <= 1024 ? 1 : N <= 2048 ? 2 : 4; }
+// Size of the one-block CG's LDS array of products / piece sums for EPT
+// entries per thread (at least 1024 EPT; what the LDS leaves for EPT = 4).
+__host__ __device__ constexpr int pcg_parts(int ept) { return ept <= 2 ? 2048 * ept : 6144; }
 
 // Jagged-diagonal storage for the one-block CG (see Ctrl::jds).  Each row of a
 // half (rows of S, then rows of S^T) of nq quads is cut into nq / JDS_PQ full
@@ -911,11 +914,10 @@ __device__ __forceinline__ int pcg_ept(int N) { return N <= 1024 ? 1 : N <= 2048
 // wave, one piece each, then read consecutive quads.  Per row k, rowbin[k]
 // receives jds_info: the position of its first full piece (the full pieces
 // are consecutive) in the low 16 bits, 1 + the position of its shorter piece
-// (0: none) in the high bits.  Positions within a length are handed out by
-// atomics, so the layout may differ from run to run; each row's entries, their
-// order and every sum formed from them do not.  Returns false, writing
+// (0: none) in the high bits.  Within a length the pieces follow the row
+// order (the full pieces of a row consecutive).  Returns false, writing
 // nothing but Ctrl::jds = 0, when a half has more pieces than the CG's LDS
-// array of partial sums holds (1024 * pcg_ept(N)).
+// array of partial sums holds (pcg_parts(pcg_ept(N))).
 template <class NQ>
 __device__ bool jds_layout(const DevInst& I, Ctrl& C, int m, int N, NQ nq_of) {
     __shared__ int hist[2][JDS_PQ + 1];
@@ -948,17 +950,54 @@ __device__ bool jds_layout(const DevInst& I, Ctrl& C, int m, int N, NQ nq_of) {
         }
     }
     __syncthreads();
-    const int vmax = 1024 * pcg_ept(N);
+    const int vmax = pcg_parts(pcg_ept(N));
     if (hist[0][0] > vmax || hist[1][0] > vmax) {
         if (tid == 0) C.jds = 0;
         return false;
     }
-    for (int k = tid; k < N; k += 1024) {
-        const int nq = nq_of(k), h = k >= m;
-        const int F = nq / JDS_PQ, rem = nq - F * JDS_PQ;
-        const int fb = F ? atomicAdd(&hist[h][JDS_PQ], F) : 0;
-        const int pp = rem ? atomicAdd(&hist[h][rem], 1) : -1;
-        I.rowbin[k] = fb | ((pp + 1) << 16);
+    // positions within each length in row order (so that neighbouring lanes
+    // take neighbouring rows): per half, chunks of 1024 rows; the full pieces
+    // by a block-wide exclusive scan of their counts, the shorter piece of
+    // each length by per-wave ballots
+    __shared__ int wcnt[16][JDS_PQ + 1];  // per wave: pieces per length (full: [JDS_PQ])
+    const int w = tid >> 6, lane = tid & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int h = 0; h < 2; ++h) {
+        const int lo = h ? m : 0, hi = h ? N : m;
+        for (int c0 = lo; c0 < hi; c0 += 1024) {
+            const int k = c0 + tid;
+            const int nq = k < hi ? nq_of(k) : 0;
+            const int F = nq / JDS_PQ, rem = nq - F * JDS_PQ;
+            int incl = F;  // inclusive scan of F over the wave
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(incl, o);
+                if (lane >= o) incl += t;
+            }
+            int rank = 0;
+#pragma unroll
+            for (int L = 1; L < JDS_PQ; ++L) {
+                const unsigned long long bal = __ballot(rem == L);
+                if (rem == L) rank = (int)__popcll(bal & below);
+                if (lane == 0) wcnt[w][L] = (int)__popcll(bal);
+            }
+            if (lane == 63) wcnt[w][JDS_PQ] = incl;
+            __syncthreads();
+            int fb = hist[h][JDS_PQ] + incl - F, pp = -1;
+            for (int q = 0; q < w; ++q) fb += wcnt[q][JDS_PQ];
+            if (rem) {
+                pp = hist[h][rem] + rank;
+                for (int q = 0; q < w; ++q) pp += wcnt[q][rem];
+            }
+            if (k < hi) I.rowbin[k] = (F ? fb : 0) | ((pp + 1) << 16);
+            __syncthreads();
+            if (tid <= JDS_PQ && tid >= 1) {  // advance the cursors past this chunk
+                int t = 0;
+                for (int q = 0; q < 16; ++q) t += wcnt[q][tid];
+                hist[h][tid] += t;
+            }
+            __syncthreads();
+        }
     }
     if (tid == 0) C.jds = 1;
     return true;
@@ -1380,11 +1419,11 @@ __device__ __forceinline__ void spmv_part(const SpArrays<IX, VT>& A, int m, cons
 }
 
 // One half of M's off-diagonal product in the jagged-diagonal form (see
-// jds_layout): lane v of the block sums piece v (its quads in order, U in
-// flight) into part[v]; jd = the half's quad offsets jdp[0..JDS_PQ] in LDS.
-// The lanes of a wave take consecutive pieces of about the same length, so
-// each of its quad loads reads consecutive memory and no lane waits for a
-// cross-lane reduction.
+// jds_layout): a lane sums piece v (its quads in order, U in flight) into
+// part[v]; jd = the half's quad offsets jdp[0..JDS_PQ] in LDS.  The lanes of
+// a wave take consecutive pieces of about the same length, so each of its
+// quad loads reads consecutive memory and no lane waits for a cross-lane
+// reduction.
 // element k of an array of V, the byte offset formed in 32 bits (so that the
 // load takes the array's base from scalar registers; one-block instances' S
 // arrays are far below 4 GiB)
@@ -1454,7 +1493,7 @@ __device__ __forceinline__ void jds_half(const IX* ixa, const VT* vla, const int
         part[v] = tot;
     }
 }
-constexpr int JDS_QUADS = 4;  // quads in flight per lane in jds_half
+constexpr int JDS_QUADS = 2;  // quads in flight per lane in jds_half (2 and 4 measured alike)
 
 // kind: the CG's work class (W_CG, W_CG_ROWS or W_CG_WIDE)
 __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab, double fa, const KP& kp,
@@ -1488,7 +1527,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     // sAp, products of the current half; sdg, the diagonal (r, c); the
     // pointers and the binned row list
     __shared__ double sp[1024 * EPT];
-    __shared__ double sAp[1024 * EPT];
+    __shared__ double sAp[pcg_parts(EPT)];
     __shared__ double sdg[1024 * EPT];
     __shared__ double sh[32];
     __shared__ int sptr[1024 * EPT + 2];
@@ -1529,16 +1568,20 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     const double eta = kp.eta;
     // right-hand side eta (target - diagonal) of entry k (recomputed where needed)
     auto rhs = [&](int k) { return eta * (((k < m) ? I.a[k] : I.b[k - m]) - sdg[k]); };
-    // registers: on the rows the iterate x, residual r, direction p
-    double x[EPT], r[EPT], p[EPT];
+    // registers: on the rows the iterate x, residual r, direction p; the
+    // inverse diagonal dinv (rows: the Jacobi preconditioner D_r^-1; columns:
+    // the D_c^-1 of the reduced matrix)
+    double x[EPT], r[EPT], p[EPT], dinv[EPT];
     double bb = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
         const int k = tid + 1024 * t;
         x[t] = r[t] = p[t] = 0.0;
+        dinv[t] = 0.0;
         if (k < N) {
             const double dk = I.rc[k];
             sdg[k] = dk;
+            dinv[t] = 1.0 / dk;
             const double tg = (k < m) ? I.a[k] : I.b[k - m];
             const double bk = eta * (tg - dk);
             bb += bk * bk;
@@ -1555,7 +1598,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
         const int k = tid + 1024 * t;
         if (k < m) {
             r[t] = rhs(k) - rowval(k);
-            p[t] = r[t] / sdg[k];
+            p[t] = r[t] * dinv[t];
             sp[k] = p[t];
             rr += r[t] * r[t];
             rz += r[t] * p[t];
@@ -1565,27 +1608,36 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     // q_k = ((D_r - S D_c^-1 S^T) p)_k, read twice per iteration from the same
     // products (nothing writes sAp in between)
     auto qval = [&](int k, double pk) { return sdg[k] * pk - rowval(k); };
+    __shared__ double spq[16];  // per-wave parts of <p, q>
     int it = 0;
     if (bn > 0.0 && sqrt(rr) > kp.cg_rtol * bn) {
         while (it < kp.cg_max) {
             __syncthreads();
-            prod(1);  // S^T p
+            prod(1);  // y = S^T p
             __syncthreads();
-#pragma unroll
-            for (int t = 0; t < EPT; ++t) {
-                const int k = tid + 1024 * t;
-                if (k >= m && k < N) sp[k] = rowval(k) / sdg[k];
-            }
-            __syncthreads();
-            prod(0);  // S D_c^-1 S^T p
-            __syncthreads();
+            // D_c^-1 y on the columns, and <p, q> = <p, D_r p> - <y, D_c^-1 y>
+            // (q = (D_r - S D_c^-1 S^T) p) in per-wave parts that the barrier
+            // before the next product publishes
             double pq = 0.0;
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
-                if (k < m) pq += p[t] * qval(k, p[t]);
+                if (k < m) {
+                    pq += sdg[k] * (p[t] * p[t]);
+                } else if (k < N) {
+                    const double y = rowval(k), z = y * dinv[t];
+                    sp[k] = z;
+                    pq -= y * z;
+                }
             }
-            pq = block_sum<1024>(pq, sh);
+            pq = wave_sum(pq);
+            if ((tid & 63) == 0) spq[tid >> 6] = pq;
+            __syncthreads();
+            prod(0);  // S D_c^-1 S^T p
+            __syncthreads();
+            pq = 0.0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) pq += spq[w];
             if (!(pq > 0.0)) break;
             const double al = rz / pq;
             double rz2 = 0.0;
@@ -1597,7 +1649,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
                     x[t] += al * p[t];
                     r[t] -= al * qval(k, p[t]);
                     rr += r[t] * r[t];
-                    rz2 += r[t] * (r[t] / sdg[k]);
+                    rz2 += r[t] * (r[t] * dinv[t]);
                 }
             }
             block_sum2<1024>(rr, rz2, sh);
@@ -1609,7 +1661,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
             for (int t = 0; t < EPT; ++t) {
                 const int k = tid + 1024 * t;
                 if (k < m) {
-                    p[t] = r[t] / sdg[k] + be * p[t];
+                    p[t] = r[t] * dinv[t] + be * p[t];
                     sp[k] = p[t];
                 }
             }

@@ -561,13 +561,13 @@ def test_cg_storage_forms_against_oracle(ctx):
     """The one-block CG's two storage forms of S against the oracle: the
     jagged-diagonal form (rows cut into pieces of up to 16 quads, one lane per
     piece), and the row-contiguous form it falls back to when a half has more
-    pieces than the CG's LDS array of piece sums holds (1024 for m + n <= 1024,
-    2048 up to 2048, else 4096).  A 100x100 instance at eta = 0.01 keeps a sparse
-    set (jagged-diagonal); a 300x300 instance at eta = 0.5 with a budget of 256
-    spanning trees keeps all 90 000 entries: per half 300 rows of 75 quads, five
-    pieces each, 1500 > 1024 (row-contiguous).  Each form must have done the
+    pieces than the CG's LDS array of piece sums holds (2048 for m + n <= 1024,
+    4096 up to 2048, else 6144).  A 100x100 instance at eta = 0.01 keeps a sparse
+    set (jagged-diagonal); a 600x600 instance at eta = 0.5 with a budget of 512
+    spanning trees keeps all 360 000 entries: per half 600 rows of 150 quads,
+    ten pieces each, 6000 > 4096 (row-contiguous).  Each form must have done the
     instance's CG work."""
-    for m, eta, K, budget, cls in ((100, 0.01, 10, 64.0, "pcg"), (300, 0.5, 3, 256.0, "pcg_rows")):
+    for m, eta, K, budget, cls in ((100, 0.01, 10, 64.0, "pcg"), (600, 0.5, 3, 512.0, "pcg_rows")):
         print("case cg storage %s m=n=%d" % (cls, m), flush=True)
         C, a, b = _rand(m, m, 4242 + m)
         g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), P.params(eta=eta, max_outer=K, budget=budget))
