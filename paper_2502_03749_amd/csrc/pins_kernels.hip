@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
         const double* __restrict__ G = I.G;
         double mx = -INFINITY;
         T sm = T(0);
-        constexpr int U = 4;
+        constexpr int U = 8;  // columns per lane in flight (8: 0.61 of 8 TB/s in FP64 on a dense cost, 4: 0.60)
         // chunks of 64 U columns: the full ones without bounds tests (so that
         // their U loads of C and G are issued together), then the last partial
         // one; the same operations in the same order either way
