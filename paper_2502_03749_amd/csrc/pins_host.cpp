@@ -354,6 +354,7 @@ DevInst build_inst(const InstPlan& L, const pins_problem& P, char* base, bool ho
 void fill_launch(LaunchCtx& L, const DevInst* hI, int count, const pins_params& p) {
     L.sp_f32 = p.precision == PINS_MIXED_FAST ? 1 : 0;
     L.any_small = L.any_wide16 = L.any_wide32 = false;
+    L.any_tiny = L.any_big = L.any_rows_form = false;
     L.max_mn_small = 0;
     L.max_m = L.max_n = L.max_mn = L.max_tiles = 0;
     for (int q = 0; q < count; ++q) {
@@ -366,6 +367,12 @@ void fill_launch(LaunchCtx& L, const DevInst* hI, int count, const pins_params& 
         if (!(f & 1)) {
             L.any_small = true;
             L.max_mn_small = std::max(L.max_mn_small, I.m + I.n);
+            if (I.m + I.n <= PCG_SMALL_N)
+                L.any_tiny = true;
+            else
+                L.any_big = true;
+            const long pieces = (long)I.nnz_cap / (4 * JDS_PQ) + std::max(I.m, I.n) + 1;
+            if (pieces > pcg_parts(pcg_ept(I.m + I.n))) L.any_rows_form = true;
         } else if (f & 2) {
             L.any_wide16 = true;
         } else {
@@ -492,11 +499,13 @@ struct OuterRunner {
             // sparsified products: the one-block CG for the instances with m + n <=
             // WCG_MAX_N and the wide CG for the others (the choice is each
             // instance's own); matrix-free products: the wide CG for every instance
-            // (the storage form of each instance's S is chosen on the device: both
-            // forms' kernels are launched, each returning at once for the others)
+            // (the storage form of each instance's S is chosen on the device: the
+            // row-contiguous form's kernel is launched when some instance's S could
+            // need it (LaunchCtx::any_rows_form), each kernel returning at once for
+            // the instances stored the other way)
             if (!mf_ && L.any_small) {
                 run_k(PINS_K_PCG, [&] { launch_pcg(L, true); });
-                run_k(PINS_K_PCG_ROWS, [&] { launch_pcg(L, false); });
+                if (L.any_rows_form) run_k(PINS_K_PCG_ROWS, [&] { launch_pcg(L, false); });
             }
             if (mf_ || L.any_wide16 || L.any_wide32) {
                 // wide or matrix-free CG: iterations in chunks between readbacks of cg_on

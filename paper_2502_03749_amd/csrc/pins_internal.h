@@ -28,6 +28,19 @@ constexpr int JDS_PQ = 16;     // one-block CG, jagged-diagonal storage: quads p
 constexpr int WCG_NT = 256;        // wide CG: threads per block of a half-product (256/512/1024 measured)
 constexpr int WCG_ROWS = WCG_NT / 8;  // wide CG: rows of one half of M per block
 constexpr int WCG_MAX_N = 4096;  // instances with m+n above this take the wide CG
+constexpr int PCG_SMALL_N = 256;  // one-block CG: instances with m+n up to this use 256-thread blocks
+
+// Entries per thread of the one-block CG for an instance with m + n = N (the
+// kernel is launched with the largest over its batch, never fewer).
+__host__ __device__ constexpr int pcg_ept(int N) { return N <= 1024 ? 1 : N <= 2048 ? 2 : 4; }
+// Threads of the one-block CG's block for an instance with m + n = N: 256 up
+// to PCG_SMALL_N entries (four waves: cheaper barriers and reductions for the
+// small instances, whose iterations are latency-bound), else 1024.  A function
+// of N alone, so an instance takes the same block alone and in any batch.
+__host__ __device__ constexpr int pcg_threads(int N) { return N <= PCG_SMALL_N ? 256 : 1024; }
+// Size of the one-block CG's LDS array of products / piece sums for EPT
+// entries per thread (at least 1024 EPT; what the LDS leaves for EPT = 4).
+__host__ __device__ constexpr int pcg_parts(int ept) { return ept <= 2 ? 2048 * ept : 6144; }
 constexpr int WCG_VROWS = 1024;  // wide CG: rows per block of the vector steps
 
 enum Phase : int { PH_DONE = 0, PH_WARM = 1, PH_NEWTON = 2, PH_FALLBACK = 3 };

@@ -264,6 +264,29 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
     b = tb;
 }
 
+// Two sums over a block when no thread can still be reading sh (the caller's
+// earlier barriers order the previous readers): one barrier instead of two.
+template <int NT>
+__device__ __forceinline__ void block_sum2_nolead(double& a, double& b, double* sh) {
+    constexpr int NW = NT / 64;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        sh[w] = a;
+        sh[NW + w] = b;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        ta += sh[k];
+        tb += sh[NW + k];
+    }
+    a = ta;
+    b = tb;
+}
+
 // Sum of p[0..len) by a block of NT threads in a fixed order.
 template <int NT>
 __device__ __forceinline__ double block_sum_array(const double* p, int len, double* sh) {
@@ -898,12 +921,6 @@ __global__ __launch_bounds__(256) void k_scan_totals(const DevInst* __restrict__
                           : prefix_in_place(I.cntc + (k - m), n, I.nrb);
 }
 
-// Entries per thread of the one-block CG for an instance with m + n = N (the
-// kernel is launched with the largest over its batch, never fewer).
-__device__ __forceinline__ int pcg_ept(int N) { return N <= 1024 ? 1 : N <= 2048 ? 2 : 4; }
-// Size of the one-block CG's LDS array of products / piece sums for EPT
-// entries per thread (at least 1024 EPT; what the LDS leaves for EPT = 4).
-__host__ __device__ constexpr int pcg_parts(int ept) { return ept <= 2 ? 2048 * ept : 6144; }
 
 // Jagged-diagonal storage for the one-block CG (see Ctrl::jds).  Each row of a
 // half (rows of S, then rows of S^T) of nq quads is cut into nq / JDS_PQ full
@@ -1405,17 +1422,17 @@ constexpr int cg_lanes(int quads) { return (quads >> CG_LANE_SHIFT) > 1 ? (quads
 // of S^T (out[m + j] = (S^T u)_j, u = pv[0..m)).  Bin t holds rows of up to
 // 2^t quads (the last bin: more); each row gets cg_lanes(2^t) lanes, so that
 // a lane takes a few quads of its row.
-template <class IX, class VT>
+template <int NT, class IX, class VT>
 __device__ __forceinline__ void spmv_part(const SpArrays<IX, VT>& A, int m, const int* bins, const int* bo,
                                           const int* rp, const int* cp, const double* __restrict__ pv,
                                           double* __restrict__ out) {
     auto fin = [out](int k, double v) { out[k] = v; };
-    spmv_bin<1, CG_QUADS, 1024, IX, VT>(A, m, bins, bo[0], bo[1], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(2), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[1], bo[2], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(4), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[2], bo[3], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(8), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[3], bo[4], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(16), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[4], bo[5], rp, cp, pv, fin);
-    spmv_bin<cg_lanes(32), CG_QUADS, 1024, IX, VT>(A, m, bins, bo[5], bo[6], rp, cp, pv, fin);
+    spmv_bin<1, CG_QUADS, NT, IX, VT>(A, m, bins, bo[0], bo[1], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(2), CG_QUADS, NT, IX, VT>(A, m, bins, bo[1], bo[2], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(4), CG_QUADS, NT, IX, VT>(A, m, bins, bo[2], bo[3], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(8), CG_QUADS, NT, IX, VT>(A, m, bins, bo[3], bo[4], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(16), CG_QUADS, NT, IX, VT>(A, m, bins, bo[4], bo[5], rp, cp, pv, fin);
+    spmv_bin<cg_lanes(32), CG_QUADS, NT, IX, VT>(A, m, bins, bo[5], bo[6], rp, cp, pv, fin);
 }
 
 // One half of M's off-diagonal product in the jagged-diagonal form (see
@@ -1432,7 +1449,7 @@ __device__ __forceinline__ V ld32(const V* base, int k) {
     return ldg(reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + (unsigned)k * (unsigned)sizeof(V)));
 }
 
-template <int U, class IX, class VT>
+template <int U, int NT, class IX, class VT>
 __device__ __forceinline__ void jds_half(const IX* ixa, const VT* vla, const int* jd, const double* __restrict__ pv,
                                          double* __restrict__ part) {
     typedef typename QuadIx<IX>::T XV;
@@ -1440,14 +1457,15 @@ __device__ __forceinline__ void jds_half(const IX* ixa, const VT* vla, const int
     const XV* ix = reinterpret_cast<const XV*>(ixa);
     const WV* vl = reinterpret_cast<const WV*>(vla);
     const int V = jd[1];  // every piece has at least one quad
-    for (int v = threadIdx.x; v < V; v += 1024) {
+    for (int v = threadIdx.x; v < V; v += NT) {
         double s[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) s[u] = 0.0;
         int q = 0;
-        // quads q .. q+U-1 exist while the piece is longer than q+U-1 (not
-        // unrolled: U quads in flight per lane, not all of the piece's)
-#pragma unroll 1
+        // quads q .. q+U-1 exist while the piece is longer than q+U-1
+        // (unrolled twice: 2U quads' loads in flight per lane; fully unrolled,
+        // every quad of the piece would be, and the registers spill)
+#pragma unroll 2
         for (; q + U <= JDS_PQ && v < jd[q + U] - jd[q + U - 1]; q += U) {
             XV x[U];
             WV w[U];
@@ -1516,29 +1534,30 @@ __device__ __forceinline__ void ls_setup(Ctrl& S, int it, double gd, double dab,
     }
 }
 
-template <int EPT, class IX, class VT, bool JDS>
-__global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
+template <int NT, int EPT, class IX, class VT, bool JDS>
+__global__ __launch_bounds__(NT) void k_pcg_lds(const DevInst* __restrict__ insts, Ctrl* __restrict__ ctrl, KP kp) {
     const int b = blockIdx.x;
     // wide instances take the wide CG; the instances stored the other way the other instantiation
     if (ctrl[b].phase != PH_NEWTON || (insts[b].cgfmt & 1) || ctrl[b].jds != (JDS ? 1 : 0)) return;
     const DevInst& I = insts[b];
     const int m = I.m, n = I.n, N = m + n;
+    if (pcg_threads(N) != NT) return;  // the block size is the instance's own (pcg_threads)
     // LDS: sp, the direction p on the rows and D_c^-1 S^T p on the columns;
     // sAp, products of the current half; sdg, the diagonal (r, c); the
     // pointers and the binned row list
-    __shared__ double sp[1024 * EPT];
+    __shared__ double sp[NT * EPT];
     __shared__ double sAp[pcg_parts(EPT)];
-    __shared__ double sdg[1024 * EPT];
+    __shared__ double sdg[NT * EPT];
     __shared__ double sh[32];
-    __shared__ int sptr[1024 * EPT + 2];
-    __shared__ int sbin[1024 * EPT];
+    __shared__ int sptr[NT * EPT + 2];
+    __shared__ int sbin[NT * EPT];
     __shared__ int sbo[2 * NBIN + 1];
     __shared__ int sjd[2][JDS_PQ + 1];
     const int tid = threadIdx.x;
     const SpArrays<IX, VT> A(I);
-    for (int k = tid; k <= m; k += 1024) sptr[k] = I.rowptr[k];
-    for (int k = tid; k <= n; k += 1024) sptr[m + 1 + k] = I.colptr[k];
-    for (int k = tid; k < N; k += 1024) sbin[k] = I.rowbin[k];  // row list, or jds_info per row
+    for (int k = tid; k <= m; k += NT) sptr[k] = I.rowptr[k];
+    for (int k = tid; k <= n; k += NT) sptr[m + 1 + k] = I.colptr[k];
+    for (int k = tid; k < N; k += NT) sbin[k] = I.rowbin[k];  // row list, or jds_info per row
     const int* rp = sptr;
     const int* cp = sptr + m + 1;
     const int* bins = sbin;
@@ -1548,11 +1567,11 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     // form, (M p)_k into sAp[k]; jagged-diagonal form, piece sums into sAp
     auto prod = [&](int h) {
         if constexpr (!JDS)
-            spmv_part<IX, VT>(A, m, bins, sbo + h * NBIN, rp, cp, sp, sAp);
+            spmv_part<NT, IX, VT>(A, m, bins, sbo + h * NBIN, rp, cp, sp, sAp);
         else if (h == 0)
-            jds_half<JDS_QUADS, IX, VT>(A.col, A.val, sjd[0], sp, sAp);
+            jds_half<JDS_QUADS, NT, IX, VT>(A.col, A.val, sjd[0], sp, sAp);
         else
-            jds_half<JDS_QUADS, IX, VT>(A.rowT, A.valT, sjd[1], sp, sAp);
+            jds_half<JDS_QUADS, NT, IX, VT>(A.rowT, A.valT, sjd[1], sp, sAp);
     };
     // (M p)_k after prod (and a barrier): the sum of row k's pieces in order
     auto rowval = [&](int k) -> double {
@@ -1575,7 +1594,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     double bb = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
-        const int k = tid + 1024 * t;
+        const int k = tid + NT * t;
         x[t] = r[t] = p[t] = 0.0;
         dinv[t] = 0.0;
         if (k < N) {
@@ -1588,14 +1607,14 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
             if (k >= m) sp[k] = bk / dk;  // D_c^-1 b_2
         }
     }
-    bb = block_sum<1024>(bb, sh);  // also orders the LDS writes above
+    bb = block_sum<NT>(bb, sh);  // also orders the LDS writes above
     const double bn = sqrt(bb);
     prod(0);  // S D_c^-1 b_2 on the rows
     __syncthreads();
     double rr = 0.0, rz = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
-        const int k = tid + 1024 * t;
+        const int k = tid + NT * t;
         if (k < m) {
             r[t] = rhs(k) - rowval(k);
             p[t] = r[t] * dinv[t];
@@ -1604,11 +1623,12 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
             rz += r[t] * p[t];
         }
     }
-    block_sum2<1024>(rr, rz, sh);
+    block_sum2<NT>(rr, rz, sh);
     // q_k = ((D_r - S D_c^-1 S^T) p)_k, read twice per iteration from the same
     // products (nothing writes sAp in between)
     auto qval = [&](int k, double pk) { return sdg[k] * pk - rowval(k); };
-    __shared__ double spq[16];  // per-wave parts of <p, q>
+    constexpr int NW = NT / 64;
+    __shared__ double spq[NW];  // per-wave parts of <p, q>
     int it = 0;
     if (bn > 0.0 && sqrt(rr) > kp.cg_rtol * bn) {
         while (it < kp.cg_max) {
@@ -1621,7 +1641,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
             double pq = 0.0;
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
-                const int k = tid + 1024 * t;
+                const int k = tid + NT * t;
                 if (k < m) {
                     pq += sdg[k] * (p[t] * p[t]);
                 } else if (k < N) {
@@ -1637,14 +1657,14 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
             __syncthreads();
             pq = 0.0;
 #pragma unroll
-            for (int w = 0; w < 16; ++w) pq += spq[w];
+            for (int w = 0; w < NW; ++w) pq += spq[w];
             if (!(pq > 0.0)) break;
             const double al = rz / pq;
             double rz2 = 0.0;
             rr = 0.0;
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
-                const int k = tid + 1024 * t;
+                const int k = tid + NT * t;
                 if (k < m) {
                     x[t] += al * p[t];
                     r[t] -= al * qval(k, p[t]);
@@ -1652,14 +1672,14 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
                     rz2 += r[t] * (r[t] * dinv[t]);
                 }
             }
-            block_sum2<1024>(rr, rz2, sh);
+            block_sum2_nolead<NT>(rr, rz2, sh);  // sh's last readers are several barriers back
             ++it;
             if (sqrt(rr) <= kp.cg_rtol * bn) break;
             const double be = rz2 / rz;
             rz = rz2;
 #pragma unroll
             for (int t = 0; t < EPT; ++t) {
-                const int k = tid + 1024 * t;
+                const int k = tid + NT * t;
                 if (k < m) {
                     p[t] = r[t] * dinv[t] + be * p[t];
                     sp[k] = p[t];
@@ -1671,7 +1691,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
-        const int k = tid + 1024 * t;
+        const int k = tid + NT * t;
         if (k < m) sp[k] = x[t];
     }
     __syncthreads();
@@ -1680,7 +1700,7 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
     double gd = 0.0, dab = 0.0, fa = 0.0;
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
-        const int k = tid + 1024 * t;
+        const int k = tid + NT * t;
         if (k < N) {
             if (k >= m) x[t] = (rhs(k) - rowval(k)) / sdg[k];
             const double tg = (k < m) ? I.a[k] : I.b[k - m];
@@ -1690,9 +1710,9 @@ __global__ __launch_bounds__(1024) void k_pcg_lds(const DevInst* __restrict__ in
             fa += fabs(tg * x[t]);
         }
     }
-    gd = block_sum<1024>(gd, sh);
-    dab = block_sum<1024>(dab, sh);
-    fa = block_sum<1024>(fa, sh);
+    gd = block_sum<NT>(gd, sh);
+    dab = block_sum<NT>(dab, sh);
+    fa = block_sum<NT>(fa, sh);
     if (tid == 0) ls_setup(ctrl[b], it, gd, dab, fa, kp, JDS ? W_CG : W_CG_ROWS);
 }
 
@@ -2728,14 +2748,18 @@ void launch_sparsify(const LaunchCtx& L, int src) {
 static_assert(WCG_MAX_N <= 4 * 1024, "k_pcg_lds holds at most 4096 vector entries");
 template <class IX, class VT, bool JDS>
 static void launch_pcg_t(const LaunchCtx& L) {
+    const dim3 g(L.count);
+    // instances with m + n <= PCG_SMALL_N: 256-thread blocks, one entry per thread
+    if (L.any_tiny) hipLaunchKernelGGL((k_pcg_lds<256, 1, IX, VT, JDS>), g, dim3(256), 0, L.stream, L.insts, L.ctrl, L.kp);
+    if (!L.any_big) return;
     const int ept = (L.max_mn_small + 1023) / 1024;
-    const dim3 g(L.count), blk(1024);
+    const dim3 blk(1024);
     if (ept <= 1)
-        hipLaunchKernelGGL((k_pcg_lds<1, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<1024, 1, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else if (ept <= 2)
-        hipLaunchKernelGGL((k_pcg_lds<2, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<1024, 2, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
     else
-        hipLaunchKernelGGL((k_pcg_lds<4, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+        hipLaunchKernelGGL((k_pcg_lds<1024, 4, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
 }
 
 template <class IX, class VT>

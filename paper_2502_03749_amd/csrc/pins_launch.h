@@ -21,9 +21,16 @@ struct LaunchCtx {
     int sp_f32;                // values of S stored in float (fast-mixed precision), else double
     // CG kinds present in the batch (per instance by DevInst::cgfmt): the
     // one-block CG, the wide CG with uint16 / int32 indices; the largest m+n
-    // among the one-block instances
+    // among the one-block instances; one-block instances with m+n up to
+    // PCG_SMALL_N (256-thread blocks) and above it (1024-thread blocks)
     bool any_small, any_wide16, any_wide32;
     int max_mn_small;
+    bool any_tiny, any_big;
+    // some one-block instance whose S may have more row pieces in a half than
+    // the CG's LDS holds (the row-contiguous CG form must then be launched):
+    // a half holds at most cap/64 + max(m, n) pieces (cap/4 quads in pieces of
+    // up to 16 plus one shorter piece per row)
+    bool any_rows_form;
 };
 
 void launch_row_lse(const LaunchCtx& L, int src, bool f32, int mask);
