@@ -136,6 +136,10 @@ def parse():
     ap.add_argument("--pcg-only", action="store_true",
                     help="only run the single-instance CG measurement (pair 0 alone, sparsified Hessian products "
                          "throughout, events around the one-block CG launches)")
+    ap.add_argument("--hw-queues", type=int, default=8, metavar="Q",
+                    help="hardware queues of the HIP runtime for this process (GPU_MAX_HW_QUEUES, read when the "
+                         "runtime starts; its default is 4): every stream takes one, and four lanes plus the "
+                         "caller's and the null stream need more than four; 0 leaves the environment as it is")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference kernel that scales "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
@@ -165,6 +169,8 @@ def main():
               "this library has no multi-GPU path (see the design notes for how it would shard); "
               "run with --gpus 1.", file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)  # before the HIP runtime starts (torch import)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
@@ -248,7 +254,7 @@ def main():
     lanes, autotune, tiles, graphs = args.lanes, None, [0, 0, 0, 0], 0
     if lanes <= 0:
         # on the caller's stream, like the timed steps: every stream of the process
-        # takes one of its hardware queues (four here), so no extra stream is
+        # takes one of its hardware queues (--hw-queues), so no extra stream is
         # added (graph replay runs on the lanes' own streams when there are two or more)
         best, trials = ctx.tune_batch_device(probs, P.params(eta=args.eta, max_outer=args.K, precision=prec, **hess),
                                              outs, max_lanes=4, reps=2, stream=st)
@@ -318,6 +324,7 @@ def main():
                                      "streamed, eta=0.1, K=250, batched (one call per step)",
                             pairs=args.pairs, m=n, n=n, eta=args.eta, K=args.K, precision=args.precision,
                             mode="batched", lanes=lanes, tile_rows=tiles,
+                            hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "runtime default"),
                             hessian=("matrix-free full Hessian for outer iterations k < %d, sparsified (CSR) after"
                                      % args.hvp_switch) if args.hvp_switch > 0 else "sparsified (CSR)"),
                 roofline=roofline, autotune=autotune)
@@ -622,6 +629,7 @@ def other_configs(P, W, torch, np, ctx, dev):
     out["uneven"] = dict(workload="256 point clouds, m, n log-uniform in [64, 2048], d in {2, 8, 32}, Dirichlet(1) "
                                   "marginals, eta = 1e-2, K = %d, mixed precision, one batched call (one lane)" % Kc,
                          solves_per_s=256 / dt, ms=round(1e3 * dt, 1), statuses=sorted({r["status"] for r in rs}),
+                         newton_cap_reached=sum(r["status"] == 1 for r in rs),  # PINS_NOT_CONVERGED
                          max_resid=max(r["resid"] for r in rs), rel_error_vs_lp_smallest=err)
     return out
 

@@ -102,7 +102,8 @@ typedef struct {
     int32_t shift_mode;   /* pins_shift_mode */
     int32_t profile;      /* nonzero: time every kernel launch with HIP events (pins_result.kern_*) */
     int32_t streams;      /* batch entry point: number of concurrent lanes (own HIP stream and host
-                             thread each, instances split into contiguous groups, at most 4);
+                             thread each, instances split into contiguous groups, at most
+                             PINS_MAX_LANES);
                              0 or 1 = one lane on the caller's stream; results do not depend on it */
     int32_t profile_mask; /* with profile: bit k set = time the launches of kernel class k
                              (PINS_K_*); 0 = every class.  Fewer timed classes, less overhead */
@@ -144,6 +145,7 @@ typedef struct {
 } pins_problem;
 
 #define PINS_NKERN 16
+#define PINS_MAX_LANES 8 /* most concurrent lanes of one batch call (params.streams) */
 
 /* Results.  alpha/beta/X point to caller-owned arrays (host for pins_solve,
  * device for the *_device entry points); X may be NULL (not written).
@@ -294,7 +296,7 @@ int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count,
  * replay (params.graphs), which leave every result bitwise unchanged, and the
  * rows per tile of the dense passes (params.tile_rows), which changes the
  * summation order but keeps each result a function of its own instance.  The
- * search is greedy: lane counts 1 .. max_lanes (at most 4, at most `count`)
+ * search is greedy: lane counts 1 .. max_lanes (at most PINS_MAX_LANES and `count`)
  * with graphs off and 16-row tiles; then graphs on at the best count; then,
  * for each size class of m present in the batch, 4 and 8 rows per tile.  Each
  * configuration is solved once untimed (workspace set-up) and then `reps`
@@ -304,7 +306,7 @@ int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count,
  * up to max_trials of the tried configurations in order, *ntrials (when
  * non-NULL) their number.  The outputs in res (DEVICE arrays, as for
  * pins_solve_batch_device) are those of the last solve.  Returns the batch's
- * worst status; PINS_EINVAL for max_lanes outside [1, 4], reps < 1 or a NULL
+ * worst status; PINS_EINVAL for max_lanes outside [1, PINS_MAX_LANES], reps < 1 or a NULL
  * best. */
 typedef struct {
     int32_t streams, graphs;

@@ -913,7 +913,7 @@ void free_lane(Lane* L) {
 int lane_count(const pins_params& p, int count, bool host_api) {
     if (host_api || count < 2) return 1;
     int g = p.streams > 1 ? p.streams : 1;
-    g = std::max(1, std::min({g, 4, count}));
+    g = std::max(1, std::min({g, PINS_MAX_LANES, count}));
     return g;
 }
 
@@ -1571,7 +1571,7 @@ int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, 
                            pins_tune_trial* trials, int max_trials, int32_t* ntrials) {
     return guarded(ctx, [&] {
         if (!probs || !p || !res || !best) fail(PINS_EINVAL, "null argument");
-        if (max_lanes < 1 || max_lanes > 4) fail(PINS_EINVAL, "max_lanes must be in [1, 4]");
+        if (max_lanes < 1 || max_lanes > PINS_MAX_LANES) fail(PINS_EINVAL, "max_lanes must be in [1, PINS_MAX_LANES]");
         if (reps < 1) fail(PINS_EINVAL, "reps must be >= 1");
         if (count < 1) fail(PINS_EINVAL, "count must be >= 1");
         check_params(*p);

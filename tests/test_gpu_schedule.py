@@ -115,7 +115,7 @@ def test_tuner_rejects_bad_arguments(ctx):
     print("case tuner bad arguments", flush=True)
     probs, outs = _batch()
     prm = P.params(eta=0.03, max_outer=2)
-    for kw in (dict(max_lanes=0), dict(max_lanes=5), dict(reps=0)):
+    for kw in (dict(max_lanes=0), dict(max_lanes=9), dict(reps=0)):
         with pytest.raises(P.PinsError) as e:
             ctx.tune_batch_device(probs[:2], prm, outs[:2], **kw)
         assert e.value.code == P._binding.PINS_EINVAL
