@@ -87,6 +87,29 @@ def test_tuner_picks_a_schedule_and_tiles_and_keeps_results(ctx):
         assert torch.equal(o1["alpha"], o3[q]["alpha"]) and r1["cost"] == got[q]["cost"], q
 
 
+@pytest.mark.parametrize("lanes", [6, 8, 12])
+def test_many_lanes_equal_one_lane(ctx, lanes):
+    """Up to PINS_MAX_LANES (8) lanes, here more than the process's hardware
+    queues, so that lane streams share them; a request above the cap runs on 8
+    lanes.  Every instance bitwise its one-lane result (8 uneven dense
+    instances: with 6 lanes two groups hold two instances, with 8 or more each
+    lane one)."""
+    print("case lanes %d" % lanes, flush=True)
+    probs, outs = _batch()
+    st = torch.cuda.Stream()
+    rc, _ = ctx.solve_batch_device(probs, P.params(eta=0.03, max_outer=6, streams=1), outs, stream=st.cuda_stream)
+    st.synchronize()
+    assert rc == 0
+    want = _host(outs)
+    o2 = [dict(alpha=torch.empty_like(o["alpha"]), beta=torch.empty_like(o["beta"])) for o in outs]
+    rc, got = ctx.solve_batch_device(probs, P.params(eta=0.03, max_outer=6, streams=lanes), o2, stream=st.cuda_stream)
+    st.synchronize()
+    assert rc == 0
+    assert max(r["group"] for r in got) == min(lanes, 8) - 1
+    for (a1, b1), (a2, b2) in zip(want, _host(o2)):
+        assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
 @pytest.mark.parametrize("rows", [1, 3, 8])
 def test_tile_rows_parity(ctx, rows):
     """Dense passes with 1, 3 and 8 rows per tile (every size class): parity
