@@ -539,6 +539,34 @@ def test_one_newton_step_parity(ctx, case, t2, budget):
     assert np.abs(g["beta"] - o["beta"]).max() <= 1e-9
 
 
+def test_sparsify_at_the_papers_retained_fraction(ctx):
+    """The numerical appendix's own Sparsify setting: at most (3n - 1)/(2n^2) of
+    the n x n coupling block kept, i.e. a budget of (3n - 1)/2 entries, which in
+    units of m + n - 1 is (3n - 1)/(2(2n - 1)) (about 0.75).  On a 40 x 40 dense
+    instance at eta = 0.05, K = 8 the kept sets are then so small that every
+    subproblem ends at the Newton cap on both sides (391 Newton steps against 19
+    with the default budget of 64 spanning trees, the reason for that default).
+    The GPU must still follow the oracle step for step: the same status, Newton
+    and fallback counts, the same kept count in the last Newton step (within the
+    budget), and cost and potentials at parity."""
+    print("case sparsify paper fraction", flush=True)
+    n = 40
+    C, a, b = _rand(n, n, 11)
+    eta, K = 0.05, 8
+    budget = (3 * n - 1) / (2 * (2 * n - 1))
+    g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b), P.params(eta=eta, max_outer=K, budget=budget))
+    o = oracle.pins(C, a, b, eta=eta, K=K, budget=budget)
+    assert g["rc"] == o["status"] == 1, (g["rc"], o["status"])
+    assert g["newton_iters"] == o["newton"], (g["newton_iters"], o["newton"])
+    assert g["fallbacks"] == o["fallbacks"], (g["fallbacks"], o["fallbacks"])
+    assert g["nnz_last"] == o["nnz_last"] <= (3 * n - 1) // 2, (g["nnz_last"], o["nnz_last"])
+    assert abs(g["cost"] - o["cost"]) <= 1e-9 * o["cost"], (g["cost"], o["cost"])
+    # the last subproblem is far from its tolerance too (residual about 4e-4), the same on both sides
+    assert abs(g["resid"] - o["resid"]) <= 1e-8 * o["resid"], (g["resid"], o["resid"])
+    assert np.abs(g["alpha"] - o["alpha"]).max() <= 1e-8
+    assert np.abs(g["beta"] - o["beta"]).max() <= 1e-8
+
+
 def test_sparsify_no_level_within_budget(ctx):
     """One Sparsify level (rho = 1e-3) and a budget of three spanning trees
     (3 (m + n - 1) entries): whenever the level keeps more, no entry is kept and
