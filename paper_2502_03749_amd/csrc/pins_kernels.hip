@@ -1201,6 +1201,12 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
         cnq = (I.colptr[j + 1] - cstart) >> 2;
         if (jds) cinfo = I.rowbin[m + j];
     }
+    // the column's facts for the write phase, where any lane of the wave may
+    // write an entry of this column
+    __shared__ int sCs[TILE_C], sCn[TILE_C], sCi[TILE_C];
+    sCs[threadIdx.x] = cstart;
+    sCn[threadIdx.x] = cnq;
+    sCi[threadIdx.x] = cinfo;
     double xr[TILE_RMAX];
     unsigned keepm = 0;
     const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
@@ -1223,28 +1229,56 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     }
     __syncthreads();
     const unsigned long long below = (1ull << lane) - 1ull;
+    // Writes, KCH rows at a time: each wave first lists its kept entries of
+    // those rows in LDS (row by row, in lane order within a row), then writes
+    // them with every lane taking one listed entry, so that no lane idles
+    // while the few kept lanes of a row write theirs.  The value, CSR entry
+    // index e and CSC entry index (the column's running count) of each entry
+    // are those an entry-by-entry pass gives, so every slot receives the same
+    // value.
+    constexpr int KCH = 4;
+    __shared__ double kX[4][KCH * 64];
+    __shared__ int kRL[4][KCH * 64], kE[4][KCH * 64], kCe[4][KCH * 64];
 #pragma unroll
-    for (int r = 0; r < TILE_RMAX; ++r) {
-        const bool keep = (keepm >> r) & 1u;
-        const unsigned long long bal = __ballot(keep);
-        if (keep) {
-            int woff = 0;
-            for (int q = 0; q < w; ++q) woff += wc[r][q];
-            const int e = sE0[r] + woff + (int)__popcll(bal & below);
-            const VT v = (VT)texp(xr[r], sT);
-            const int nq = sNq[r];
+    for (int c0 = 0; c0 < TILE_RMAX; c0 += KCH) {
+        int cnt = 0;  // listed entries of the wave (uniform over it)
+#pragma unroll
+        for (int u = 0; u < KCH; ++u) {
+            const int r = c0 + u;
+            const bool keep = (keepm >> r) & 1u;
+            const unsigned long long bal = __ballot(keep);
+            if (keep) {
+                int woff = 0;
+                for (int q = 0; q < w; ++q) woff += wc[r][q];
+                const int rank = (int)__popcll(bal & below);
+                const int pos = cnt + rank;
+                kX[w][pos] = xr[r];
+                kRL[w][pos] = (lane << 8) | r;
+                kE[w][pos] = sE0[r] + woff + rank;
+                kCe[w][pos] = ce;
+                ++ce;
+            }
+            cnt += (int)__popcll(bal);
+        }
+        __syncthreads();
+        for (int it = lane; it < cnt; it += 64) {
+            const int rl = kRL[w][it];
+            const int r = rl & 0xff, t = w * 64 + (rl >> 8);  // row in the tile, thread of the column
+            const VT v = (VT)texp(kX[w][it], sT);
+            const int e = kE[w][it], nq = sNq[r];
             if (e < 4 * nq) {
                 const int slot = slot_of(sJd[0], sStart[r], nq, sInfo[r], e);
-                put(I.col, slot, j, m);
+                put(I.col, slot, cb * TILE_C + t, m);
                 static_cast<VT*>(I.val)[slot] = v;
             }
-            if (ce < 4 * cnq) {
-                const int slot = slot_of(sJd[1], cstart, cnq, cinfo, ce);
+            const int cev = kCe[w][it], cq = sCn[t];
+            if (cev < 4 * cq) {
+                const int slot = slot_of(sJd[1], sCs[t], cq, sCi[t], cev);
                 put(I.rowT, slot, i0 + r, 0);
                 static_cast<VT*>(I.valT)[slot] = v;
             }
-            ++ce;
         }
+        __syncthreads();  // the lists are rewritten for the next rows
     }
     // pads (index 0, value 0) up to a whole number of quads: rows of S in the
     // last column block, columns of S^T in the last row block
