@@ -15,7 +15,7 @@ by the full Hessian (matrix-free) in the first 15 outer iterations, while the
 plans are diffuse, and by the sparsified Hessian (CSR/CSC) after
 (--hvp-switch).  The number of concurrent lanes and the rows per tile of the dense
 passes are picked on the batch by the library's autotuner before the warm-up
-(--lanes fixes the lanes and keeps 16-row tiles instead).
+(--lanes fixes the lanes, and --tile-rows the rows per tile, 16 by default, instead).
 
 The JSON line also carries:
   autotune     -- every configuration the tuner tried (lanes, graph replay,
@@ -110,6 +110,9 @@ def parse():
     ap.add_argument("--lanes", type=int, default=0,
                     help="concurrent lanes of the batched call (params.streams); results do not depend on it. "
                          "0 = the library's autotuner (pins_tune_batch_device) picks it on this batch, untimed")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="with --lanes: rows per tile of the dense passes for every size class (params.tile_rows; "
+                         "0 = the library default, 16)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the materialised-cost Sinkhorn sweep measurement (16384 x 16384 FP64 cost)")
     ap.add_argument("--sweep-only", action="store_true", help="only run the sweep measurements (materialised and streamed cost)")
@@ -251,7 +254,7 @@ def main():
         return kms, kwork, kcalls
 
     hess = dict(hvp=2, hvp_switch=args.hvp_switch) if args.hvp_switch > 0 else dict(hvp=0)
-    lanes, autotune, tiles, graphs = args.lanes, None, [0, 0, 0, 0], 0
+    lanes, autotune, tiles, graphs = args.lanes, None, [args.tile_rows] * 4, 0
     if lanes <= 0:
         # on the caller's stream, like the timed steps: every stream of the process
         # takes one of its hardware queues (--hw-queues), so no extra stream is
@@ -262,7 +265,7 @@ def main():
         lanes, tiles, graphs = best.streams, list(best.tile_rows), best.graphs
         autotune = dict(lanes=lanes, graphs=graphs, tile_rows=tiles, reps=2,
                         trials=[dict(t, ms=round(t["ms"], 1)) for t in trials],
-                        searched="lanes 1..4 and graph replay (launch schedule; results unchanged), then 4 / 8 "
+                        searched="lanes 1..4 and graph replay (launch schedule; results unchanged), then 8 / 32 / 64 "
                                  "rows per tile per size class present (0 = 16)")
     base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=lanes, tile_rows=tiles, **hess)
     share_ms, _, _ = aggregate([step(P.params(profile=1, **base))])

@@ -99,10 +99,10 @@ struct InstPlan {
 // [256, 1024), [1024, ...).
 int size_class(int m) { return m < 64 ? 0 : m < 256 ? 1 : m < 1024 ? 2 : 3; }
 
-// Rows per tile of the dense passes: params.tile_rows of the instance's class (0 = TILE_RMAX).
+// Rows per tile of the dense passes: params.tile_rows of the instance's class (0 = TILE_RDEF).
 int tile_rows_for(const pins_params& p, int m) {
     const int r = p.tile_rows[size_class(m)];
-    return r > 0 ? r : TILE_RMAX;
+    return r > 0 ? r : TILE_RDEF;
 }
 
 long nnz_capacity(int m, int n, double budget) {
@@ -231,7 +231,7 @@ void check_params(const pins_params& p) {
     if (p.hvp < 0 || p.hvp > 2) fail(PINS_EINVAL, "hvp must be 0 (sparsified), 1 (matrix-free) or 2 (switch)");
     if (p.hvp_switch < 0) fail(PINS_EINVAL, "hvp_switch must be >= 0");
     for (int c = 0; c < 4; ++c)
-        if (p.tile_rows[c] < 0 || p.tile_rows[c] > TILE_RMAX) fail(PINS_EINVAL, "tile_rows must be in [0, 16]");
+        if (p.tile_rows[c] < 0 || p.tile_rows[c] > TILE_RMAX) fail(PINS_EINVAL, "tile_rows must be in [0, 64]");
 }
 
 void check_problem_shape(const pins_problem& P) {
@@ -1622,7 +1622,7 @@ int pins_tune_batch_device(pins_ctx* ctx, const pins_problem* probs, int count, 
         for (int q = 0; q < count; ++q) present[size_class(probs[q].m)] = true;
         for (int c = 0; c < 4; ++c) {
             if (!present[c]) continue;
-            for (int rows : {4, 8}) {
+            for (int rows : {8, 32, 64}) {
                 cur = top;
                 cur.tile_rows[c] = rows;
                 trial(cur);

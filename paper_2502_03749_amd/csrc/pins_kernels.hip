@@ -1207,27 +1207,7 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     sCs[threadIdx.x] = cstart;
     sCn[threadIdx.x] = cnq;
     sCi[threadIdx.x] = cinfo;
-    double xr[TILE_RMAX];
-    unsigned keepm = 0;
     const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
-#pragma unroll
-    for (int r = 0; r < TILE_RMAX; ++r) xr[r] = src.at(i0 + min(r, rows - 1), jc);  // loads issued together
-#pragma unroll
-    for (int r = 0; r < TILE_RMAX; ++r) {
-        const double cr = xr[r];
-        xr[r] = 0.0;
-        bool keep = false;
-        if (r < rows && valid) {
-            xr[r] = expo(sF[r], Gj, kap, cr, ie);
-            keep = lev_q(xr[r], lrho, sLa[r], lbj) >= lev;
-        }
-        if (r < rows) {
-            const unsigned long long bal = __ballot(keep);
-            if (lane == 0) wc[r][w] = (int)__popcll(bal);
-        }
-        keepm |= keep ? (1u << r) : 0u;
-    }
-    __syncthreads();
     const unsigned long long below = (1ull << lane) - 1ull;
     // Writes, KCH rows at a time: each wave first lists its kept entries of
     // those rows in LDS (row by row, in lane order within a row), then writes
@@ -1239,46 +1219,73 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     constexpr int KCH = 4;
     __shared__ double kX[4][KCH * 64];
     __shared__ int kRL[4][KCH * 64], kE[4][KCH * 64], kCe[4][KCH * 64];
+    // the tile's rows in passes of RS (the exponents of a pass in registers)
+    constexpr int RS = 16;
 #pragma unroll
-    for (int c0 = 0; c0 < TILE_RMAX; c0 += KCH) {
-        int cnt = 0;  // listed entries of the wave (uniform over it)
+    for (int h0 = 0; h0 < TILE_RMAX; h0 += RS) {
+        if (h0 >= rows) break;  // uniform over the block
+        const int hr = min(RS, rows - h0);
+        double xr[RS];
+        unsigned keepm = 0;
 #pragma unroll
-        for (int u = 0; u < KCH; ++u) {
-            const int r = c0 + u;
-            const bool keep = (keepm >> r) & 1u;
-            const unsigned long long bal = __ballot(keep);
-            if (keep) {
-                int woff = 0;
-                for (int q = 0; q < w; ++q) woff += wc[r][q];
-                const int rank = (int)__popcll(bal & below);
-                const int pos = cnt + rank;
-                kX[w][pos] = xr[r];
-                kRL[w][pos] = (lane << 8) | r;
-                kE[w][pos] = sE0[r] + woff + rank;
-                kCe[w][pos] = ce;
-                ++ce;
+        for (int r = 0; r < RS; ++r) xr[r] = src.at(i0 + h0 + min(r, hr - 1), jc);  // loads issued together
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+            const double cr = xr[r];
+            xr[r] = 0.0;
+            bool keep = false;
+            if (r < hr && valid) {
+                xr[r] = expo(sF[h0 + r], Gj, kap, cr, ie);
+                keep = lev_q(xr[r], lrho, sLa[h0 + r], lbj) >= lev;
             }
-            cnt += (int)__popcll(bal);
+            if (r < hr) {
+                const unsigned long long bal = __ballot(keep);
+                if (lane == 0) wc[h0 + r][w] = (int)__popcll(bal);
+            }
+            keepm |= keep ? (1u << r) : 0u;
         }
         __syncthreads();
-        for (int it = lane; it < cnt; it += 64) {
-            const int rl = kRL[w][it];
-            const int r = rl & 0xff, t = w * 64 + (rl >> 8);  // row in the tile, thread of the column
-            const VT v = (VT)texp(kX[w][it], sT);
-            const int e = kE[w][it], nq = sNq[r];
-            if (e < 4 * nq) {
-                const int slot = slot_of(sJd[0], sStart[r], nq, sInfo[r], e);
-                put(I.col, slot, cb * TILE_C + t, m);
-                static_cast<VT*>(I.val)[slot] = v;
+#pragma unroll
+        for (int c0 = 0; c0 < RS; c0 += KCH) {
+            int cnt = 0;  // listed entries of the wave (uniform over it)
+#pragma unroll
+            for (int u = 0; u < KCH; ++u) {
+                const int r = c0 + u, rt = h0 + r;
+                const bool keep = (keepm >> r) & 1u;
+                const unsigned long long bal = __ballot(keep);
+                if (keep) {
+                    int woff = 0;
+                    for (int q = 0; q < w; ++q) woff += wc[rt][q];
+                    const int rank = (int)__popcll(bal & below);
+                    const int pos = cnt + rank;
+                    kX[w][pos] = xr[r];
+                    kRL[w][pos] = (lane << 8) | rt;
+                    kE[w][pos] = sE0[rt] + woff + rank;
+                    kCe[w][pos] = ce;
+                    ++ce;
+                }
+                cnt += (int)__popcll(bal);
             }
-            const int cev = kCe[w][it], cq = sCn[t];
-            if (cev < 4 * cq) {
-                const int slot = slot_of(sJd[1], sCs[t], cq, sCi[t], cev);
-                put(I.rowT, slot, i0 + r, 0);
-                static_cast<VT*>(I.valT)[slot] = v;
+            __syncthreads();
+            for (int it = lane; it < cnt; it += 64) {
+                const int rl = kRL[w][it];
+                const int r = rl & 0xff, t = w * 64 + (rl >> 8);  // row in the tile, thread of the column
+                const VT v = (VT)texp(kX[w][it], sT);
+                const int e = kE[w][it], nq = sNq[r];
+                if (e < 4 * nq) {
+                    const int slot = slot_of(sJd[0], sStart[r], nq, sInfo[r], e);
+                    put(I.col, slot, cb * TILE_C + t, m);
+                    static_cast<VT*>(I.val)[slot] = v;
+                }
+                const int cev = kCe[w][it], cq = sCn[t];
+                if (cev < 4 * cq) {
+                    const int slot = slot_of(sJd[1], sCs[t], cq, sCi[t], cev);
+                    put(I.rowT, slot, i0 + r, 0);
+                    static_cast<VT*>(I.valT)[slot] = v;
+                }
             }
+            __syncthreads();  // the lists are rewritten for the next rows
         }
-        __syncthreads();  // the lists are rewritten for the next rows
     }
     // pads (index 0, value 0) up to a whole number of quads: rows of S in the
     // last column block, columns of S^T in the last row block
@@ -2235,8 +2242,8 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
     __shared__ double sF[TILE_RMAX], sA[TILE_RMAX][NT], sA1[TILE_RMAX][NT];
     __shared__ double sT[64];
     texp_table(sT);
-    if ((int)threadIdx.x < rows * NT) {
-        const int r = threadIdx.x / NT, t = threadIdx.x - r * NT;
+    for (int k = threadIdx.x; k < rows * NT; k += 256) {
+        const int r = k / NT, t = k - r * NT;
         const double A = expm1(al[t] * (I.d[i0 + r] * kp.inv_eta));
         sA[r][t] = A;
         sA1[r][t] = 1.0 + A;
@@ -2615,7 +2622,8 @@ __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts
     const int m = I.m, n = I.n;
     count_work(ctrl, b, W_FINAL, m, n, tl);
     const int i0 = rb * I.R, rows = min(I.R, m - i0);
-    __shared__ double red[TILE_RMAX][TILE_C + 1];
+    // the tile's rows 16 at a time through red (row sums: 16 lanes per row)
+    __shared__ double red[16][TILE_C + 1];
     __shared__ double sh[4];
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
@@ -2626,30 +2634,34 @@ __global__ __launch_bounds__(256) void k_final(const DevInst* __restrict__ insts
     __syncthreads();
     const double bj = valid ? I.beta[j] : 0.0;
     double colacc = 0.0, cst = 0.0, ent = 0.0;
-    for (int r = 0; r < rows; ++r) {
-        const int i = i0 + r;
-        double xv = 0.0;
-        if (valid) {
-            const double c = base.at(i, j);
-            const double lx = (sA[r] + bj - c) * ieps;
-            xv = exp(lx);
-            cst += c * xv;
-            if (xv > 0.0) ent -= xv * lx;
-            if (write_x && I.X) I.X[(long)i * n + j] = xv;
+    for (int h0 = 0; h0 < rows; h0 += 16) {  // uniform over the block
+        const int hr = min(16, rows - h0);
+        for (int r = 0; r < hr; ++r) {
+            const int i = i0 + h0 + r;
+            double xv = 0.0;
+            if (valid) {
+                const double c = base.at(i, j);
+                const double lx = (sA[h0 + r] + bj - c) * ieps;
+                xv = exp(lx);
+                cst += c * xv;
+                if (xv > 0.0) ent -= xv * lx;
+                if (write_x && I.X) I.X[(long)i * n + j] = xv;
+            }
+            colacc += xv;
+            red[r][threadIdx.x] = xv;
         }
-        colacc += xv;
-        red[r][threadIdx.x] = xv;
+        __syncthreads();
+        {
+            const int r = threadIdx.x >> 4, s = threadIdx.x & 15;
+            double v = 0.0;
+            if (r < hr)
+                for (int k = 0; k < 16; ++k) v += red[r][s * 16 + k];
+            v = group_sum<16>(v);
+            if (r < hr && s == 0) I.part2[(long)cb * m + i0 + h0 + r] = v;
+        }
+        __syncthreads();  // red is rewritten by the next rows
     }
     if (valid) I.part[(long)rb * n + j] = colacc;
-    __syncthreads();
-    {
-        const int r = threadIdx.x >> 4, s = threadIdx.x & 15;
-        double v = 0.0;
-        if (r < rows)
-            for (int k = 0; k < 16; ++k) v += red[r][s * 16 + k];
-        v = group_sum<16>(v);
-        if (r < rows && s == 0) I.part2[(long)cb * m + i0 + r] = v;
-    }
     cst = block_sum<256>(cst, sh);
     ent = block_sum<256>(ent, sh);
     if (threadIdx.x == 0) {

@@ -43,7 +43,7 @@ def _host(outs):
 
 
 def test_tuner_picks_a_schedule_and_tiles_and_keeps_results(ctx):
-    """The tuner tries lanes 1..4, graph replay and 4 / 8 rows per tile for each
+    """The tuner tries lanes 1..4, graph replay and 8 / 32 / 64 rows per tile for each
     size class present; the lane count and the graphs leave every result bitwise
     unchanged, and a solve with the chosen parameters reproduces the tuner's
     last outputs exactly (results depend on the tile rows only through each
@@ -59,9 +59,9 @@ def test_tuner_picks_a_schedule_and_tiles_and_keeps_results(ctx):
     best, trials = ctx.tune_batch_device(probs, prm, outs, max_lanes=4, reps=1, stream=st.cuda_stream)
     st.synchronize()
     assert 1 <= best.streams <= 4 and best.graphs in (0, 1)
-    # the batch's m span three size classes: 4 lane counts, graphs, 2 tile choices per class
+    # the batch's m span three size classes: 4 lane counts, graphs, 3 tile choices per class
     classes = {0 if p["m"] < 64 else 1 if p["m"] < 256 else 2 for p in probs}
-    assert len(trials) == 4 + 1 + 2 * len(classes)
+    assert len(trials) == 4 + 1 + 3 * len(classes)
     assert all(t["ms"] > 0 for t in trials)
     chosen = [t for t in trials if t["streams"] == best.streams and t["graphs"] == best.graphs and
               t["tile_rows"] == list(best.tile_rows)]
@@ -110,10 +110,12 @@ def test_many_lanes_equal_one_lane(ctx, lanes):
         assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
 
 
-@pytest.mark.parametrize("rows", [1, 3, 8])
+@pytest.mark.parametrize("rows", [1, 3, 8, 32, 40, 64])
 def test_tile_rows_parity(ctx, rows):
-    """Dense passes with 1, 3 and 8 rows per tile (every size class): parity
-    with the oracle at the FP64 bar."""
+    """Dense passes with 1 to 64 rows per tile (every size class; 150 rows, so
+    the last row block is ragged, and 40 rows leave a partial 16-row pass in
+    the Sparsify fill and the output kernel): parity with the oracle at the
+    FP64 bar."""
     import oracle
     from test_gpu_parity import check_parity, gpu_solve
 
@@ -143,7 +145,7 @@ def test_tuner_rejects_bad_arguments(ctx):
             ctx.tune_batch_device(probs[:2], prm, outs[:2], **kw)
         assert e.value.code == P._binding.PINS_EINVAL
     with pytest.raises(P.PinsError) as e:
-        ctx.solve_batch_device(probs[:2], P.params(eta=0.03, max_outer=2, tile_rows=[17, 0, 0, 0]), outs[:2])
+        ctx.solve_batch_device(probs[:2], P.params(eta=0.03, max_outer=2, tile_rows=[65, 0, 0, 0]), outs[:2])
     assert e.value.code == P._binding.PINS_EINVAL
 
 

@@ -61,7 +61,7 @@ int main() {
     pins_params best;
     EXPECT(pins_tune_batch_device(nullptr, &pr, 1, &p, 4, 1, &r, nullptr, &best, nullptr, 0, nullptr) == PINS_EINVAL);
     EXPECT(pins_solve_device_noalloc(nullptr, &pr, &p, &r, nullptr) == PINS_EINVAL);
-    p.tile_rows[1] = 17; EXPECT(pins_workspace_bytes(&pr, 1, &p, &x) == PINS_EINVAL); pins_params_default(&p);
+    p.tile_rows[1] = 65; EXPECT(pins_workspace_bytes(&pr, 1, &p, &x) == PINS_EINVAL); pins_params_default(&p);
     pins_server* s = nullptr;
     rc = pins_server_create(0, 2, 8, 0, &p, &s);
     EXPECT(rc == PINS_EDEVICE || rc == PINS_OK);
