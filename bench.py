@@ -15,7 +15,8 @@ by the full Hessian (matrix-free) in the first 15 outer iterations, while the
 plans are diffuse, and by the sparsified Hessian (CSR/CSC) after
 (--hvp-switch).  The number of concurrent lanes and the rows per tile of the dense
 passes are picked on the batch by the library's autotuner before the warm-up
-(--lanes fixes the lanes, and --tile-rows the rows per tile, 16 by default, instead).
+(--lanes fixes the lanes, and --tile-rows the rows per tile, the library's defaults
+unless given, instead).
 
 The JSON line also carries:
   autotune     -- every configuration the tuner tried (lanes, graph replay,
@@ -112,7 +113,7 @@ def parse():
                          "0 = the library's autotuner (pins_tune_batch_device) picks it on this batch, untimed")
     ap.add_argument("--tile-rows", type=int, default=0,
                     help="with --lanes: rows per tile of the dense passes for every size class (params.tile_rows; "
-                         "0 = the library default, 16)")
+                         "0 = the library's defaults: 16, 32, 32, 64 rows for m < 64, < 256, < 1024, larger)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the materialised-cost Sinkhorn sweep measurement (16384 x 16384 FP64 cost)")
     ap.add_argument("--sweep-only", action="store_true", help="only run the sweep measurements (materialised and streamed cost)")
@@ -266,7 +267,7 @@ def main():
         autotune = dict(lanes=lanes, graphs=graphs, tile_rows=tiles, reps=2,
                         trials=[dict(t, ms=round(t["ms"], 1)) for t in trials],
                         searched="lanes 1..4 and graph replay (launch schedule; results unchanged), then 8 / 32 / 64 "
-                                 "rows per tile per size class present (0 = 16)")
+                                 "rows per tile per size class present (0 = the library's default: 16, 32, 32, 64 by class)")
     base = dict(eta=args.eta, max_outer=args.K, precision=prec, streams=lanes, tile_rows=tiles, **hess)
     share_ms, _, _ = aggregate([step(P.params(profile=1, **base))])
     dom = max(share_ms, key=share_ms.get)

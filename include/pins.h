@@ -122,7 +122,7 @@ typedef struct {
                              those of the kernel-by-kernel launches */
     int32_t tile_rows[4]; /* rows per tile of the dense passes (the tiles are 256 columns wide) for
                              instances with m in [1, 64), [64, 256), [256, 1024), [1024, ...);
-                             0 = 16, else 1..64.  The order in which column partials are summed
+                             0 = 16, 32, 32, 64 for the four classes, else 1..64.  The order in which column partials are summed
                              follows it, so results depend on it (last bits), but only through each
                              instance's own m: an instance gets the same result alone and in any
                              batch solved with the same parameters */
@@ -297,7 +297,7 @@ int pins_solve_batch_device(pins_ctx* ctx, const pins_problem* probs, int count,
  * rows per tile of the dense passes (params.tile_rows), which changes the
  * summation order but keeps each result a function of its own instance.  The
  * search is greedy: lane counts 1 .. max_lanes (at most PINS_MAX_LANES and `count`)
- * with graphs off and 16-row tiles; then graphs on at the best count; then,
+ * with graphs off and the default tiles; then graphs on at the best count; then,
  * for each size class of m present in the batch, 8, 32 and 64 rows per tile.  Each
  * configuration is solved once untimed (workspace set-up) and then `reps`
  * times, timed with the host clock (each solve returns when it has finished),

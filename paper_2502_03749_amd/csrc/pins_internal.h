@@ -23,7 +23,6 @@ constexpr int LEV_NONE = 1 << 20;  // Sparsify level meaning "keep no entry" (no
 constexpr int LS_T = 8;      // trial step sizes per line-search pass (after the first)
 constexpr int TILE_C = 256;  // columns per tile (one per thread)
 constexpr int TILE_RMAX = 64;  // maximum rows per tile
-constexpr int TILE_RDEF = 16;  // rows per tile unless params.tile_rows says otherwise
 constexpr int NBIN = 6;        // CG row bins: <= 1, 2, 4, 8, 16 and more quads
 constexpr int JDS_PQ = 16;     // one-block CG, jagged-diagonal storage: quads per row piece (8, 32 measured slower)
 constexpr int WCG_NT = 256;        // wide CG: threads per block of a half-product (256/512/1024 measured)
