@@ -694,15 +694,19 @@ def c5_protocol(P, W, np, K=10, workers=3, max_batch=32):
         res["rates"]["%.1f" % f] = dict(r, rate_per_s=f * capacity)
         if f == 0.7:
             outs07 = outs
-    fx = os.path.join(ROOT, "tests", "golden", "c5_oracle.npz")
-    if os.path.exists(fx) and outs07 is not None:
+    acc = []
+    # sampled requests with stored FP64 oracle outputs: 32x32 and 64x64, then the first two 128x128
+    for name in ("c5_oracle.npz", "c5_oracle_128.npz"):
+        fx = os.path.join(ROOT, "tests", "golden", name)
+        if not os.path.exists(fx) or outs07 is None:
+            continue
         f = np.load(fx)
-        acc = []
         for q, c in zip(f["index"], f["cost"]):
             o = outs07[int(q)]
             acc.append(dict(request=int(q), side=stream[int(q)]["s"], rel_cost_diff=abs(o["cost"] - c) / c,
                             max_potential_diff=float(max(np.abs(o["alpha"] - f["alpha_%d" % q]).max(),
                                                          np.abs(o["beta"] - f["beta_%d" % q]).max()))))
+    if acc:
         res["accuracy_vs_oracle"] = acc
     return res
 

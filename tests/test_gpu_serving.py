@@ -189,3 +189,44 @@ def test_served_requests_match_stored_oracle_outputs():
         assert abs(o["cost"] - c) <= 1e-6 * c, (q, o["cost"], c)
         assert np.abs(o["alpha"] - f["alpha_%d" % q]).max() <= 1e-6, q
         assert np.abs(o["beta"] - f["beta_%d" % q]).max() <= 1e-6, q
+
+
+def test_largest_served_requests_match_stored_oracle_outputs():
+    """The request mix's largest size against the oracle: the first two 128x128
+    requests of the served stream (m = n = 16384; one Gaussian-mixture, one
+    white-noise pair; eta = 1e-3, K = 10), whose FP64 oracle outputs are stored
+    in tests/golden/c5_oracle_128.npz (make_c5_large_fixtures.py, about an hour
+    of oracle time each).  Served in mixed precision among the first 32x32 and
+    64x64 requests of the stream: relative cost difference and potentials within
+    1e-6.  Each alone through the host entry point in FP64: cost within 1e-9
+    relative, potentials within 1e-8, marginal residual <= 1e-10."""
+    import os
+
+    print("case 128x128 requests vs stored oracle", flush=True)
+    f = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle_128.npz"))
+    stream = W.serve_requests(int(f["stream"]), 1.0)
+    eta, K = float(f["eta"]), int(f["K"])
+    idx = [int(q) for q in f["index"]]
+    small = [q for q in range(len(stream)) if stream[q]["s"] < 128][:6]
+    srv = P.Server(P.params(eta=eta, max_outer=K, precision=P.MIXED), workers=2, max_batch=8)
+    tickets = {q: srv.submit(P.COST_GRID, stream[q]["a"], stream[q]["b"], grid_s=stream[q]["s"]) for q in small + idx}
+    out = {q: srv.wait(t) for q, t in tickets.items()}
+    srv.close()
+    for q, c in zip(idx, f["cost"]):
+        o = out[q]
+        assert o["rc"] == 0 and o["resid"] <= 1e-10, (q, o["rc"], o["resid"])
+        assert abs(o["cost"] - c) <= 1e-6 * c, (q, o["cost"], c)
+        assert np.abs(o["alpha"] - f["alpha_%d" % q]).max() <= 1e-6, q
+        assert np.abs(o["beta"] - f["beta_%d" % q]).max() <= 1e-6, q
+    ctx = P.Context(0)
+    try:
+        for q, c in zip(idx, f["cost"]):
+            print("case 128x128 request %d FP64 alone" % q, flush=True)
+            g = ctx.solve(P.COST_GRID, stream[q]["a"], stream[q]["b"], P.params(eta=eta, max_outer=K, precision=P.FP64),
+                          grid_s=128)
+            assert g["rc"] == 0 and g["resid"] <= 1e-10, (q, g["rc"], g["resid"])
+            assert abs(g["cost"] - c) <= 1e-9 * c, (q, g["cost"], c)
+            assert np.abs(g["alpha"] - f["alpha_%d" % q]).max() <= 1e-8, q
+            assert np.abs(g["beta"] - f["beta_%d" % q]).max() <= 1e-8, q
+    finally:
+        ctx.close()
