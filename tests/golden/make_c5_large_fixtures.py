@@ -2,7 +2,7 @@
 requests of the served workload's stream (instance 0 of the request generator;
 one Gaussian-mixture and one white-noise pair; eta = 1e-3, K = 10), the
 largest size of the request mix (m = n = 16384).  Each solve takes the plain
-oracle about an hour and a half on one core and about 5 GB of memory (the
+oracle about an hour on one core and about 5 GB of memory (the
 dense 16384 x 16384 cost), so the two run in two processes.  Stored per
 request: its index in the stream, side, cost and potentials.  Only oracle/ and
 the seeded input generators are called.
