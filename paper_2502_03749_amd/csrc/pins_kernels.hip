@@ -57,6 +57,14 @@ struct DenseSrc {
     __device__ __forceinline__ DenseSrc(const DevInst& I, bool base = false)
         : C(base ? I.cbase : I.csrc), ld(I.ldc), s(base ? I.bscale : I.cscale) {}
     __device__ __forceinline__ double at(int i, int j) const { return ldg(C + ((long)i * ld + j)) * s; }
+    // walking a row: the row's base, a column cursor advanced by a fixed step
+    typedef const double* Row;
+    typedef int Col;
+    __device__ __forceinline__ Row row(int i) const { return C + (long)i * ld; }
+    __device__ __forceinline__ Col col(int j) const { return j; }
+    template <int STEP>
+    __device__ __forceinline__ void next(Col& c) const { c += STEP; }
+    __device__ __forceinline__ double at(Row r, Col c) const { return ldg(r + c) * s; }
 };
 
 // Squared distance between pixels p = row*s + col of an s x s grid, times the
@@ -76,8 +84,42 @@ struct GridSrc {
         const int dr = ri - rj, dc = ci - cj;
         return (double)(dr * dr + dc * dc) * sc;
     }
+    // walking a row: pixel coordinates, the column's advanced by a fixed step
+    // of pixels without a division (the same exact integers as at(i, j))
+    struct Px {
+        int r, c;
+    };
+    typedef Px Row;
+    typedef Px Col;
+    __device__ __forceinline__ Px row(int i) const {
+        const int r = quot(i);
+        return Px{r, i - r * s};
+    }
+    __device__ __forceinline__ Px col(int j) const { return row(j); }
+    template <int STEP>
+    __device__ __forceinline__ void next(Px& q) const {
+        q.c += STEP % s;
+        q.r += STEP / s;
+        if (q.c >= s) {
+            q.c -= s;
+            q.r += 1;
+        }
+    }
+    __device__ __forceinline__ double at(Px a, Px b) const {
+        const int dr = a.r - b.r, dc = a.c - b.c;
+        return (double)(dr * dr + dc * dc) * sc;
+    }
 };
 
+
+// A tile's rows as cursors of its cost source, in LDS: entry r is row
+// i0 + min(r, rows - 1), so that every entry of the table is a row in range.
+// (For the grid cost this takes each row's pixel coordinates out of the
+// per-entry work.)
+template <class Src>
+__device__ __forceinline__ void tile_row_table(const Src& src, typename Src::Row* sRow, int i0, int rows) {
+    if ((int)threadIdx.x < TILE_RMAX) sRow[threadIdx.x] = src.row(i0 + min((int)threadIdx.x, rows - 1));
+}
 
 // log of the recovery map, eq. (eppa_x): (F_i + G_j - kappa*C_ij)/eta
 __device__ __forceinline__ double expo(double Fi, double Gj, double kap, double c, double ie) {
@@ -413,6 +455,8 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
         // their U loads of C and G are issued together), then the last partial
         // one; the same operations in the same order either way
         const int nfull = n - n % (64 * U);
+        const typename Src::Row ro = src.row(i);
+        typename Src::Col co = src.col(lane);  // column j0 + u * 64 + lane below
         int j0 = 0;
         for (; j0 < nfull; j0 += 64 * U) {
             double z[U];
@@ -420,7 +464,8 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * 64 + lane;
-                z[u] = (ldg(G + j) - kap * src.at(i, j)) * ie;
+                z[u] = (ldg(G + j) - kap * src.at(ro, co)) * ie;
+                src.template next<64>(co);
                 cm = fmax(cm, z[u]);
             }
             if (cm > mx) {
@@ -436,7 +481,8 @@ __global__ __launch_bounds__(256) void k_row_lse(const DevInst* __restrict__ ins
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * 64 + lane;
-                z[u] = (j < n) ? (ldg(G + j) - kap * src.at(i, j)) * ie : -INFINITY;
+                z[u] = (j < n) ? (ldg(G + j) - kap * src.at(ro, co)) * ie : -INFINITY;
+                src.template next<64>(co);
                 cm = fmax(cm, z[u]);
             }
             if (cm > mx) {
@@ -484,11 +530,14 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
     __shared__ double sT[64];
     texp_table(sT);
     if ((int)threadIdx.x < TILE_RMAX + 4) sF[threadIdx.x] = (i0 + (int)threadIdx.x < i1) ? I.F[i0 + threadIdx.x] : 0.0;
+    const Src src(I);
+    __shared__ typename Src::Row sRow[TILE_RMAX];
+    tile_row_table(src, sRow, i0, i1 - i0);
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     if (j >= n) return;
     const double kap = ctrl[b].kappa, ie = kp.inv_eta;
-    const Src src(I);
+    const typename Src::Col cj = src.col(j);
     double mx = -INFINITY;
     T sm = T(0);
     constexpr int U = 4;
@@ -501,7 +550,7 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
         double cm = -INFINITY;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            z[u] = (sF[i + u - i0] - kap * src.at(i + u, j)) * ie;
+            z[u] = (sF[i + u - i0] - kap * src.at(sRow[i + u - i0], cj)) * ie;
             cm = fmax(cm, z[u]);
         }
         if (cm > mx) {
@@ -517,7 +566,7 @@ __global__ __launch_bounds__(256) void k_col_lse(const DevInst* __restrict__ ins
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int ii = i + u;
-            z[u] = (ii < i1) ? (sF[ii - i0] - kap * src.at(ii, j)) * ie : -INFINITY;
+            z[u] = (ii < i1) ? (sF[ii - i0] - kap * src.at(sRow[min(ii - i0, TILE_RMAX - 1)], cj)) * ie : -INFINITY;
             cm = fmax(cm, z[u]);
         }
         if (cm > mx) {
@@ -663,21 +712,24 @@ __global__ __launch_bounds__(256) void k_grad(const DevInst* __restrict__ insts,
         sF[threadIdx.x] = I.F[i0 + threadIdx.x];
         sLa[threadIdx.x] = I.loga[i0 + threadIdx.x];
     }
+    const Src src(I);
+    __shared__ typename Src::Row sRow[TILE_RMAX];
+    tile_row_table(src, sRow, i0, rows);
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
     const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
     const int nlev = kp.nlev;
-    const Src src(I);
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
     double colacc = 0.0;
     const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
+    const typename Src::Col cj = src.col(jc);
     for (int r0 = 0; r0 < rows; r0 += 4) {
         // the group's 4 cost values first (clamped in range, so that their
         // loads are issued together), then the entries
         double cv[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) cv[u] = src.at(i0 + min(r0 + u, rows - 1), jc);
+        for (int u = 0; u < 4; ++u) cv[u] = src.at(sRow[min(r0 + u, rows - 1)], cj);
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -853,19 +905,22 @@ __global__ __launch_bounds__(256) void k_count(const DevInst* __restrict__ insts
         sF[threadIdx.x] = I.F[i0 + threadIdx.x];
         sLa[threadIdx.x] = I.loga[i0 + threadIdx.x];
     }
+    const Src src(I);
+    __shared__ typename Src::Row sRow[TILE_RMAX];
+    tile_row_table(src, sRow, i0, rows);
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double lev = (double)ctrl[b].level, kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
-    const Src src(I);
     const double Gj = valid ? ldg(I.G + j) : 0.0, lbj = valid ? ldg(I.logb + j) : 0.0;
     int cc = 0;
     const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
+    const typename Src::Col cj = src.col(jc);
     for (int r0 = 0; r0 < rows; r0 += 4) {
         double cv[4];  // the group's cost values first (loads issued together)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) cv[u] = src.at(i0 + min(r0 + u, rows - 1), jc);
+        for (int u = 0; u < 4; ++u) cv[u] = src.at(sRow[min(r0 + u, rows - 1)], cj);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int r = r0 + u;
@@ -1176,6 +1231,8 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
         sInfo[threadIdx.x] = jds ? I.rowbin[i] : 0;
     }
     if (jds && (int)threadIdx.x < 2 * (JDS_PQ + 1)) (&sJd[0][0])[threadIdx.x] = (&ctrl[b].jdp[0][0])[threadIdx.x];
+    __shared__ typename Src::Row sRow[TILE_RMAX];
+    tile_row_table(Src(I), sRow, i0, rows);
     __syncthreads();
     // slot of entry e of a row of S (jd = sJd[0]) or of S^T (sJd[1])
     auto slot_of = [&](const int* jd, int start, int nq, int info, int e) {
@@ -1208,6 +1265,7 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
     sCn[threadIdx.x] = cnq;
     sCi[threadIdx.x] = cinfo;
     const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
+    const typename Src::Col cj = src.col(jc);
     const unsigned long long below = (1ull << lane) - 1ull;
     // Writes, KCH rows at a time: each wave first lists its kept entries of
     // those rows in LDS (row by row, in lane order within a row), then writes
@@ -1228,7 +1286,7 @@ __global__ __launch_bounds__(256) void k_fill(const DevInst* __restrict__ insts,
         double xr[RS];
         unsigned keepm = 0;
 #pragma unroll
-        for (int r = 0; r < RS; ++r) xr[r] = src.at(i0 + h0 + min(r, hr - 1), jc);  // loads issued together
+        for (int r = 0; r < RS; ++r) xr[r] = src.at(sRow[h0 + min(r, hr - 1)], cj);  // loads issued together
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
             const double cr = xr[r];
@@ -1996,16 +2054,19 @@ __global__ __launch_bounds__(256) void k_mf_tile(const DevInst* __restrict__ ins
         sF[threadIdx.x] = I.F[i0 + threadIdx.x];
         su[threadIdx.x] = u[i0 + threadIdx.x];
     }
+    const Src src(I);
+    __shared__ typename Src::Row sRow[TILE_RMAX];
+    tile_row_table(src, sRow, i0, rows);
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
     const double kap = ctrl[b].kappa, ie = kp.inv_eta;
-    const Src src(I);
+    const typename Src::Col cj = src.col(valid ? j : 0);
     const double Gj = valid ? ldg(I.G + j) : 0.0;
     if (cols) {
         double acc = 0.0;
         if (valid)
-            for (int r = 0; r < rows; ++r) acc += (double)ex<T>(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), sT) * su[r];
+            for (int r = 0; r < rows; ++r) acc += (double)ex<T>(expo(sF[r], Gj, kap, src.at(sRow[r], cj), ie), sT) * su[r];
         if (valid) I.part[(long)rb * n + j] = acc;
     } else {
         const double wj = valid ? p[m + j] : 0.0;
@@ -2014,7 +2075,7 @@ __global__ __launch_bounds__(256) void k_mf_tile(const DevInst* __restrict__ ins
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int r = r0 + t;
-                v[t] = (valid && r < rows) ? (double)ex<T>(expo(sF[r], Gj, kap, src.at(i0 + r, j), ie), sT) * wj : 0.0;
+                v[t] = (valid && r < rows) ? (double)ex<T>(expo(sF[r], Gj, kap, src.at(sRow[min(r, rows - 1)], cj), ie), sT) * wj : 0.0;
             }
             wave_rows4(v, r0, wsum);
         }
@@ -2127,22 +2188,25 @@ __global__ __launch_bounds__(256) void k_ls_first(const DevInst* __restrict__ in
         sA[threadIdx.x] = A;
         sA1[threadIdx.x] = 1.0 + A;
     }
+    const Src src(I);
+    __shared__ typename Src::Row sRow[TILE_RMAX];
+    tile_row_table(src, sRow, i0, rows);
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
     const double kap = ctrl[b].kappa, ie = kp.inv_eta, lrho = kp.log_rho;
     const int nlev = kp.nlev;
-    const Src src(I);
     double acc = 0.0, colacc = 0.0;
     const double Gj = valid ? ldg(I.G + j) : 0.0, dGj = valid ? ldg(I.d + m + j) * ie : 0.0;
     const double lbj = valid ? ldg(I.logb + j) : 0.0;
     // expm1(a_i + b_j) = A_i + B_j (1 + A_i) with A_i = expm1(a_i), B_j = expm1(b_j)
     const double Bj = expm1(dGj);
     const int jc = valid ? j : 0;  // a column in range for the loads of idle lanes
+    const typename Src::Col cj = src.col(jc);
     for (int r0 = 0; r0 < rows; r0 += 4) {
         double cv[4];  // the group's cost values first (loads issued together)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) cv[u] = src.at(i0 + min(r0 + u, rows - 1), jc);
+        for (int u = 0; u < 4; ++u) cv[u] = src.at(sRow[min(r0 + u, rows - 1)], cj);
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -2249,11 +2313,13 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
         sA1[r][t] = 1.0 + A;
     }
     if ((int)threadIdx.x < rows) sF[threadIdx.x] = I.F[i0 + threadIdx.x];
+    const Src src(I);
+    __shared__ typename Src::Row sRow[TILE_RMAX];
+    tile_row_table(src, sRow, i0, rows);
     __syncthreads();
     const int j = cb * TILE_C + threadIdx.x;
     const bool valid = j < n;
     const double kap = ctrl[b].kappa, ie = kp.inv_eta;
-    const Src src(I);
     double acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = 0.0;
@@ -2262,9 +2328,9 @@ __global__ __launch_bounds__(256) void k_ls(const DevInst* __restrict__ insts, C
         double B[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) B[t] = expm1(al[t] * bj);
+        const typename Src::Col cj = src.col(j);
         for (int r = 0; r < rows; ++r) {
-            const int i = i0 + r;
-            const double e = texp(expo(sF[r], Gj, kap, src.at(i, j), ie), sT);
+            const double e = texp(expo(sF[r], Gj, kap, src.at(sRow[r], cj), ie), sT);
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] += e * fma(B[t], sA1[r][t], sA[r][t]);
         }
