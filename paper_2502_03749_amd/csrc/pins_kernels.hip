@@ -2587,14 +2587,21 @@ __global__ __launch_bounds__(256) void k_cost_max(const DevInst* __restrict__ in
                                                   double* __restrict__ scratch) {
     const int b = blockIdx.y;
     const DevInst& I = insts[b];
-    const long mn = (long)I.m * I.n;
+    const int m = I.m, n = I.n;
+    // whole rows per block (no index division per entry); an instance with
+    // fewer rows than the grid's blocks uses m of them (the maximum does not
+    // depend on the partition)
+    const int nb = min((int)gridDim.x, m);
+    if ((int)blockIdx.x >= nb) return;
     double mx = 0.0;
     int bad = 0;
-    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < mn; q += (long)gridDim.x * 256) {
-        const int i = (int)(q / I.n), j = (int)(q - (long)i * I.n);
-        const double v = I.cbase[(long)i * I.ldc + j];
-        if (!isfinite(v)) bad = 1;
-        mx = fmax(mx, v);
+    for (int i = blockIdx.x; i < m; i += nb) {
+        const double* __restrict__ row = I.cbase + (long)i * I.ldc;
+        for (int j = threadIdx.x; j < n; j += 256) {
+            const double v = row[j];
+            if (!isfinite(v)) bad = 1;
+            mx = fmax(mx, v);
+        }
     }
     __shared__ double sm[256];
     __shared__ int sb;
@@ -2611,10 +2618,10 @@ __global__ __launch_bounds__(256) void k_cost_max(const DevInst* __restrict__ in
         scratch[(long)b * gridDim.x + blockIdx.x] = sm[0];
         if (sb) atomicOr(&ctrl[b].nonfinite, 1);
     }
-    if (!last_block(&ctrl[b].ticket, gridDim.x)) return;
+    if (!last_block(&ctrl[b].ticket, nb)) return;
     if (threadIdx.x == 0) {
         double M = 0.0;
-        for (int k = 0; k < (int)gridDim.x; ++k) M = fmax(M, scratch[(long)b * gridDim.x + k]);
+        for (int k = 0; k < nb; ++k) M = fmax(M, scratch[(long)b * gridDim.x + k]);
         ctrl[b].scale = (M > 0.0) ? 1.0 / M : 1.0;
     }
 }

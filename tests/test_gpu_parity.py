@@ -347,6 +347,22 @@ def test_full_size_batch_sampled_parity(ctx, precision, hvp_switch):
         assert np.abs(outs[q]["beta"].cpu().numpy() - be).max() <= pbar, q
 
 
+@pytest.mark.parametrize("m,n", [(150, 97), (2000, 30)])
+def test_dense_cost_scaled_by_its_maximum(ctx, m, n):
+    """cost_scale <= 0 on the device path: the library divides C by its own
+    maximum (a reduction over whole rows; 150 rows leave blocks of the grid
+    idle, 2000 rows give each block several).  Parity with the oracle run on
+    C / max C."""
+    print("case dense 1/max scale %dx%d" % (m, n), flush=True)
+    C, a, b = _rand(m, n, 4000 + m)
+    C = 3.7 * C
+    Cs = C / C.max()
+    g = gpu_solve(ctx, dict(kind=P.COST_DENSE, C=C, a=a, b=b, cost_scale=0.0), P.params(eta=0.05, max_outer=4))
+    g["_C"] = Cs
+    o = oracle.pins(Cs, a, b, eta=0.05, K=4)
+    check_parity(g, o, a, b)
+
+
 @pytest.mark.parametrize("m,n,d", [(77, 50, 2), (45, 130, 8), (100, 64, 32), (33, 17, 3)])
 def test_points_cost_on_matrix_cores_parity(ctx, m, n, d):
     """Point-cloud cost built with the FP64 matrix cores (ragged 32x32 tiles,
