@@ -2865,6 +2865,28 @@ void launch_sparsify(const LaunchCtx& L, int src) {
 // thread owns beyond an instance's m + n add zeros to its sums, so the
 // instance's arithmetic does not depend on the batch's largest m + n.
 static_assert(WCG_MAX_N <= 4 * 1024, "k_pcg_lds holds at most 4096 vector entries");
+// The 1024-thread CG blocks keep their compute unit to themselves: a launch
+// reserves the rest of the unit's LDS as dynamic shared memory that the kernel
+// does not use, so that no block of another lane's kernels lands on the unit
+// and slows the iterations (measured on the 64-pair batch: 285-286 against
+// 289 ms per step).  Zero (no reservation) if the attributes cannot be read.
+template <int EPT, class IX, class VT, bool JDS>
+static size_t pcg_exclusive_lds() {
+    static const size_t pad = [] {
+        hipFuncAttributes a;
+        int dev = 0, maxs = 0;
+        if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&k_pcg_lds<1024, EPT, IX, VT, JDS>)) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&maxs, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            (size_t)maxs <= a.sharedSizeBytes) {
+            (void)hipGetLastError();
+            return (size_t)0;
+        }
+        return (size_t)maxs - a.sharedSizeBytes;
+    }();
+    return pad;
+}
+
 template <class IX, class VT, bool JDS>
 static void launch_pcg_t(const LaunchCtx& L) {
     const dim3 g(L.count);
@@ -2873,12 +2895,16 @@ static void launch_pcg_t(const LaunchCtx& L) {
     if (!L.any_big) return;
     const int ept = (L.max_mn_small + 1023) / 1024;
     const dim3 blk(1024);
-    if (ept <= 1)
-        hipLaunchKernelGGL((k_pcg_lds<1024, 1, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
-    else if (ept <= 2)
-        hipLaunchKernelGGL((k_pcg_lds<1024, 2, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
-    else
-        hipLaunchKernelGGL((k_pcg_lds<1024, 4, IX, VT, JDS>), g, blk, 0, L.stream, L.insts, L.ctrl, L.kp);
+    if (ept <= 1) {
+        const size_t pad = pcg_exclusive_lds<1, IX, VT, JDS>();
+        hipLaunchKernelGGL((k_pcg_lds<1024, 1, IX, VT, JDS>), g, blk, pad, L.stream, L.insts, L.ctrl, L.kp);
+    } else if (ept <= 2) {
+        const size_t pad = pcg_exclusive_lds<2, IX, VT, JDS>();
+        hipLaunchKernelGGL((k_pcg_lds<1024, 2, IX, VT, JDS>), g, blk, pad, L.stream, L.insts, L.ctrl, L.kp);
+    } else {
+        const size_t pad = pcg_exclusive_lds<4, IX, VT, JDS>();
+        hipLaunchKernelGGL((k_pcg_lds<1024, 4, IX, VT, JDS>), g, blk, pad, L.stream, L.insts, L.ctrl, L.kp);
+    }
 }
 
 template <class IX, class VT>
